@@ -1,0 +1,503 @@
+"""FP64 CPU oracle for graph-form ADMM with equilibration and adaptive rho.
+
+TEST INFRASTRUCTURE ONLY.  This module is a plain, slow, obviously-correct
+NumPy implementation of what the GPU solver computes.  Only the test suite,
+the package's smoke check and the benchmark's CPU-baseline leg may import it;
+the GPU library never calls, links or loads anything here, and nothing here
+imports the GPU package.
+
+Problem (Section 1): minimize f(y) + g(x) subject to y = A x, with f and g
+separable and each term written in the parametric form of Section 5,
+    f_i(y) = c h(a y - b) + d y + (e/2) y^2,   c >= 0, e >= 0.
+A function is passed as an object with attributes ``h`` (base-function name),
+``size``, and a method ``field(name)`` returning the float64 array of a, b, c,
+d or e (``Fn`` of the workload module has that shape; any duck type does).
+
+Everything here runs in float64.  Readings of passages the paper leaves open
+(the fixed Sinkhorn-Knopp iteration count, which machine epsilon, 0-based k in
+the adaptive-rho test, strict inequalities, scaled-space residuals, rho0 = 1)
+are stated where used.
+
+Pins (tests/test_oracle_*.py) check every function here against closed forms,
+brute force, library solvers and invariants that do not reuse this code.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Base functions h, their proximal operators and conjugates
+# ---------------------------------------------------------------------------
+
+H_NAMES = ("zero", "identity", "abs", "square", "huber", "hinge", "logistic",
+           "ind_ge0", "ind_le0", "ind_eq0", "ind_box01")
+
+
+def h_eval(h: str, u, tol: float = 0.0):
+    """Value of the base function h at u (elementwise, +inf outside its domain).
+
+    ``tol`` widens the domains of the indicator functions by that amount, for
+    points that rounding has pushed just outside.
+    """
+    u = np.asarray(u, dtype=np.float64)
+    if h == "zero":
+        return np.zeros_like(u)
+    if h == "identity":
+        return u.copy()
+    if h == "abs":
+        return np.abs(u)
+    if h == "square":
+        return 0.5 * u * u
+    if h == "huber":
+        au = np.abs(u)
+        return np.where(au <= 1.0, 0.5 * u * u, au - 0.5)
+    if h == "hinge":
+        return np.maximum(u, 0.0)
+    if h == "logistic":
+        return np.logaddexp(0.0, u)
+    if h == "ind_ge0":
+        return np.where(u >= -tol, 0.0, np.inf)
+    if h == "ind_le0":
+        return np.where(u <= tol, 0.0, np.inf)
+    if h == "ind_eq0":
+        return np.where(np.abs(u) <= tol, 0.0, np.inf)
+    if h == "ind_box01":
+        return np.where((u >= -tol) & (u <= 1.0 + tol), 0.0, np.inf)
+    raise ValueError(h)
+
+
+def h_conj(h: str, s, tol: float = 0.0):
+    """Convex conjugate h*(s) = sup_u (s u - h(u)), elementwise (textbook forms).
+
+    ``tol`` widens the closed domain of conjugates that are indicators (or
+    finite only on an interval) by that amount, for points that rounding has
+    pushed just outside; the value is taken at the nearest domain point.
+    """
+    s = np.asarray(s, dtype=np.float64)
+    inf = np.inf
+
+    def box(lo, hi):
+        inside = (s >= lo - tol) & (s <= hi + tol)
+        return inside, np.clip(s, lo, hi)
+
+    if h == "zero":
+        ok, _ = box(0.0, 0.0)
+        return np.where(ok, 0.0, inf)
+    if h == "identity":
+        ok, _ = box(1.0, 1.0)
+        return np.where(ok, 0.0, inf)
+    if h == "abs":
+        ok, _ = box(-1.0, 1.0)
+        return np.where(ok, 0.0, inf)
+    if h == "square":
+        return 0.5 * s * s
+    if h == "huber":
+        ok, t = box(-1.0, 1.0)
+        return np.where(ok, 0.5 * t * t, inf)
+    if h == "hinge":
+        ok, _ = box(0.0, 1.0)
+        return np.where(ok, 0.0, inf)
+    if h == "logistic":
+        ok, t = box(0.0, 1.0)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ent = np.where(t > 0.0, t * np.log(np.where(t > 0.0, t, 1.0)), 0.0) \
+                + np.where(t < 1.0, (1.0 - t) * np.log(np.where(t < 1.0, 1.0 - t, 1.0)), 0.0)
+        return np.where(ok, ent, inf)
+    if h == "ind_ge0":
+        ok, _ = box(-inf, 0.0)
+        return np.where(ok, 0.0, inf)
+    if h == "ind_le0":
+        ok, _ = box(0.0, inf)
+        return np.where(ok, 0.0, inf)
+    if h == "ind_eq0":
+        return np.zeros_like(s)
+    if h == "ind_box01":
+        return np.maximum(s, 0.0)
+    raise ValueError(h)
+
+
+def _logistic_prox(z, r):
+    """Root of sigma(u) + r (u - z) = 0 by bisection on [z - 1/r, z].
+
+    The left side is increasing in u, negative at z - 1/r (sigma < 1) and
+    positive at z (sigma > 0), so the bracket always holds the root.
+    """
+    lo = z - 1.0 / r
+    hi = z.copy()
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        sig = 0.5 * (1.0 + np.tanh(0.5 * mid))
+        pos = sig + r * (mid - z) > 0.0
+        hi = np.where(pos, mid, hi)
+        lo = np.where(pos, lo, mid)
+        if np.all(hi - lo <= 4 * np.finfo(float).eps * np.maximum(1.0, np.abs(hi))):
+            break
+    return 0.5 * (lo + hi)
+
+
+def prox_h(h: str, z, r):
+    """prox_{h,r}(z) = argmin_u h(u) + (r/2)(u - z)^2 (elementwise; r > 0).
+
+    Closed forms are the textbook ones (soft threshold for |u|, shrinkage
+    for u^2/2, clipping for indicators); logistic has none and is solved by
+    bisection.
+    """
+    z = np.asarray(z, dtype=np.float64)
+    r = np.broadcast_to(np.asarray(r, dtype=np.float64), z.shape)
+    if h == "zero":
+        return z.copy()
+    if h == "identity":
+        return z - 1.0 / r
+    if h == "abs":
+        return np.sign(z) * np.maximum(np.abs(z) - 1.0 / r, 0.0)
+    if h == "square":
+        return r * z / (1.0 + r)
+    if h == "huber":
+        return np.where(np.abs(z) <= 1.0 + 1.0 / r, r * z / (1.0 + r), z - np.sign(z) / r)
+    if h == "hinge":
+        return np.where(z > 1.0 / r, z - 1.0 / r, np.where(z < 0.0, z, 0.0))
+    if h == "logistic":
+        return _logistic_prox(z, r)
+    if h == "ind_ge0":
+        return np.maximum(z, 0.0)
+    if h == "ind_le0":
+        return np.minimum(z, 0.0)
+    if h == "ind_eq0":
+        return np.zeros_like(z)
+    if h == "ind_box01":
+        return np.clip(z, 0.0, 1.0)
+    raise ValueError(h)
+
+
+# ---------------------------------------------------------------------------
+# Parametric separable functions (Section 5)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Param:
+    """Plain parameter arrays of a separable parametric function."""
+
+    h: str
+    a: np.ndarray
+    b: np.ndarray
+    c: np.ndarray
+    d: np.ndarray
+    e: np.ndarray
+
+    @property
+    def size(self) -> int:
+        return self.a.shape[0]
+
+    def field(self, name: str) -> np.ndarray:
+        return getattr(self, name)
+
+
+def as_param(fn) -> Param:
+    """Copy a duck-typed function description into float64 arrays."""
+    return Param(fn.h, *(np.array(fn.field(k), dtype=np.float64) for k in "abcde"))
+
+
+def fn_eval(fn, y, tol: float = 0.0) -> float:
+    """Sum of c h(a y - b) + d y + (e/2) y^2 (Section 5), without constant
+    offsets.  ``tol`` is passed to h_eval (indicator domains)."""
+    p = as_param(fn)
+    y = np.asarray(y, dtype=np.float64)
+    hv = h_eval(p.h, p.a * y - p.b, tol)
+    with np.errstate(invalid="ignore"):
+        term = np.where(p.c == 0.0, 0.0, p.c * hv)
+    return float(np.sum(term + p.d * y + 0.5 * p.e * y * y))
+
+
+def fn_conj(fn, nu, tol: float = 0.0) -> float:
+    """Conjugate f*(nu) of a parametric function with e = 0:
+    f*(nu) = c h*((nu - d)/(a c)) + b (nu - d)/a  (for c > 0, a != 0),
+    and the indicator of {nu = d} when c = 0.  ``tol`` is passed to h_conj."""
+    p = as_param(fn)
+    if np.any(p.e != 0.0):
+        raise ValueError("conjugate implemented for e = 0 only")
+    nu = np.asarray(nu, dtype=np.float64)
+    s = nu - p.d
+    out = np.empty_like(nu)
+    zero_c = p.c == 0.0
+    out[zero_c] = np.where(np.abs(s[zero_c]) <= tol, 0.0, np.inf)
+    k = ~zero_c
+    out[k] = p.c[k] * h_conj(p.h, s[k] / (p.a[k] * p.c[k]), tol) + p.b[k] * s[k] / p.a[k]
+    return float(np.sum(out))
+
+
+def prox_param(fn, v, rho):
+    """prox of a parametric separable function with penalty rho (Section 5):
+
+        argmin_y c h(a y - b) + d y + (e/2) y^2 + (rho/2)(y - v)^2
+          = (1/a) (prox_{h, (e+rho)/(c a^2)}(a (rho v - d)/(e + rho) - b) + b).
+
+    ``rho`` may be a scalar or a per-element array.  With c = 0 the h term is
+    absent and the result is (rho v - d)/(e + rho).
+    """
+    p = as_param(fn)
+    v = np.asarray(v, dtype=np.float64)
+    rho = np.broadcast_to(np.asarray(rho, dtype=np.float64), v.shape)
+    vq = (rho * v - p.d) / (p.e + rho)
+    out = vq.copy()
+    k = p.c > 0.0
+    if np.any(k):
+        a, b, c = p.a[k], p.b[k], p.c[k]
+        r = (p.e[k] + rho[k]) / (c * a * a)
+        out[k] = (prox_h(p.h, a * vq[k] - b, r) + b) / a
+    return out
+
+
+def scale_fn(fn, s) -> Param:
+    """The function y -> f(s * y) elementwise, as parametric data:
+    c h(a s y - b) + d s y + (e/2) s^2 y^2 (used for the pre-conditioned
+    functions of Section 4.1: f^(y^) = f(D^-1 y^), g^(x^) = g(E x^))."""
+    p = as_param(fn)
+    s = np.asarray(s, dtype=np.float64)
+    return Param(p.h, p.a * s, p.b.copy(), p.c.copy(), p.d * s, p.e * s * s)
+
+
+# ---------------------------------------------------------------------------
+# Equilibration (Section 4.2, Algorithm 2) and Frobenius normalisation (4.1.2)
+# ---------------------------------------------------------------------------
+
+def sinkhorn_knopp(A, gamma: float, iters: int, p: int = 2):
+    """Regularised Sinkhorn-Knopp (Algorithm 2) run for a fixed number of sweeps.
+
+    Starting from e = 1, each sweep sets
+        d = n / (|A|^p e + gamma/m),   e = m / (|A^T|^p d + gamma/n),
+    and the scalings are D = diag(d)^(1/p), E = diag(e)^(1/p).
+    Reading: the algorithm's stopping tolerance is unspecified, so a fixed
+    sweep count is used (partial equilibration suffices, Section 4.1.2).
+    Returns (d, e) (the p-th powers of the diagonals).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    Ap = np.abs(A) ** p
+    e = np.ones(n)
+    d = np.ones(m)
+    for _ in range(iters):
+        d = n / (Ap @ e + gamma / m)
+        e = m / (Ap.T @ d + gamma / n)
+    return d, e
+
+
+def equilibrate(A, eps_cmp: float, iters: int = 10):
+    """Section 5's pre-conditioner: Algorithm 2 with p = 2 and
+    gamma = (m + n) sqrt(eps_cmp), then D and E both rescaled by the same
+    factor so that ||D A E||_F / sqrt(min(m, n)) = 1 (Section 4.1.2).
+
+    Reading of "rescaled evenly": D <- D / sqrt(s), E <- E / sqrt(s) with
+    s = ||D A E||_F / sqrt(min(m, n)).  Returns the diagonals (D, E).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    gamma = (m + n) * math.sqrt(eps_cmp)
+    d, e = sinkhorn_knopp(A, gamma, iters, p=2)
+    D = np.sqrt(d)
+    E = np.sqrt(e)
+    s = np.linalg.norm(D[:, None] * A * E[None, :]) / math.sqrt(min(m, n))
+    return D / math.sqrt(s), E / math.sqrt(s)
+
+
+# ---------------------------------------------------------------------------
+# Graph projection (Section 3.1 projection formula; Section 3.5 reduced update)
+# ---------------------------------------------------------------------------
+
+class Projector:
+    """Projection onto {(x, y) : y = A x} through the reduced update of
+    Section 3.5 with a cached Cholesky factor:
+
+      m >= n:  x = (I + A^T A)^{-1} (c + A^T d),  y = A x
+      m <  n:  y = d + (I + A A^T)^{-1} (A c - d),  x = c + A^T (d - y)
+
+    Reading: the paper prints the last update as c - A^T (d - y).  The
+    optimality conditions of the projection (x - c + A^T(y - d) = 0 with
+    y = A x, i.e. the K system of Section 3.1) give c + A^T (d - y); the
+    printed sign does not return a point of the graph's orthogonal projection.
+    """
+
+    def __init__(self, A):
+        self.A = np.asarray(A, dtype=np.float64)
+        m, n = self.A.shape
+        self.tall = m >= n
+        K = (self.A.T @ self.A if self.tall else self.A @ self.A.T) + np.eye(min(m, n))
+        self.L = np.linalg.cholesky(K)
+
+    def _solve(self, r):
+        z = _tri_solve(self.L, r, lower=True)
+        return _tri_solve(self.L.T, z, lower=False)
+
+    def __call__(self, c, d):
+        A = self.A
+        if self.tall:
+            x = self._solve(c + A.T @ d)
+            y = A @ x
+        else:
+            y = d + self._solve(A @ c - d)
+            x = c + A.T @ (d - y)
+        return x, y
+
+
+def _tri_solve(T, r, lower: bool):
+    """Forward or back substitution with a triangular matrix (library primitive)."""
+    from scipy.linalg import solve_triangular
+    return solve_triangular(T, r, lower=lower)
+
+
+# ---------------------------------------------------------------------------
+# Adaptive penalty (Section 4.3, Algorithm 3)
+# ---------------------------------------------------------------------------
+
+def adaptive_rho(rho: float, l: int, u: int, k: int, r_pri: float, eps_pri: float,
+                 r_dual: float, eps_dual: float, delta: float, tau: float):
+    """One decision of Algorithm 3 after iteration k (0-based).
+
+    If the dual residual has converged and tau k > l: rho *= delta, u = k.
+    Else if the primal residual has converged and tau k > u: rho /= delta, l = k.
+    Returns (rho, l, u).
+    """
+    if r_dual < eps_dual and tau * k > l:
+        return rho * delta, l, k
+    if r_pri < eps_pri and tau * k > u:
+        return rho / delta, k, u
+    return rho, l, u
+
+
+# ---------------------------------------------------------------------------
+# The solver (Algorithm 1 with the Section 3.2 extensions, Sections 3.3-5)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Params:
+    eps_abs: float = 1e-4
+    eps_rel: float = 1e-3
+    max_iter: int = 10000
+    rho0: float = 1.0        # reading: unspecified, 1 after the Frobenius normalisation
+    alpha: float = 1.7       # Section 5
+    delta: float = 1.05      # Section 5
+    tau: float = 0.8         # Section 5
+    adaptive_rho: bool = True
+    equil_iters: int = 10    # reading: fixed sweep count for Algorithm 2
+    equilibrate: bool = True
+    eps_cmp: float = float(np.finfo(np.float32).eps)  # machine epsilon of the iteration type
+
+
+@dataclasses.dataclass
+class Result:
+    x: np.ndarray
+    y: np.ndarray
+    mu: np.ndarray
+    nu: np.ndarray
+    iters: int
+    converged: bool
+    rho: float
+    r_pri: float
+    r_dual: float
+    eps_pri: float
+    eps_dual: float
+    optval: float           # f(y) + g(x) at the returned (x, y), without constants
+    D: np.ndarray
+    E: np.ndarray
+    history: Optional[dict] = None
+
+
+def solve(A, f, g, params: Params = Params(), record: bool = False,
+          D: Optional[np.ndarray] = None, E: Optional[np.ndarray] = None) -> Result:
+    """Graph projection splitting (Algorithm 1) on the pre-conditioned problem.
+
+    Per iteration k = 0, 1, ... (all in the scaled variables of Section 4.1,
+    A^ = D A E, f^(y) = f(D^-1 y), g^(x) = g(E x)):
+      1. x_h = prox_g^(x - x~), y_h = prox_f^(y - y~)                (Alg. 1)
+      2. mu_h = -rho (x_h - x + x~), nu_h = -rho (y_h - y + y~)      (Sec. 3.3)
+      3. x_r = alpha x_h + (1 - alpha) x, likewise y_r                (Sec. 3.2)
+      4. (x, y) = Pi(x_r + x~, y_r + y~)                            (Alg. 1, Sec. 3.5)
+      5. x~ += x_r - x, y~ += y_r - y                               (Alg. 1 + Sec. 3.2)
+      6. r_pri = ||A^ x_h - y_h||, r_dual = ||A^T nu_h + mu_h||,
+         eps_pri = eps_abs + eps_rel ||y_h||, eps_dual = eps_abs + eps_rel ||mu_h||
+                                                                    (Sec. 3.4)
+      7. stop when r_pri < eps_pri and r_dual < eps_dual               (Alg. 3)
+      8. Algorithm 3 may change rho; (x~, y~) are then rescaled by
+         rho_old / rho_new (Sec. 3.2, varying penalty).
+    Readings: residuals and tolerances are taken in the scaled variables the
+    iteration runs in; the inequalities are strict as in Algorithm 3; k is the
+    0-based iteration index of Algorithm 1.
+
+    The returned tuple is the last half-step tuple (Section 5) mapped back to
+    the original variables: x = E x_h, y = D^-1 y_h, mu = E^-1 mu_h, nu = D nu_h.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if D is None or E is None:
+        if params.equilibrate:
+            D, E = equilibrate(A, params.eps_cmp, params.equil_iters)
+        else:
+            D, E = np.ones(m), np.ones(n)
+    Ah = D[:, None] * A * E[None, :]
+    fh = scale_fn(f, 1.0 / D)
+    gh = scale_fn(g, E)
+    proj = Projector(Ah)
+
+    x = np.zeros(n)
+    y = np.zeros(m)
+    xt = np.zeros(n)
+    yt = np.zeros(m)
+    rho = params.rho0
+    l = u = 0
+    hist = {"r_pri": [], "r_dual": [], "eps_pri": [], "eps_dual": [], "rho": [],
+            "inv_dual": [], "inv_primal": []} if record else None
+    converged = False
+    k = 0
+    for k in range(params.max_iter):
+        xh = prox_param(gh, x - xt, rho)
+        yh = prox_param(fh, y - yt, rho)
+        mu = -rho * (xh - x + xt)
+        nu = -rho * (yh - y + yt)
+        xr = params.alpha * xh + (1.0 - params.alpha) * x
+        yr = params.alpha * yh + (1.0 - params.alpha) * y
+        x_new, y_new = proj(xr + xt, yr + yt)
+        xt = xt + xr - x_new
+        yt = yt + yr - y_new
+        x, y = x_new, y_new
+        r_pri = float(np.linalg.norm(Ah @ xh - yh))
+        r_dual = float(np.linalg.norm(Ah.T @ nu + mu))
+        eps_pri = params.eps_abs + params.eps_rel * float(np.linalg.norm(yh))
+        eps_dual = params.eps_abs + params.eps_rel * float(np.linalg.norm(mu))
+        if record:
+            hist["r_pri"].append(r_pri)
+            hist["r_dual"].append(r_dual)
+            hist["eps_pri"].append(eps_pri)
+            hist["eps_dual"].append(eps_dual)
+            hist["rho"].append(rho)
+            hist["inv_dual"].append(float(np.linalg.norm(xt + Ah.T @ yt)))
+            hist["inv_primal"].append(float(np.linalg.norm(y - Ah @ x)))
+        if r_pri < eps_pri and r_dual < eps_dual:
+            converged = True
+            break
+        if params.adaptive_rho:
+            rho_new, l, u = adaptive_rho(rho, l, u, k, r_pri, eps_pri, r_dual, eps_dual,
+                                         params.delta, params.tau)
+            if rho_new != rho:
+                xt = xt * (rho / rho_new)
+                yt = yt * (rho / rho_new)
+                rho = rho_new
+    x_out = E * xh
+    y_out = yh / D
+    mu_out = mu / E
+    nu_out = D * nu
+    # indicator domains checked to 1e-9 (prox outputs meet them up to rounding)
+    optval = fn_eval(f, y_out, 1e-9) + fn_eval(g, x_out, 1e-9)
+    return Result(x_out, y_out, mu_out, nu_out, k + 1, converged, rho, r_pri, r_dual,
+                  eps_pri, eps_dual, optval, D, E, hist)
+
+
+# ---------------------------------------------------------------------------
+# Certificates (Section 2)
+# ---------------------------------------------------------------------------
+
+def duality_gap(f, g, x, y, mu, nu, tol: float = 0.0) -> float:
+    """eta = f(y) + f*(nu) + g(x) + g*(mu) (Section 2.1); >= 0 for feasible tuples."""
+    return fn_eval(f, y, tol) + fn_conj(f, nu, tol) + fn_eval(g, x, tol) + fn_conj(g, mu, tol)
