@@ -1,0 +1,243 @@
+/*
+ * pogs.h - C ABI of a graph-form ADMM solver for MI355X (gfx950).
+ *
+ * Solves   minimize f(y) + g(x)   subject to   y = A x          (Section 1)
+ * with A dense (m x n) and f, g separable, each term in the parametric form
+ * of Section 5:
+ *     f_i(y) = c_i h_i(a_i y - b_i) + d_i y + (e_i / 2) y^2,   c_i >= 0, e_i >= 0.
+ *
+ * The method is graph projection splitting (Section 3.1, Algorithm 1) with
+ * over-relaxation (Section 3.2), residual stopping on the half-step tuple
+ * (Sections 3.3-3.4), diagonal pre-conditioning by regularised
+ * Sinkhorn-Knopp equilibration plus Frobenius normalisation (Sections 4.1,
+ * 4.2, Algorithm 2, Section 5) and the adaptive penalty of Section 4.3
+ * (Algorithm 3).  The graph projection uses the reduced update of Section 3.5
+ * with a factorisation of I + A^T A (m >= n) or I + A A^T (m < n) computed
+ * once per matrix and cached in the context.
+ *
+ * Conventions for every entry point:
+ *   - return value: 0 (POGS_OK) or a negative POGS_E* code; nothing is
+ *     launched when an argument check fails.  Failing to converge is not an
+ *     error: it is reported in pogs_result.status.
+ *   - pointers tagged POGS_HOST are host memory, POGS_DEVICE are device
+ *     memory on the current HIP device.  Input buffers are only read and may
+ *     be freed by the caller as soon as the call returns (the library copies
+ *     what it keeps).  Output buffers are caller-allocated.
+ *   - "stream" arguments are a hipStream_t passed as void*; NULL means the
+ *     library's own stream.  Calls are synchronous with respect to the host:
+ *     they return after their device work has finished.
+ *   - A context (pogs_ctx) is not thread-safe; use one per thread.  The batch
+ *     engine (pogs_batch) is thread-safe.
+ */
+#ifndef POGS_H
+#define POGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define POGS_OK            0
+#define POGS_EINVAL       -1   /* bad argument (size, pointer, non-finite data,
+                                  c < 0 or e < 0, a == 0 with c > 0, unknown h) */
+#define POGS_ENOMEM       -2   /* device or host allocation failed */
+#define POGS_EDEVICE      -3   /* a HIP runtime call failed */
+#define POGS_EAGAIN       -4   /* batch: request can never fit the memory budget,
+                                  or the queue is full */
+#define POGS_ENOTFOUND    -5   /* batch: unknown ticket */
+#define POGS_EUNSUPPORTED -6   /* valid request this build does not implement */
+
+/* ---- solve status (pogs_result.status) ---------------------------------- */
+#define POGS_CONVERGED  0      /* r_pri < eps_pri and r_dual < eps_dual */
+#define POGS_MAXITER    1      /* iteration cap reached */
+#define POGS_NUMERICAL  2      /* a residual became non-finite */
+#define POGS_CANCELLED  3      /* batch: cancelled before completion */
+
+typedef enum { POGS_F32 = 0, POGS_F64 = 1 } pogs_dtype;
+typedef enum { POGS_ROW_MAJOR = 0, POGS_COL_MAJOR = 1 } pogs_order;
+typedef enum { POGS_HOST = 0, POGS_DEVICE = 1 } pogs_mem;
+
+/* Base functions h of the parametric form (Section 5). */
+typedef enum {
+  POGS_H_ZERO = 0,      /* 0 */
+  POGS_H_IDENTITY = 1,  /* u */
+  POGS_H_ABS = 2,       /* |u| */
+  POGS_H_SQUARE = 3,    /* u^2 / 2 */
+  POGS_H_HUBER = 4,     /* u^2/2 for |u| <= 1, |u| - 1/2 otherwise */
+  POGS_H_HINGE = 5,     /* max(0, u) */
+  POGS_H_LOGISTIC = 6,  /* log(1 + e^u) */
+  POGS_H_IND_GE0 = 7,   /* indicator of u >= 0 */
+  POGS_H_IND_LE0 = 8,   /* indicator of u <= 0 */
+  POGS_H_IND_EQ0 = 9,   /* indicator of u == 0 */
+  POGS_H_IND_BOX01 = 10 /* indicator of 0 <= u <= 1 */
+} pogs_h;
+
+/* A separable function of length len, in host memory.  Each of h, a..e is
+ * either an array of len entries (stride 1) or a single entry used for every
+ * element (stride 0).  A NULL parameter pointer means its default
+ * (a = 1, b = 0, c = 1, d = 0, e = 0); h may not be NULL. */
+typedef struct {
+  int64_t len;
+  int64_t stride;                 /* 1: per element, 0: broadcast entry 0 */
+  const uint8_t *h;               /* pogs_h codes */
+  const double *a, *b, *c, *d, *e;
+} pogs_fn;
+
+/* Solver parameters; pogs_params_default fills the values of Section 5. */
+typedef struct {
+  double eps_abs;        /* absolute tolerance (Section 3.4), default 1e-4 */
+  double eps_rel;        /* relative tolerance, default 1e-3 */
+  int32_t max_iter;      /* iteration cap, default 10000 */
+  double rho0;           /* initial penalty, default 1 */
+  double alpha;          /* over-relaxation (Section 3.2), default 1.7 */
+  double delta;          /* adaptive-rho factor (Algorithm 3), default 1.05 */
+  double tau;            /* adaptive-rho spacing (Algorithm 3), default 0.8 */
+  int32_t adaptive_rho;  /* 1 = Algorithm 3 on (default), 0 = fixed rho */
+  int32_t equil_iters;   /* Sinkhorn-Knopp sweeps (Algorithm 2), default 10;
+                            0 = no pre-conditioning (D = E = I) */
+  double eps_cmp;        /* machine epsilon in gamma = (m+n) sqrt(eps_cmp);
+                            <= 0 selects the epsilon of the matrix dtype */
+  int32_t chunk_iters;   /* iterations per device launch sequence between
+                            host checks of the stop flag, default 20 */
+  int32_t verbose;       /* 0 silent, 1 per-chunk log on stderr */
+} pogs_params;
+
+/* Result of a solve: the half-step tuple (x, y, mu, nu) of the last iteration,
+ * in the original (unscaled) variables (Section 5).  x, y, mu, nu are
+ * caller-allocated buffers of n, m, n, m elements of the context's dtype in
+ * memory space `mem`; any of them may be NULL to skip that copy. */
+typedef struct {
+  void *x, *y, *mu, *nu;
+  pogs_mem mem;
+  double optval;     /* f(y) + g(x) at the returned tuple (parametric terms only;
+                        indicator terms are zero there by construction) */
+  double r_pri, r_dual, eps_pri, eps_dual;  /* last residuals (scaled space) */
+  double rho;        /* final penalty */
+  int32_t iters;     /* iterations run */
+  int32_t status;    /* POGS_CONVERGED / POGS_MAXITER / POGS_NUMERICAL / POGS_CANCELLED */
+  double ms_setup;   /* setup time of the context this solve used (ms) */
+  double ms_solve;   /* wall time of this solve (ms) */
+} pogs_result;
+
+typedef struct pogs_ctx pogs_ctx;
+
+/* Fill *p with the defaults above.  POGS_EINVAL if p is NULL. */
+int pogs_params_default(pogs_params *p);
+
+/* Create a context for matrix A (m x n, element type dt, storage order ord,
+ * leading dimension lda >= n for row-major or >= m for column-major, in
+ * memory `mem`).  Copies A to the device, converts it to row-major storage of
+ * dt with a 64-element-aligned leading dimension, runs Algorithm 2
+ * (params->equil_iters sweeps, p = 2, gamma = (m + n) sqrt(eps_cmp)), the
+ * Frobenius normalisation of Section 4.1.2, scales A in place to D A E, forms
+ * the Gram matrix (Section 3.5) and factors I + G by Cholesky in float64, and
+ * keeps everything for later solves.  params may be NULL (defaults).
+ * Errors: EINVAL (m, n <= 0, NULL pointers, lda too small, non-finite A),
+ * ENOMEM, EDEVICE.  On error *out is set to NULL. */
+int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, pogs_dtype dt,
+              pogs_order ord, int64_t lda, pogs_mem mem, const pogs_params *params,
+              void *stream);
+
+/* Solve with functions f (len m) and g (len n) on the context's matrix.
+ * params may be NULL (the context's).  x0 and nu0 are reserved for warm
+ * starts and must be NULL (POGS_EUNSUPPORTED otherwise).
+ * Errors: EINVAL (NULL ctx/f/g/out, wrong lengths, c < 0, e < 0, a == 0 with
+ * c > 0, unknown h, non-finite parameters), EUNSUPPORTED, EDEVICE. */
+int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, const pogs_params *params,
+               const void *x0, const void *nu0, pogs_result *out);
+
+/* Solve R problems that share the context's matrix (a lambda path): problem r
+ * uses f[r], g[r] and writes out[r].  The R right-hand sides are stacked so the
+ * two passes over A are matrix-matrix products (one read of A per pass for
+ * all R problems); each problem keeps its own rho, stopping test and status,
+ * exactly as if solved alone up to rounding.  1 <= R <= 256.
+ * Errors as pogs_solve. */
+int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const pogs_fn *g,
+                    const pogs_params *params, pogs_result *out);
+
+/* Release a context and all its device memory.  NULL is a no-op. */
+int pogs_free(pogs_ctx *ctx);
+
+/* ---- primitives on a context (each one step of the method) -------------- */
+
+/* Copy the diagonal pre-conditioners D (m entries) and E (n entries) of
+ * Section 4.1 (after the Frobenius normalisation) into D, E (float64, memory
+ * `mem`).  Either pointer may be NULL. */
+int pogs_get_scaling(pogs_ctx *ctx, double *D, double *E, pogs_mem mem);
+
+/* Orthogonal projection of (c, d) onto the graph {(x, y) : y = A^ x} of the
+ * scaled matrix A^ = D A E (Section 3.1 projection, computed by the reduced
+ * update of Section 3.5 with the cached factor).  c, x have n entries, d, y
+ * have m entries, all of the context's dtype in memory `mem`. */
+int pogs_project(pogs_ctx *ctx, const void *c, const void *d, void *x, void *y, pogs_mem mem);
+
+/* Evaluate prox_{f,rho}(v) elementwise (Section 5 formula) on the device for a
+ * function of length fn->len: out_i = argmin_y f_i(y) + (rho/2)(y - v_i)^2.
+ * v and out have fn->len entries of dtype dt in memory `mem`. */
+int pogs_prox(const pogs_fn *fn, pogs_dtype dt, double rho, const void *v, void *out,
+              pogs_mem mem, void *stream);
+
+/* ---- batched and served solves ------------------------------------------ */
+
+/* One problem for the batch engine (all pointers host memory, copied on
+ * submit). */
+typedef struct {
+  int64_t m, n;
+  const void *A;
+  pogs_dtype dt;        /* POGS_F32 only in this build */
+  pogs_order ord;
+  int64_t lda;
+  pogs_fn f, g;
+  pogs_params params;
+} pogs_problem;
+
+typedef struct {
+  size_t hbm_budget_bytes;  /* device memory the engine may hold for resident
+                               problems; 0 = 80% of free memory at creation */
+  int32_t max_slots;        /* problems resident at once, 0 = 1024 */
+  int32_t chunk_iters;      /* iterations per scheduling round, 0 = 50 */
+  void *stream;             /* NULL = engine's own stream */
+} pogs_batch_cfg;
+
+typedef struct pogs_batch pogs_batch;
+
+/* Create a batch engine with its own scheduler thread.  cfg may be NULL. */
+int pogs_batch_create(pogs_batch **out, const pogs_batch_cfg *cfg);
+
+/* Queue a problem; copies its data.  Returns a ticket in *ticket.
+ * POGS_EAGAIN if the problem alone exceeds the memory budget; EINVAL as
+ * pogs_init/pogs_solve. */
+int pogs_batch_submit(pogs_batch *b, const pogs_problem *p, uint64_t *ticket);
+
+/* Non-blocking: 0 and *out filled (x, y, mu, nu copied into out's buffers,
+ * which must be host memory here) when the ticket has finished, 1 while it is
+ * pending, POGS_ENOTFOUND for an unknown or already-collected ticket.  A
+ * finished ticket is released by the poll that returns 0. */
+int pogs_batch_poll(pogs_batch *b, uint64_t ticket, pogs_result *out);
+
+/* Block until every submitted ticket has finished. */
+int pogs_batch_wait_all(pogs_batch *b);
+
+/* Cancel a queued or running ticket; its poll then returns status
+ * POGS_CANCELLED.  POGS_ENOTFOUND for unknown tickets. */
+int pogs_batch_cancel(pogs_batch *b, uint64_t ticket);
+
+/* Stop the scheduler thread and free everything (pending tickets are dropped). */
+int pogs_batch_destroy(pogs_batch *b);
+
+/* Solve nprob independent problems (host data) in one call: setup for all of
+ * them runs as batched kernels over a flattened work list, then one persistent
+ * launch runs every problem's ADMM iterations to its own stop, one workgroup
+ * per problem pulled from a device work queue (largest first).  out[i]
+ * receives problem i's result (host buffers).  Errors as pogs_init/pogs_solve. */
+int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_result *out, void *stream);
+
+const char *pogs_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POGS_H */

@@ -1,0 +1,104 @@
+// Internal structures shared by the kernels' host launchers and the C ABI.
+#pragma once
+
+#include "common.hpp"
+#include "../../include/pogs.h"
+
+namespace pogs {
+
+// Device control block of one solve: penalty, counters, stop flag and the
+// last residuals.  Written only by the final workgroup of each iteration.
+struct Ctrl {
+  double rho;       // current penalty rho^k
+  double rescale;   // factor applied to (x~, y~) by the next prox step
+  double r_pri, r_dual, eps_pri, eps_dual;
+  double eps_abs, eps_rel, alpha, delta, tau;
+  int k;            // iterations completed
+  int l, u;         // Algorithm 3 markers
+  int done;         // 0 running, else 1 + pogs status
+  int max_iter;
+  int adaptive;
+  int pad0, pad1;
+  unsigned cnt_a, cnt_b;  // last-workgroup counters
+  unsigned pad2, pad3;
+};
+
+// Separable function as device arrays (per element).
+template <typename T> struct FnDev {
+  const uint8_t *h;
+  const T *a, *b, *c, *d, *e;
+};
+
+// Everything one iteration of the single-problem pipeline touches.
+template <typename T> struct IterArgs {
+  int m, n, ld;          // scaled matrix A^ (row-major, leading dim ld)
+  int q, ldk;            // (I + G)^{-1}, q = min(m, n), leading dim ldk
+  const T *A;
+  const T *Kinv;
+  FnDev<T> f, g;         // pre-conditioned f^ (length m), g^ (length n)
+  T *x, *y, *xt, *yt;    // projected iterate and scaled duals
+  T *xh, *yh, *mu, *nu;  // half-step tuple
+  T *cx, *dy;            // projection inputs c = x_r + x~, d = y_r + y~
+  T *rhs;                // right-hand side of the reduced system (length q)
+  double *part;          // gemv_t split partials
+  unsigned *tile_cnt;    // gemv_t tile counters
+  double *s_mu, *s_yh;   // prox-block partial sums of mu_h^2, y_h^2
+  double *s_pri, *s_dual;// partial sums of the residuals
+  int nbx, nby;          // prox blocks over x (n) and y (m)
+  int n_pri, n_dual;     // number of residual partial slots
+  Ctrl *ctrl;
+};
+
+// ---- launchers (setup.hip) ------------------------------------------------
+// Convert a matrix (f32/f64, row/col-major, leading dim lda) already on the
+// device into row-major T with leading dim ld and zero padding; counts
+// non-finite inputs into *bad.
+template <typename T>
+void launch_layout(const void *src, pogs_dtype sdt, pogs_order ord, int64_t lda, int m, int n,
+                   T *dst, int ld, unsigned *bad, hipStream_t s);
+
+// Algorithm 2 sweeps and Frobenius normalisation: fills D (m) and E (n)
+// (float64) and scales A in place to D A E.  ws: workspace (see setup.hip).
+template <typename T>
+int run_equilibrate(T *A, int m, int n, int ld, int iters, double eps_cmp, double *D, double *E,
+                    double *ws, size_t ws_bytes, unsigned *counters, hipStream_t s);
+size_t equil_workspace_bytes(int m, int n);
+
+// Gram matrix of A^ (A^T A if m >= n else A A^T) plus I, as float64 q x q
+// (leading dim ldq = Q, padded to a multiple of 64 with identity).
+template <typename T>
+int run_gram(const T *A, int m, int n, int ld, double *K, int Q, float *ws32, double *ws64,
+             size_t ws_bytes, hipStream_t s);
+size_t gram_workspace_bytes(int m, int n, int elem_size);
+
+// Cholesky of K (Q x Q float64, in place, lower) and the explicit inverse
+// written as T into Kinv (q x q, leading dim ldk).  ws: Q*Q doubles + Q*64 doubles.
+template <typename T>
+int run_factor_inverse(double *K, int q, int Q, T *Kinv, int ldk, double *ws, unsigned *bad,
+                       hipStream_t s);
+
+// ---- launchers (iter.hip) -------------------------------------------------
+template <typename T> void launch_scale_fn(const uint8_t *h, const double *a, const double *b,
+                                           const double *c, const double *d, const double *e,
+                                           const double *scale, bool divide, int len, uint8_t *oh,
+                                           T *oa, T *ob, T *oc, T *od, T *oe, hipStream_t s);
+template <typename T> void launch_iteration(const IterArgs<T> &p, int splits, int rows_per_split,
+                                            int ncolp, hipStream_t s);
+template <typename T> void launch_project(const IterArgs<T> &p, int splits, int rows_per_split,
+                                          int ncolp, const T *c, const T *d, T *x, T *y, hipStream_t s);
+template <typename T>
+void launch_unscale(const IterArgs<T> &p, const double *D, const double *E, const uint8_t *fh0,
+                    const double *fa0, const double *fb0, const double *fc0, const double *fd0,
+                    const double *fe0, const uint8_t *gh0, const double *ga0, const double *gb0,
+                    const double *gc0, const double *gd0, const double *ge0, T *xo, T *yo, T *muo,
+                    T *nuo, double *obj_slots, double *obj_out, unsigned *cnt, hipStream_t s);
+template <typename T> void launch_prox_eval(const uint8_t *h, const T *a, const T *b, const T *c,
+                                            const T *d, const T *e, double rho, const T *v, T *out,
+                                            int len, hipStream_t s);
+
+// Iteration geometry helpers.
+int gemv_t_tile(int elem_size);
+void gemv_t_geometry(int m, int ncols, int elem_size, int *splits, int *rows_per_split, int *ncolp);
+int gemv_n_blocks(int m, int ncols, int elem_size, int nrhs_rows_hint);
+
+}  // namespace pogs

@@ -1,0 +1,582 @@
+// C ABI of the graph-form ADMM library (see include/pogs.h): argument checks,
+// context and device-memory management, the setup pipeline, and the host loop
+// that replays captured iteration chunks until the device stop flag is set.
+#include <algorithm>
+#include <cfloat>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+#include "prox.hpp"
+
+using namespace pogs;
+
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device allocations owned by a context, freed together.
+struct DevArena {
+  std::vector<void *> ptrs;
+  int alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      *p = nullptr;
+      return POGS_ENOMEM;
+    }
+    ptrs.push_back(*p);
+    return POGS_OK;
+  }
+  void release(void *p) {
+    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    if (it != ptrs.end()) {
+      (void)hipFree(*it);
+      ptrs.erase(it);
+    }
+  }
+  ~DevArena() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+};
+
+bool finite(double v) { return std::isfinite(v); }
+
+// Expand a pogs_fn into per-element float64 arrays (host); validate it.
+struct HostFn {
+  std::vector<uint8_t> h;
+  std::vector<double> a, b, c, d, e;
+};
+
+int expand_fn(const pogs_fn *fn, int64_t len, HostFn *out) {
+  if (!fn || fn->len != len || !fn->h || (fn->stride != 0 && fn->stride != 1)) return POGS_EINVAL;
+  out->h.resize(len);
+  out->a.resize(len);
+  out->b.resize(len);
+  out->c.resize(len);
+  out->d.resize(len);
+  out->e.resize(len);
+  for (int64_t i = 0; i < len; ++i) {
+    const int64_t k = fn->stride ? i : 0;
+    const uint8_t h = fn->h[k];
+    const double a = fn->a ? fn->a[k] : 1.0;
+    const double b = fn->b ? fn->b[k] : 0.0;
+    const double c = fn->c ? fn->c[k] : 1.0;
+    const double d = fn->d ? fn->d[k] : 0.0;
+    const double e = fn->e ? fn->e[k] : 0.0;
+    if (h >= kNumH) return POGS_EINVAL;
+    if (!finite(a) || !finite(b) || !finite(c) || !finite(d) || !finite(e)) return POGS_EINVAL;
+    if (c < 0.0 || e < 0.0) return POGS_EINVAL;   // convexity (Section 5: c, e >= 0)
+    if (c > 0.0 && a == 0.0) return POGS_EINVAL;  // h term would be constant
+    out->h[i] = h;
+    out->a[i] = a;
+    out->b[i] = b;
+    out->c[i] = c;
+    out->d[i] = d;
+    out->e[i] = e;
+  }
+  return POGS_OK;
+}
+
+int check_params(const pogs_params &p) {
+  if (!(p.eps_abs >= 0.0) || !(p.eps_rel >= 0.0) || p.max_iter <= 0 || !(p.rho0 > 0.0) || !(p.alpha > 0.0) ||
+      !(p.alpha < 2.0) || !(p.delta >= 1.0) || !(p.tau > 0.0) || !(p.tau <= 1.0) || p.equil_iters < 0 ||
+      p.chunk_iters < 0 || !finite(p.eps_abs) || !finite(p.eps_rel) || !finite(p.rho0) || !finite(p.delta))
+    return POGS_EINVAL;
+  return POGS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct pogs_ctx {
+  int64_t m = 0, n = 0;
+  int ld = 0, q = 0, Q = 0, ldk = 0;
+  pogs_dtype dt = POGS_F32;
+  pogs_params params{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevArena arena;
+  void *A = nullptr;     // scaled matrix, T
+  void *Kinv = nullptr;  // (I + G)^{-1}, T
+  double *D = nullptr, *E = nullptr;
+  // iteration state (T): x y xt yt xh yh mu nu cx dy rhs, outputs xo yo muo nuo
+  void *vec = nullptr;
+  // scaled functions (T) and original functions (float64)
+  uint8_t *fh = nullptr, *gh = nullptr, *fh0 = nullptr, *gh0 = nullptr;
+  void *fs = nullptr, *gs = nullptr;     // 5 arrays each, T
+  double *f0 = nullptr, *g0 = nullptr;   // 5 arrays each, float64
+  double *part = nullptr, *slots = nullptr;
+  unsigned *counters = nullptr;
+  Ctrl *ctrl = nullptr;
+  Ctrl *ctrl_host = nullptr;   // pinned
+  double *obj_host = nullptr;  // pinned
+  double *obj_dev = nullptr;
+  int splits = 0, rps = 0, ncolp = 0;
+  int nbx = 0, nby = 0, n_pri = 0, n_dual = 0;
+  double ms_setup = 0.0;
+  hipGraphExec_t graph = nullptr;
+  int graph_chunk = 0;
+
+  size_t esz() const { return dt == POGS_F32 ? 4 : 8; }
+  template <typename T> T *vecp(int idx) const {
+    // vectors 0..3: x, y, xt, yt; 4..7: xh, yh, mu, nu; 8: cx, 9: dy, 10: rhs; 11..14: outputs
+    static const int kind[15] = {0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 2, 0, 1, 0, 1};  // 0: n, 1: m, 2: q
+    size_t off = 0;
+    const size_t L[3] = {(size_t)round_up(n, 64), (size_t)round_up(m, 64), (size_t)round_up(q, 64)};
+    for (int i = 0; i < idx; ++i) off += L[kind[i]];
+    return reinterpret_cast<T *>(vec) + off;
+  }
+  size_t vec_elems() const {  // the 15 vectors of vecp: 7 of length n, 7 of m, 1 of q
+    return 7 * (size_t)round_up(n, 64) + 7 * (size_t)round_up(m, 64) + (size_t)round_up(q, 64);
+  }
+  template <typename T> IterArgs<T> iter_args() const {
+    IterArgs<T> p{};
+    p.m = (int)m;
+    p.n = (int)n;
+    p.ld = ld;
+    p.q = q;
+    p.ldk = ldk;
+    p.A = (const T *)A;
+    p.Kinv = (const T *)Kinv;
+    const T *fsp = (const T *)fs;
+    const T *gsp = (const T *)gs;
+    p.f = FnDev<T>{fh, fsp, fsp + m, fsp + 2 * m, fsp + 3 * m, fsp + 4 * m};
+    p.g = FnDev<T>{gh, gsp, gsp + n, gsp + 2 * n, gsp + 3 * n, gsp + 4 * n};
+    p.x = vecp<T>(0);
+    p.y = vecp<T>(1);
+    p.xt = vecp<T>(2);
+    p.yt = vecp<T>(3);
+    p.xh = vecp<T>(4);
+    p.yh = vecp<T>(5);
+    p.mu = vecp<T>(6);
+    p.nu = vecp<T>(7);
+    p.cx = vecp<T>(8);
+    p.dy = vecp<T>(9);
+    p.rhs = vecp<T>(10);
+    p.part = part;
+    p.tile_cnt = counters;
+    p.nbx = nbx;
+    p.nby = nby;
+    p.s_mu = slots;
+    p.s_yh = slots + nbx;
+    p.s_pri = slots + nbx + nby;
+    p.s_dual = slots + nbx + nby + n_pri;
+    p.n_pri = n_pri;
+    p.n_dual = n_dual;
+    p.ctrl = ctrl;
+    return p;
+  }
+  ~pogs_ctx() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (ctrl_host) (void)hipHostFree(ctrl_host);
+    if (obj_host) (void)hipHostFree(obj_host);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+extern "C" {
+
+const char *pogs_strerror(int code) {
+  switch (code) {
+    case POGS_OK: return "ok";
+    case POGS_EINVAL: return "invalid argument";
+    case POGS_ENOMEM: return "out of memory";
+    case POGS_EDEVICE: return "HIP runtime error";
+    case POGS_EAGAIN: return "request does not fit the memory budget or the queue is full";
+    case POGS_ENOTFOUND: return "unknown ticket";
+    case POGS_EUNSUPPORTED: return "not supported by this build";
+    default: return "unknown error";
+  }
+}
+
+int pogs_params_default(pogs_params *p) {
+  if (!p) return POGS_EINVAL;
+  p->eps_abs = 1e-4;
+  p->eps_rel = 1e-3;
+  p->max_iter = 10000;
+  p->rho0 = 1.0;
+  p->alpha = 1.7;
+  p->delta = 1.05;
+  p->tau = 0.8;
+  p->adaptive_rho = 1;
+  p->equil_iters = 10;
+  p->eps_cmp = 0.0;
+  p->chunk_iters = 20;
+  p->verbose = 0;
+  return POGS_OK;
+}
+
+int pogs_free(pogs_ctx *ctx) {
+  if (!ctx) return POGS_OK;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return POGS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, pogs_order ord, int64_t lda,
+                                    pogs_mem mem) {
+  const int m = (int)c->m, n = (int)c->n;
+  hipStream_t s = c->stream;
+  DevArena tmp;
+  int rc;
+  // -- layout -------------------------------------------------------------
+  if ((rc = c->arena.alloc(&c->A, (size_t)m * c->ld * sizeof(T)))) return rc;
+  const size_t selem = sdt == POGS_F32 ? 4 : 8;
+  const size_t src_elems = ord == POGS_ROW_MAJOR ? (size_t)(m - 1) * lda + n : (size_t)(n - 1) * lda + m;
+  const void *src = A;
+  if (mem == POGS_HOST) {
+    void *stage;
+    if ((rc = tmp.alloc(&stage, src_elems * selem))) return rc;
+    POGS_HIP_TRY(hipMemcpyAsync(stage, A, src_elems * selem, hipMemcpyHostToDevice, s));
+    src = stage;
+  }
+  unsigned *flags;  // [0] non-finite A, [1] factorisation failures
+  if ((rc = tmp.alloc((void **)&flags, 64))) return rc;
+  POGS_HIP_TRY(hipMemsetAsync(flags, 0, 64, s));
+  launch_layout<T>(src, sdt, ord, lda, m, n, (T *)c->A, c->ld, flags, s);
+  // -- equilibration ------------------------------------------------------
+  if ((rc = c->arena.alloc((void **)&c->D, (size_t)m * 8))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->E, (size_t)n * 8))) return rc;
+  unsigned *cnt;
+  const size_t ncnt = (size_t)cdiv(n, 128) + 16;
+  if ((rc = tmp.alloc((void **)&cnt, ncnt * sizeof(unsigned)))) return rc;
+  POGS_HIP_TRY(hipMemsetAsync(cnt, 0, ncnt * sizeof(unsigned), s));
+  {
+    const size_t wsb = equil_workspace_bytes(m, n);
+    double *ws;
+    if ((rc = tmp.alloc((void **)&ws, wsb))) return rc;
+    double eps = c->params.eps_cmp > 0.0 ? c->params.eps_cmp
+                                         : (sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON);
+    if ((rc = run_equilibrate<T>((T *)c->A, m, n, c->ld, c->params.equil_iters, eps, c->D, c->E, ws, wsb, cnt, s)))
+      return rc;
+  }
+  // -- Gram and factorisation ---------------------------------------------
+  const int Q = c->Q;
+  double *K;
+  if ((rc = tmp.alloc((void **)&K, (size_t)Q * Q * 8))) return rc;
+  {
+    const size_t gb = gram_workspace_bytes(m, n, sizeof(T));
+    void *gws;
+    if ((rc = tmp.alloc(&gws, gb))) return rc;
+    if ((rc = run_gram<T>((const T *)c->A, m, n, c->ld, K, Q, (float *)gws, (double *)gws, gb, s))) return rc;
+    tmp.release(gws);
+  }
+  if ((rc = c->arena.alloc(&c->Kinv, (size_t)c->q * c->ldk * sizeof(T)))) return rc;
+  {
+    double *fws;
+    if ((rc = tmp.alloc((void **)&fws, ((size_t)Q * Q + (size_t)Q * 64) * 8))) return rc;
+    if ((rc = run_factor_inverse<T>(K, c->q, Q, (T *)c->Kinv, c->ldk, fws, flags + 1, s))) return rc;
+  }
+  unsigned hflags[2] = {0, 0};
+  POGS_HIP_TRY(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+  POGS_HIP_TRY(hipStreamSynchronize(s));
+  POGS_HIP_TRY(hipGetLastError());
+  if (hflags[0]) return POGS_EINVAL;  // non-finite entries in A
+  if (hflags[1]) return POGS_EDEVICE;  // I + G not positive definite numerically
+  return POGS_OK;
+}
+
+template <typename T> int alloc_iteration(pogs_ctx *c) {
+  const int m = (int)c->m, n = (int)c->n;
+  int rc;
+  if ((rc = c->arena.alloc(&c->vec, c->vec_elems() * sizeof(T)))) return rc;
+  POGS_HIP_TRY(hipMemsetAsync(c->vec, 0, c->vec_elems() * sizeof(T), c->stream));
+  if ((rc = c->arena.alloc((void **)&c->fh, m))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->gh, n))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->fh0, m))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->gh0, n))) return rc;
+  if ((rc = c->arena.alloc(&c->fs, (size_t)5 * m * sizeof(T)))) return rc;
+  if ((rc = c->arena.alloc(&c->gs, (size_t)5 * n * sizeof(T)))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->f0, (size_t)5 * m * 8))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->g0, (size_t)5 * n * 8))) return rc;
+  // gemv_t geometry over the n columns (same for both orientations)
+  gemv_t_geometry(m, n, sizeof(T), &c->splits, &c->rps, &c->ncolp);
+  if ((rc = c->arena.alloc((void **)&c->part, (size_t)c->splits * 2 * c->ncolp * 8))) return rc;
+  c->nbx = (int)cdiv(n, kBlock);
+  c->nby = (int)cdiv(m, kBlock);
+  c->n_pri = gemv_n_blocks(m, n, sizeof(T), 0);
+  c->n_dual = (int)cdiv(n, gemv_t_tile(sizeof(T)));
+  const int nslots = c->nbx + c->nby + c->n_pri + c->n_dual + c->nbx + c->nby;  // + unscale slots
+  if ((rc = c->arena.alloc((void **)&c->slots, (size_t)nslots * 8))) return rc;
+  const int ntiles = (int)cdiv(n, gemv_t_tile(sizeof(T)));
+  if ((rc = c->arena.alloc((void **)&c->counters, (size_t)(ntiles + 64) * sizeof(unsigned)))) return rc;
+  POGS_HIP_TRY(hipMemsetAsync(c->counters, 0, (size_t)(ntiles + 64) * sizeof(unsigned), c->stream));
+  if ((rc = c->arena.alloc((void **)&c->ctrl, sizeof(Ctrl)))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->obj_dev, 64))) return rc;
+  if (hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl)) != hipSuccess) return POGS_ENOMEM;
+  if (hipHostMalloc((void **)&c->obj_host, 64) != hipSuccess) return POGS_ENOMEM;
+  return POGS_OK;
+}
+
+}  // namespace
+
+extern "C" int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, pogs_dtype dt, pogs_order ord,
+                         int64_t lda, pogs_mem mem, const pogs_params *params, void *stream) {
+  if (!out) return POGS_EINVAL;
+  *out = nullptr;
+  if (m <= 0 || n <= 0 || !A || m > (1LL << 31) - 1 || n > (1LL << 31) - 1) return POGS_EINVAL;
+  if (dt != POGS_F32 && dt != POGS_F64) return POGS_EINVAL;
+  if (ord != POGS_ROW_MAJOR && ord != POGS_COL_MAJOR) return POGS_EINVAL;
+  if (mem != POGS_HOST && mem != POGS_DEVICE) return POGS_EINVAL;
+  if (lda < (ord == POGS_ROW_MAJOR ? n : m)) return POGS_EINVAL;
+  if ((size_t)round_up(m, 64) * (size_t)round_up(n, 64) > (size_t)(1ULL << 40)) return POGS_EINVAL;
+  if (std::min(m, n) > 32768) return POGS_EUNSUPPORTED;  // factor of I + G would exceed 8 GiB
+  pogs_params p;
+  pogs_params_default(&p);
+  if (params) p = *params;
+  if (check_params(p)) return POGS_EINVAL;
+  const double t0 = now_ms();
+  pogs_ctx *c = new (std::nothrow) pogs_ctx();
+  if (!c) return POGS_ENOMEM;
+  c->m = m;
+  c->n = n;
+  c->dt = dt;
+  c->params = p;
+  c->ld = (int)round_up(n, 64);
+  c->q = (int)std::min(m, n);
+  c->Q = (int)round_up(c->q, 64);
+  c->ldk = (int)round_up(c->q, 64);
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return POGS_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  int rc = dt == POGS_F32 ? init_impl<float>(c, A, dt, ord, lda, mem) : init_impl<double>(c, A, dt, ord, lda, mem);
+  if (!rc) rc = dt == POGS_F32 ? alloc_iteration<float>(c) : alloc_iteration<double>(c);
+  if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = POGS_EDEVICE;
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  c->ms_setup = now_ms() - t0;
+  *out = c;
+  return POGS_OK;
+}
+
+namespace {
+
+template <typename T> int upload_fns(pogs_ctx *c, const HostFn &f, const HostFn &g) {
+  const int m = (int)c->m, n = (int)c->n;
+  hipStream_t s = c->stream;
+  const HostFn *fs[2] = {&f, &g};
+  double *dst[2] = {c->f0, c->g0};
+  uint8_t *hd[2] = {c->fh0, c->gh0};
+  const int len[2] = {m, n};
+  for (int k = 0; k < 2; ++k) {
+    const HostFn &F = *fs[k];
+    const int L = len[k];
+    POGS_HIP_TRY(hipMemcpyAsync(hd[k], F.h.data(), L, hipMemcpyHostToDevice, s));
+    const std::vector<double> *arr[5] = {&F.a, &F.b, &F.c, &F.d, &F.e};
+    for (int j = 0; j < 5; ++j)
+      POGS_HIP_TRY(hipMemcpyAsync(dst[k] + (size_t)j * L, arr[j]->data(), (size_t)L * 8, hipMemcpyHostToDevice, s));
+  }
+  T *fsp = (T *)c->fs, *gsp = (T *)c->gs;
+  // f^(y) = f(y / D), g^(x) = g(E x)  (Section 4.1)
+  launch_scale_fn<T>(c->fh0, c->f0, c->f0 + m, c->f0 + 2 * m, c->f0 + 3 * m, c->f0 + 4 * m, c->D, true, m, c->fh, fsp,
+                     fsp + m, fsp + 2 * m, fsp + 3 * m, fsp + 4 * m, s);
+  launch_scale_fn<T>(c->gh0, c->g0, c->g0 + n, c->g0 + 2 * n, c->g0 + 3 * n, c->g0 + 4 * n, c->E, false, n, c->gh, gsp,
+                     gsp + n, gsp + 2 * n, gsp + 3 * n, gsp + 4 * n, s);
+  // The host vectors must outlive the asynchronous copies.
+  POGS_HIP_TRY(hipStreamSynchronize(s));
+  return POGS_OK;
+}
+
+template <typename T> int ensure_graph(pogs_ctx *c, int chunk) {
+  if (c->graph && c->graph_chunk == chunk) return POGS_OK;
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  const IterArgs<T> p = c->iter_args<T>();
+  hipGraph_t g;
+  POGS_HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < chunk; ++i) launch_iteration<T>(p, c->splits, c->rps, c->ncolp, c->stream);
+  POGS_HIP_TRY(hipStreamEndCapture(c->stream, &g));
+  hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return POGS_EDEVICE;
+  c->graph_chunk = chunk;
+  return POGS_OK;
+}
+
+template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn &g, const pogs_params &p,
+                                     pogs_result *out) {
+  const double t0 = now_ms();
+  const int m = (int)c->m, n = (int)c->n;
+  hipStream_t s = c->stream;
+  int rc;
+  if ((rc = upload_fns<T>(c, f, g))) return rc;
+  // zero state (Algorithm 1 starts from x = y = x~ = y~ = 0)
+  POGS_HIP_TRY(hipMemsetAsync(c->vec, 0, c->vec_elems() * sizeof(T), s));
+  Ctrl h{};
+  h.rho = p.rho0;
+  h.rescale = 1.0;
+  h.eps_abs = p.eps_abs;
+  h.eps_rel = p.eps_rel;
+  h.alpha = p.alpha;
+  h.delta = p.delta;
+  h.tau = p.tau;
+  h.max_iter = p.max_iter;
+  h.adaptive = p.adaptive_rho ? 1 : 0;
+  *c->ctrl_host = h;
+  POGS_HIP_TRY(hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  const int chunk = std::max(1, p.chunk_iters > 0 ? p.chunk_iters : 20);
+  if ((rc = ensure_graph<T>(c, chunk))) return rc;
+  for (;;) {
+    POGS_HIP_TRY(hipGraphLaunch(c->graph, s));
+    POGS_HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    POGS_HIP_TRY(hipStreamSynchronize(s));
+    if (p.verbose)
+      fprintf(stderr, "pogs: k=%d r_pri=%.3e eps_pri=%.3e r_dual=%.3e eps_dual=%.3e rho=%.4g\n", c->ctrl_host->k,
+              c->ctrl_host->r_pri, c->ctrl_host->eps_pri, c->ctrl_host->r_dual, c->ctrl_host->eps_dual,
+              c->ctrl_host->rho);
+    if (c->ctrl_host->done) break;
+  }
+  // unscale into the caller's buffers (device) or staging (host)
+  const IterArgs<T> ia = c->iter_args<T>();
+  T *xo = c->vecp<T>(11), *yo = c->vecp<T>(12), *muo = c->vecp<T>(13), *nuo = c->vecp<T>(14);
+  if (out->mem == POGS_DEVICE) {
+    xo = (T *)out->x;
+    yo = (T *)out->y;
+    muo = (T *)out->mu;
+    nuo = (T *)out->nu;
+  }
+  double *fa = c->f0, *ga = c->g0;
+  launch_unscale<T>(ia, c->D, c->E, c->fh0, fa, fa + m, fa + 2 * m, fa + 3 * m, fa + 4 * m, c->gh0, ga, ga + n,
+                    ga + 2 * n, ga + 3 * n, ga + 4 * n, xo, yo, muo, nuo, c->slots + ia.nbx + ia.nby + ia.n_pri + ia.n_dual,
+                    c->obj_dev, c->counters + (int)cdiv(n, gemv_t_tile(sizeof(T))) + 8, s);
+  POGS_HIP_TRY(hipMemcpyAsync(c->obj_host, c->obj_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (out->mem == POGS_HOST) {
+    if (out->x) POGS_HIP_TRY(hipMemcpyAsync(out->x, xo, (size_t)n * sizeof(T), hipMemcpyDeviceToHost, s));
+    if (out->y) POGS_HIP_TRY(hipMemcpyAsync(out->y, yo, (size_t)m * sizeof(T), hipMemcpyDeviceToHost, s));
+    if (out->mu) POGS_HIP_TRY(hipMemcpyAsync(out->mu, muo, (size_t)n * sizeof(T), hipMemcpyDeviceToHost, s));
+    if (out->nu) POGS_HIP_TRY(hipMemcpyAsync(out->nu, nuo, (size_t)m * sizeof(T), hipMemcpyDeviceToHost, s));
+  }
+  POGS_HIP_TRY(hipStreamSynchronize(s));
+  POGS_HIP_TRY(hipGetLastError());
+  const Ctrl &r = *c->ctrl_host;
+  out->optval = *c->obj_host;
+  out->r_pri = r.r_pri;
+  out->r_dual = r.r_dual;
+  out->eps_pri = r.eps_pri;
+  out->eps_dual = r.eps_dual;
+  out->rho = r.rho;
+  out->iters = r.k;
+  out->status = r.done - 1;
+  out->ms_setup = c->ms_setup;
+  out->ms_solve = now_ms() - t0;
+  return POGS_OK;
+}
+
+}  // namespace
+
+extern "C" int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, const pogs_params *params,
+                          const void *x0, const void *nu0, pogs_result *out) {
+  if (!ctx || !f || !g || !out) return POGS_EINVAL;
+  if (x0 || nu0) return POGS_EUNSUPPORTED;
+  if (out->mem != POGS_HOST && out->mem != POGS_DEVICE) return POGS_EINVAL;
+  pogs_params p = params ? *params : ctx->params;
+  if (check_params(p)) return POGS_EINVAL;
+  HostFn hf, hg;
+  int rc;
+  if ((rc = expand_fn(f, ctx->m, &hf))) return rc;
+  if ((rc = expand_fn(g, ctx->n, &hg))) return rc;
+  return ctx->dt == POGS_F32 ? solve_impl<float>(ctx, hf, hg, p, out) : solve_impl<double>(ctx, hf, hg, p, out);
+}
+
+extern "C" int pogs_get_scaling(pogs_ctx *ctx, double *D, double *E, pogs_mem mem) {
+  if (!ctx || (mem != POGS_HOST && mem != POGS_DEVICE)) return POGS_EINVAL;
+  const hipMemcpyKind k = mem == POGS_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (D) POGS_HIP_TRY(hipMemcpyAsync(D, ctx->D, (size_t)ctx->m * 8, k, ctx->stream));
+  if (E) POGS_HIP_TRY(hipMemcpyAsync(E, ctx->E, (size_t)ctx->n * 8, k, ctx->stream));
+  POGS_HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return POGS_OK;
+}
+
+namespace {
+template <typename T> int project_impl(pogs_ctx *c, const void *cv, const void *dv, void *x, void *y, pogs_mem mem) {
+  const int m = (int)c->m, n = (int)c->n;
+  hipStream_t s = c->stream;
+  // inputs/outputs staged in the output vectors 11..14 when on the host
+  const T *cin = (const T *)cv, *din = (const T *)dv;
+  T *xo = (T *)x, *yo = (T *)y;
+  if (mem == POGS_HOST) {
+    T *cs = c->vecp<T>(13), *ds = c->vecp<T>(14);
+    POGS_HIP_TRY(hipMemcpyAsync(cs, cv, (size_t)n * sizeof(T), hipMemcpyHostToDevice, s));
+    POGS_HIP_TRY(hipMemcpyAsync(ds, dv, (size_t)m * sizeof(T), hipMemcpyHostToDevice, s));
+    cin = cs;
+    din = ds;
+    xo = c->vecp<T>(11);
+    yo = c->vecp<T>(12);
+  }
+  launch_project<T>(c->iter_args<T>(), c->splits, c->rps, c->ncolp, cin, din, xo, yo, s);
+  if (mem == POGS_HOST) {
+    POGS_HIP_TRY(hipMemcpyAsync(x, xo, (size_t)n * sizeof(T), hipMemcpyDeviceToHost, s));
+    POGS_HIP_TRY(hipMemcpyAsync(y, yo, (size_t)m * sizeof(T), hipMemcpyDeviceToHost, s));
+  }
+  POGS_HIP_TRY(hipStreamSynchronize(s));
+  POGS_HIP_TRY(hipGetLastError());
+  return POGS_OK;
+}
+
+template <typename T> int prox_impl(const HostFn &F, double rho, const void *v, void *out, pogs_mem mem,
+                                    hipStream_t s) {
+  const int L = (int)F.h.size();
+  DevArena tmp;
+  int rc;
+  uint8_t *h;
+  T *prm, *vd, *od;
+  if ((rc = tmp.alloc((void **)&h, L))) return rc;
+  if ((rc = tmp.alloc((void **)&prm, (size_t)5 * L * sizeof(T)))) return rc;
+  std::vector<T> hp((size_t)5 * L);
+  const std::vector<double> *arr[5] = {&F.a, &F.b, &F.c, &F.d, &F.e};
+  for (int j = 0; j < 5; ++j)
+    for (int i = 0; i < L; ++i) hp[(size_t)j * L + i] = (T)(*arr[j])[i];
+  POGS_HIP_TRY(hipMemcpyAsync(h, F.h.data(), L, hipMemcpyHostToDevice, s));
+  POGS_HIP_TRY(hipMemcpyAsync(prm, hp.data(), hp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  if (mem == POGS_HOST) {
+    if ((rc = tmp.alloc((void **)&vd, (size_t)L * sizeof(T)))) return rc;
+    if ((rc = tmp.alloc((void **)&od, (size_t)L * sizeof(T)))) return rc;
+    POGS_HIP_TRY(hipMemcpyAsync(vd, v, (size_t)L * sizeof(T), hipMemcpyHostToDevice, s));
+  } else {
+    vd = (T *)v;
+    od = (T *)out;
+  }
+  launch_prox_eval<T>(h, prm, prm + L, prm + 2 * L, prm + 3 * L, prm + 4 * L, rho, vd, od, L, s);
+  if (mem == POGS_HOST) POGS_HIP_TRY(hipMemcpyAsync(out, od, (size_t)L * sizeof(T), hipMemcpyDeviceToHost, s));
+  POGS_HIP_TRY(hipStreamSynchronize(s));
+  POGS_HIP_TRY(hipGetLastError());
+  return POGS_OK;
+}
+}  // namespace
+
+extern "C" int pogs_project(pogs_ctx *ctx, const void *c, const void *d, void *x, void *y, pogs_mem mem) {
+  if (!ctx || !c || !d || !x || !y || (mem != POGS_HOST && mem != POGS_DEVICE)) return POGS_EINVAL;
+  return ctx->dt == POGS_F32 ? project_impl<float>(ctx, c, d, x, y, mem) : project_impl<double>(ctx, c, d, x, y, mem);
+}
+
+extern "C" int pogs_prox(const pogs_fn *fn, pogs_dtype dt, double rho, const void *v, void *out, pogs_mem mem,
+                         void *stream) {
+  if (!fn || !v || !out || fn->len <= 0 || !(rho > 0.0) || !std::isfinite(rho)) return POGS_EINVAL;
+  if ((dt != POGS_F32 && dt != POGS_F64) || (mem != POGS_HOST && mem != POGS_DEVICE)) return POGS_EINVAL;
+  HostFn F;
+  int rc;
+  if ((rc = expand_fn(fn, fn->len, &F))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  return dt == POGS_F32 ? prox_impl<float>(F, rho, v, out, mem, s) : prox_impl<double>(F, rho, v, out, mem, s);
+}

@@ -1,0 +1,440 @@
+"""ctypes binding to libpogs.so (the C ABI declared in include/pogs.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  Host inputs are NumPy arrays; device inputs/outputs are torch
+CUDA (ROCm) tensors, whose data pointers and the current torch stream are
+handed to the library.  If libpogs.so is missing, loading raises: there is no
+fallback.
+
+Functions carry the C names (``pogs_init``, ``pogs_solve``, ...); ``Context``
+wraps a ``pogs_ctx`` handle.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpogs.so")
+
+# --- constants of include/pogs.h ------------------------------------------
+POGS_OK, POGS_EINVAL, POGS_ENOMEM, POGS_EDEVICE, POGS_EAGAIN, POGS_ENOTFOUND, POGS_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+POGS_CONVERGED, POGS_MAXITER, POGS_NUMERICAL, POGS_CANCELLED = 0, 1, 2, 3
+POGS_F32, POGS_F64 = 0, 1
+POGS_ROW_MAJOR, POGS_COL_MAJOR = 0, 1
+POGS_HOST, POGS_DEVICE = 0, 1
+H_CODES = {"zero": 0, "identity": 1, "abs": 2, "square": 3, "huber": 4, "hinge": 5,
+           "logistic": 6, "ind_ge0": 7, "ind_le0": 8, "ind_eq0": 9, "ind_box01": 10}
+STATUS_NAMES = {0: "converged", 1: "maxiter", 2: "numerical", 3: "cancelled"}
+
+
+class PogsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {_lib().pogs_strerror(code).decode()} ({code})")
+
+
+class pogs_fn(C.Structure):
+    _fields_ = [("len", C.c_int64), ("stride", C.c_int64), ("h", C.POINTER(C.c_uint8)),
+                ("a", C.POINTER(C.c_double)), ("b", C.POINTER(C.c_double)),
+                ("c", C.POINTER(C.c_double)), ("d", C.POINTER(C.c_double)),
+                ("e", C.POINTER(C.c_double))]
+
+
+class pogs_params(C.Structure):
+    _fields_ = [("eps_abs", C.c_double), ("eps_rel", C.c_double), ("max_iter", C.c_int32),
+                ("rho0", C.c_double), ("alpha", C.c_double), ("delta", C.c_double),
+                ("tau", C.c_double), ("adaptive_rho", C.c_int32), ("equil_iters", C.c_int32),
+                ("eps_cmp", C.c_double), ("chunk_iters", C.c_int32), ("verbose", C.c_int32)]
+
+
+class pogs_result(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("mu", C.c_void_p), ("nu", C.c_void_p),
+                ("mem", C.c_int), ("optval", C.c_double), ("r_pri", C.c_double),
+                ("r_dual", C.c_double), ("eps_pri", C.c_double), ("eps_dual", C.c_double),
+                ("rho", C.c_double), ("iters", C.c_int32), ("status", C.c_int32),
+                ("ms_setup", C.c_double), ("ms_solve", C.c_double)]
+
+
+class pogs_problem(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("A", C.c_void_p), ("dt", C.c_int),
+                ("ord", C.c_int), ("lda", C.c_int64), ("f", pogs_fn), ("g", pogs_fn),
+                ("params", pogs_params)]
+
+
+class pogs_batch_cfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
+                ("chunk_iters", C.c_int32), ("stream", C.c_void_p)]
+
+
+_LIB = None
+
+# every symbol of include/pogs.h with (restype, argtypes)
+_SIGS = {
+    "pogs_strerror": (C.c_char_p, [C.c_int]),
+    "pogs_params_default": (C.c_int, [C.POINTER(pogs_params)]),
+    "pogs_init": (C.c_int, [C.POINTER(C.c_void_p), C.c_int64, C.c_int64, C.c_void_p, C.c_int, C.c_int,
+                            C.c_int64, C.c_int, C.POINTER(pogs_params), C.c_void_p]),
+    "pogs_solve": (C.c_int, [C.c_void_p, C.POINTER(pogs_fn), C.POINTER(pogs_fn), C.POINTER(pogs_params),
+                             C.c_void_p, C.c_void_p, C.POINTER(pogs_result)]),
+    "pogs_solve_path": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(pogs_fn), C.POINTER(pogs_fn),
+                                  C.POINTER(pogs_params), C.POINTER(pogs_result)]),
+    "pogs_free": (C.c_int, [C.c_void_p]),
+    "pogs_get_scaling": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "pogs_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "pogs_prox": (C.c_int, [C.POINTER(pogs_fn), C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
+                            C.c_void_p]),
+    "pogs_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(pogs_batch_cfg)]),
+    "pogs_batch_submit": (C.c_int, [C.c_void_p, C.POINTER(pogs_problem), C.POINTER(C.c_uint64)]),
+    "pogs_batch_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(pogs_result)]),
+    "pogs_batch_wait_all": (C.c_int, [C.c_void_p]),
+    "pogs_batch_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "pogs_batch_destroy": (C.c_int, [C.c_void_p]),
+    "pogs_solve_batch": (C.c_int, [C.c_int32, C.POINTER(pogs_problem), C.POINTER(pogs_result), C.c_void_p]),
+}
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built (python -m paper_1503_08366_amd.build)")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def load() -> C.CDLL:
+    """Load libpogs.so (raises if it is missing) and return the handle."""
+    return _lib()
+
+
+def _check(rc: int, what: str):
+    if rc != POGS_OK:
+        raise PogsError(rc, what)
+
+
+# --- marshalling helpers -----------------------------------------------------
+
+def default_params(**overrides) -> pogs_params:
+    p = pogs_params()
+    _check(_lib().pogs_params_default(C.byref(p)), "pogs_params_default")
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+class _FnHolder:
+    """Keeps the arrays behind a pogs_fn alive for the duration of a call."""
+
+    def __init__(self, fn, length: int):
+        if fn.size != length:
+            raise ValueError(f"function has length {fn.size}, expected {length}")
+        hname = fn.h
+        self.h = np.full(length, H_CODES[hname], dtype=np.uint8)
+        self.arrs = [np.ascontiguousarray(fn.field(k), dtype=np.float64) for k in "abcde"]
+        dp = C.POINTER(C.c_double)
+        self.s = pogs_fn(length, 1, self.h.ctypes.data_as(C.POINTER(C.c_uint8)),
+                         *(a.ctypes.data_as(dp) for a in self.arrs))
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _dtype_code(x) -> int:
+    if _is_torch(x):
+        import torch
+        if x.dtype == torch.float32:
+            return POGS_F32
+        if x.dtype == torch.float64:
+            return POGS_F64
+        raise TypeError(x.dtype)
+    if x.dtype == np.float32:
+        return POGS_F32
+    if x.dtype == np.float64:
+        return POGS_F64
+    raise TypeError(x.dtype)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _np_dtype(code: int):
+    return np.float32 if code == POGS_F32 else np.float64
+
+
+class Result:
+    """Host copy of a pogs_result plus the returned vectors."""
+
+    def __init__(self, r: pogs_result, x, y, mu, nu):
+        self.x, self.y, self.mu, self.nu = x, y, mu, nu
+        self.optval = r.optval
+        self.r_pri, self.r_dual = r.r_pri, r.r_dual
+        self.eps_pri, self.eps_dual = r.eps_pri, r.eps_dual
+        self.rho = r.rho
+        self.iters = r.iters
+        self.status = r.status
+        self.ms_setup, self.ms_solve = r.ms_setup, r.ms_solve
+
+    @property
+    def converged(self) -> bool:
+        return self.status == POGS_CONVERGED
+
+    def __repr__(self):
+        return (f"Result(status={STATUS_NAMES.get(self.status, self.status)}, iters={self.iters}, "
+                f"optval={self.optval:.6g}, r_pri={self.r_pri:.3g}/{self.eps_pri:.3g}, "
+                f"r_dual={self.r_dual:.3g}/{self.eps_dual:.3g})")
+
+
+# --- C-named entry points ------------------------------------------------------
+
+def pogs_init(A, params: Optional[pogs_params] = None, stream=None) -> "Context":
+    """Create a context for A: a NumPy array (host) or a torch CUDA tensor
+    (device), 2-D, float32 or float64, C- or F-contiguous."""
+    return Context(A, params, stream)
+
+
+def pogs_solve(ctx: "Context", f, g, params: Optional[pogs_params] = None, device_out: bool = False):
+    return ctx.solve(f, g, params, device_out=device_out)
+
+
+def pogs_free(ctx: "Context"):
+    ctx.free()
+
+
+def pogs_prox(fn, v, rho: float, stream=None):
+    """prox_{fn,rho}(v) evaluated on the device; v NumPy (host) or torch CUDA tensor."""
+    holder = _FnHolder(fn, len(v))
+    dt = _dtype_code(v)
+    if _is_torch(v):
+        import torch
+        v = v.contiguous()
+        out = torch.empty_like(v)
+        s = _stream_handle(stream if stream is not None else torch.cuda.current_stream())
+        _check(_lib().pogs_prox(C.byref(holder.s), dt, float(rho), C.c_void_p(v.data_ptr()),
+                                C.c_void_p(out.data_ptr()), POGS_DEVICE, s), "pogs_prox")
+        return out
+    v = np.ascontiguousarray(v)
+    out = np.empty_like(v)
+    _check(_lib().pogs_prox(C.byref(holder.s), dt, float(rho), v.ctypes.data_as(C.c_void_p),
+                            out.ctypes.data_as(C.c_void_p), POGS_HOST, _stream_handle(stream)), "pogs_prox")
+    return out
+
+
+class Context:
+    """A pogs_ctx: the scaled matrix, D, E and the cached factor on the device."""
+
+    def __init__(self, A, params: Optional[pogs_params] = None, stream=None):
+        lib = _lib()
+        if A.ndim != 2:
+            raise ValueError("A must be 2-D")
+        m, n = int(A.shape[0]), int(A.shape[1])
+        self.dtype = _dtype_code(A)
+        self.m, self.n = m, n
+        if _is_torch(A):
+            st = A.stride()
+            if st[1] == 1:
+                order, lda = POGS_ROW_MAJOR, st[0]
+            elif st[0] == 1:
+                order, lda = POGS_COL_MAJOR, st[1]
+            else:
+                A = A.contiguous()
+                order, lda = POGS_ROW_MAJOR, n
+            ptr, mem = A.data_ptr(), POGS_DEVICE
+            if stream is None:
+                import torch
+                stream = torch.cuda.current_stream()
+        else:
+            if A.flags.c_contiguous:
+                order, lda = POGS_ROW_MAJOR, n
+            elif A.flags.f_contiguous:
+                order, lda = POGS_COL_MAJOR, m
+            else:
+                A = np.ascontiguousarray(A)
+                order, lda = POGS_ROW_MAJOR, n
+            ptr, mem = A.ctypes.data, POGS_HOST
+        self.stream = stream
+        handle = C.c_void_p()
+        rc = lib.pogs_init(C.byref(handle), m, n, C.c_void_p(ptr), self.dtype, order, lda, mem,
+                           C.byref(params) if params is not None else None, _stream_handle(stream))
+        _check(rc, "pogs_init")
+        self.handle = handle
+
+    def _h(self):
+        if not self.handle:
+            raise RuntimeError("context freed")
+        return self.handle
+
+    def free(self):
+        if getattr(self, "handle", None):
+            _lib().pogs_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+    def solve(self, f, g, params: Optional[pogs_params] = None, device_out: bool = False) -> Result:
+        fh, gh = _FnHolder(f, self.m), _FnHolder(g, self.n)
+        r = pogs_result()
+        npdt = _np_dtype(self.dtype)
+        if device_out:
+            import torch
+            tdt = torch.float32 if self.dtype == POGS_F32 else torch.float64
+            outs = [torch.empty(k, dtype=tdt, device="cuda") for k in (self.n, self.m, self.n, self.m)]
+            r.x, r.y, r.mu, r.nu = (o.data_ptr() for o in outs)
+            r.mem = POGS_DEVICE
+        else:
+            outs = [np.empty(k, dtype=npdt) for k in (self.n, self.m, self.n, self.m)]
+            r.x, r.y, r.mu, r.nu = (o.ctypes.data for o in outs)
+            r.mem = POGS_HOST
+        rc = _lib().pogs_solve(self._h(), C.byref(fh.s), C.byref(gh.s),
+                               C.byref(params) if params is not None else None, None, None, C.byref(r))
+        _check(rc, "pogs_solve")
+        return Result(r, *outs)
+
+    def solve_path(self, fs: Sequence, gs: Sequence, params: Optional[pogs_params] = None) -> List[Result]:
+        R = len(fs)
+        fh = [_FnHolder(f, self.m) for f in fs]
+        gh = [_FnHolder(g, self.n) for g in gs]
+        farr = (pogs_fn * R)(*(h.s for h in fh))
+        garr = (pogs_fn * R)(*(h.s for h in gh))
+        res = (pogs_result * R)()
+        npdt = _np_dtype(self.dtype)
+        outs = []
+        for r in range(R):
+            o = [np.empty(k, dtype=npdt) for k in (self.n, self.m, self.n, self.m)]
+            res[r].x, res[r].y, res[r].mu, res[r].nu = (a.ctypes.data for a in o)
+            res[r].mem = POGS_HOST
+            outs.append(o)
+        rc = _lib().pogs_solve_path(self._h(), R, farr, garr, C.byref(params) if params is not None else None, res)
+        _check(rc, "pogs_solve_path")
+        return [Result(res[r], *outs[r]) for r in range(R)]
+
+    def scaling(self):
+        D = np.empty(self.m)
+        E = np.empty(self.n)
+        _check(_lib().pogs_get_scaling(self._h(), D.ctypes.data_as(C.c_void_p), E.ctypes.data_as(C.c_void_p),
+                                       POGS_HOST), "pogs_get_scaling")
+        return D, E
+
+    def project(self, c, d):
+        """Projection onto the graph of the scaled matrix D A E."""
+        if _is_torch(c):
+            import torch
+            x = torch.empty_like(c)
+            y = torch.empty_like(d)
+            _check(_lib().pogs_project(self._h(), C.c_void_p(c.data_ptr()), C.c_void_p(d.data_ptr()),
+                                       C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), POGS_DEVICE),
+                   "pogs_project")
+            return x, y
+        npdt = _np_dtype(self.dtype)
+        c = np.ascontiguousarray(c, dtype=npdt)
+        d = np.ascontiguousarray(d, dtype=npdt)
+        x = np.empty(self.n, dtype=npdt)
+        y = np.empty(self.m, dtype=npdt)
+        _check(_lib().pogs_project(self._h(), c.ctypes.data_as(C.c_void_p), d.ctypes.data_as(C.c_void_p),
+                                   x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p), POGS_HOST),
+               "pogs_project")
+        return x, y
+
+
+def _problem_struct(p, params: Optional[pogs_params], keep: list) -> pogs_problem:
+    A = np.ascontiguousarray(p.A)
+    if A.dtype != np.float32:
+        raise TypeError("batched problems take float32 matrices")
+    fh, gh = _FnHolder(p.f, A.shape[0]), _FnHolder(p.g, A.shape[1])
+    keep.extend([A, fh, gh])
+    prm = params if params is not None else default_params(eps_abs=p.eps_abs, eps_rel=p.eps_rel,
+                                                           max_iter=p.max_iter)
+    return pogs_problem(A.shape[0], A.shape[1], A.ctypes.data, POGS_F32, POGS_ROW_MAJOR, A.shape[1],
+                        fh.s, gh.s, prm)
+
+
+def _host_outputs(m: int, n: int, r: pogs_result, keep: list):
+    o = [np.empty(k, dtype=np.float32) for k in (n, m, n, m)]
+    r.x, r.y, r.mu, r.nu = (a.ctypes.data for a in o)
+    r.mem = POGS_HOST
+    keep.append(o)
+    return o
+
+
+def pogs_solve_batch(problems: Sequence, params: Optional[pogs_params] = None, stream=None) -> List[Result]:
+    """Solve independent problems (workload ``Problem`` objects) in one batched call."""
+    keep: list = []
+    N = len(problems)
+    arr = (pogs_problem * N)(*(_problem_struct(p, params, keep) for p in problems))
+    res = (pogs_result * N)()
+    outs = [_host_outputs(p.m, p.n, res[i], keep) for i, p in enumerate(problems)]
+    _check(_lib().pogs_solve_batch(N, arr, res, _stream_handle(stream)), "pogs_solve_batch")
+    return [Result(res[i], *outs[i]) for i in range(N)]
+
+
+class BatchEngine:
+    """pogs_batch: a serving engine with its own scheduler thread."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 0, chunk_iters: int = 0):
+        cfg = pogs_batch_cfg(hbm_budget_bytes, max_slots, chunk_iters, None)
+        h = C.c_void_p()
+        _check(_lib().pogs_batch_create(C.byref(h), C.byref(cfg)), "pogs_batch_create")
+        self.handle = h
+        self._pending = {}
+
+    def submit(self, p, params: Optional[pogs_params] = None) -> int:
+        keep: list = []
+        s = _problem_struct(p, params, keep)
+        t = C.c_uint64()
+        _check(_lib().pogs_batch_submit(self.handle, C.byref(s), C.byref(t)), "pogs_batch_submit")
+        self._pending[t.value] = (p.m, p.n)
+        return t.value
+
+    def poll(self, ticket: int) -> Optional[Result]:
+        m, n = self._pending[ticket]
+        keep: list = []
+        r = pogs_result()
+        o = _host_outputs(m, n, r, keep)
+        rc = _lib().pogs_batch_poll(self.handle, ticket, C.byref(r))
+        if rc == 1:
+            return None
+        _check(rc, "pogs_batch_poll")
+        del self._pending[ticket]
+        return Result(r, *o)
+
+    def cancel(self, ticket: int):
+        _check(_lib().pogs_batch_cancel(self.handle, ticket), "pogs_batch_cancel")
+
+    def wait_all(self):
+        _check(_lib().pogs_batch_wait_all(self.handle), "pogs_batch_wait_all")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib().pogs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,118 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+declared in include/pogs.h, and rejects bad arguments before touching the
+device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pogs.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pogs_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1503_08366_amd import pogs
+    if not os.path.exists(pogs.LIB_PATH):
+        pytest.skip("libpogs.so not built")
+    return pogs.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for must in ["pogs_init", "pogs_solve", "pogs_solve_path", "pogs_free", "pogs_batch_create",
+                 "pogs_batch_submit", "pogs_batch_poll", "pogs_batch_destroy", "pogs_strerror",
+                 "pogs_params_default", "pogs_project", "pogs_prox", "pogs_get_scaling",
+                 "pogs_solve_batch"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1503_08366_amd import pogs
+    assert set(_declared_functions()) == set(pogs._SIGS)
+
+
+def test_params_default_and_strerror(lib):
+    from paper_1503_08366_amd import pogs
+    p = pogs.default_params()
+    assert (p.eps_abs, p.eps_rel, p.max_iter, p.rho0, p.alpha, p.delta, p.tau) == \
+        (1e-4, 1e-3, 10000, 1.0, 1.7, 1.05, 0.8)
+    assert p.adaptive_rho == 1 and p.equil_iters == 10
+    assert lib.pogs_params_default(None) == pogs.POGS_EINVAL
+    for code in [0, -1, -2, -3, -4, -5, -6, 99]:
+        assert isinstance(lib.pogs_strerror(code), bytes)
+
+
+def test_init_rejects_bad_arguments_without_device(lib):
+    from paper_1503_08366_amd import pogs
+    A = np.ones((4, 3), dtype=np.float32)
+    h = C.c_void_p()
+    ptr = C.c_void_p(A.ctypes.data)
+    E = pogs.POGS_EINVAL
+    assert lib.pogs_init(None, 4, 3, ptr, 0, 0, 3, 0, None, None) == E
+    assert lib.pogs_init(C.byref(h), 0, 3, ptr, 0, 0, 3, 0, None, None) == E
+    assert lib.pogs_init(C.byref(h), 4, -1, ptr, 0, 0, 3, 0, None, None) == E
+    assert lib.pogs_init(C.byref(h), 4, 3, None, 0, 0, 3, 0, None, None) == E
+    assert lib.pogs_init(C.byref(h), 4, 3, ptr, 7, 0, 3, 0, None, None) == E       # dtype
+    assert lib.pogs_init(C.byref(h), 4, 3, ptr, 0, 5, 3, 0, None, None) == E       # order
+    assert lib.pogs_init(C.byref(h), 4, 3, ptr, 0, 0, 2, 0, None, None) == E       # lda < n
+    assert lib.pogs_init(C.byref(h), 4, 3, ptr, 0, 1, 3, 0, None, None) == E       # col-major lda < m
+    bad = pogs.default_params(alpha=2.5)
+    assert lib.pogs_init(C.byref(h), 4, 3, ptr, 0, 0, 3, 0, C.byref(bad), None) == E
+    bad = pogs.default_params(max_iter=0)
+    assert lib.pogs_init(C.byref(h), 4, 3, ptr, 0, 0, 3, 0, C.byref(bad), None) == E
+    assert h.value is None
+
+
+def test_solve_and_free_reject_null(lib):
+    from paper_1503_08366_amd import pogs
+    r = pogs.pogs_result()
+    assert lib.pogs_solve(None, None, None, None, None, None, C.byref(r)) == pogs.POGS_EINVAL
+    assert lib.pogs_free(None) == pogs.POGS_OK
+    assert lib.pogs_project(None, None, None, None, None, 0) == pogs.POGS_EINVAL
+    assert lib.pogs_get_scaling(None, None, None, 0) == pogs.POGS_EINVAL
+
+
+def test_prox_rejects_bad_functions_without_device(lib):
+    from paper_1503_08366_amd import pogs
+    v = np.zeros(3)
+    out = np.zeros(3)
+    h = np.array([2], np.uint8)
+    neg = np.array([-1.0])
+    zero = np.array([0.0])
+    dp = C.POINTER(C.c_double)
+
+    def fn(h=h, a=None, c=None, e=None, length=3, stride=0):
+        return pogs.pogs_fn(length, stride, h.ctypes.data_as(C.POINTER(C.c_uint8)),
+                            a.ctypes.data_as(dp) if a is not None else None, None,
+                            c.ctypes.data_as(dp) if c is not None else None, None,
+                            e.ctypes.data_as(dp) if e is not None else None)
+
+    call = lambda f, rho=1.0: lib.pogs_prox(C.byref(f), 1, rho, v.ctypes.data, out.ctypes.data, 0, None)
+    E = pogs.POGS_EINVAL
+    assert call(fn(c=neg)) == E                                    # c < 0: not convex
+    assert call(fn(e=neg)) == E                                    # e < 0: not convex
+    assert call(fn(a=zero)) == E                                   # a = 0 with c > 0
+    assert call(fn(h=np.array([42], np.uint8))) == E               # unknown h
+    assert call(fn(a=np.array([np.nan]))) == E                     # non-finite parameter
+    assert call(fn(), rho=0.0) == E                                # rho must be > 0
+    assert call(fn(stride=3)) == E                                 # stride is 0 or 1
+
+
+def test_batch_rejects_null(lib):
+    from paper_1503_08366_amd import pogs
+    assert lib.pogs_batch_submit(None, None, None) in (pogs.POGS_EINVAL, pogs.POGS_EUNSUPPORTED)
+    assert lib.pogs_batch_destroy(None) == pogs.POGS_OK
