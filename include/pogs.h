@@ -180,6 +180,18 @@ int pogs_project(pogs_ctx *ctx, const void *c, const void *d, void *x, void *y, 
 int pogs_prox(const pogs_fn *fn, pogs_dtype dt, double rho, const void *v, void *out,
               pogs_mem mem, void *stream);
 
+/* Time the per-iteration kernels on this context with HIP events on its
+ * stream (a measurement aid for benchmarks).  Requires a previous pogs_solve
+ * on the context (its functions and iterate are reused).  With the stop test
+ * disabled it runs `reps` full iterations as captured launch sequences, then
+ * `reps` back-to-back launches of each iteration kernel alone, and writes
+ *   ms[0] average ms per full iteration,
+ *   ms[1] prox step, ms[2] first pass over A, ms[3] solve with the cached
+ *   inverse, ms[4] second pass over A (average ms per launch).
+ * The solver state afterwards is meaningless; the next pogs_solve resets it.
+ * Errors: EINVAL (NULL, reps < 1, no previous solve), EDEVICE. */
+int pogs_profile_iteration(pogs_ctx *ctx, int32_t reps, double *ms);
+
 /* ---- batched and served solves ------------------------------------------ */
 
 /* One problem for the batch engine (all pointers host memory, copied on

@@ -84,6 +84,8 @@ template <typename T> void launch_scale_fn(const uint8_t *h, const double *a, co
                                            T *oa, T *ob, T *oc, T *od, T *oe, hipStream_t s);
 template <typename T> void launch_iteration(const IterArgs<T> &p, int splits, int rows_per_split,
                                             int ncolp, hipStream_t s);
+template <typename T> void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rows_per_split,
+                                                 int ncolp, hipStream_t s);
 template <typename T> void launch_project(const IterArgs<T> &p, int splits, int rows_per_split,
                                           int ncolp, const T *c, const T *d, T *x, T *y, hipStream_t s);
 template <typename T>

@@ -340,27 +340,47 @@ int gemv_n_blocks(int m, int ncols, int elem_size, int) {
   return cdiv(m, rows1) > 2048 ? (int)cdiv(m, gemv_n_rows_per_block<16, 4>()) : (int)cdiv(m, rows1);
 }
 
+// which: 0 prox, 1 first pass over A, 2 solve, 3 second pass over A.
+template <typename T>
+void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps, int ncolp, hipStream_t s) {
+  const bool tall = p.m >= p.n;
+  switch (which) {
+    case 0:
+      hipLaunchKernelGGL(prox_kernel<T>, dim3(p.nbx + p.nby), dim3(kBlock), 0, s, p);
+      break;
+    case 1:
+      if (tall) {
+        EpiTallPass1<T> e{{p}};
+        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.dy, p.nu, splits, rps, p.part, ncolp, p.tile_cnt, &p.ctrl->cnt_b, e, s);
+      } else {
+        EpiWidePass1<T> e{{p}};
+        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.cx, p.xh, &p.ctrl->cnt_a, e, s);
+      }
+      break;
+    case 2:
+      if (tall) {
+        EpiTallSolve<T> e{{p}};
+        gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, &p.ctrl->cnt_a, e, s);
+      } else {
+        EpiWideSolve<T> e{{p}};
+        gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, &p.ctrl->cnt_a, e, s);
+      }
+      break;
+    default:
+      if (tall) {
+        EpiTallPass2<T> e{{p}};
+        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.x, p.xh, &p.ctrl->cnt_a, e, s);
+      } else {
+        EpiWidePass2<T> e{{p}};
+        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.yt, p.nu, splits, rps, p.part, ncolp, p.tile_cnt, &p.ctrl->cnt_b, e, s);
+      }
+      break;
+  }
+}
+
 template <typename T>
 void launch_iteration(const IterArgs<T> &p, int splits, int rps, int ncolp, hipStream_t s) {
-  const int nprox = p.nbx + p.nby;
-  hipLaunchKernelGGL(prox_kernel<T>, dim3(nprox), dim3(kBlock), 0, s, p);
-  if (p.m >= p.n) {
-    EpiTallPass1<T> e1{{p}};
-    gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.dy, p.nu, splits, rps, p.part, ncolp, p.tile_cnt,
-                    &p.ctrl->cnt_b, e1, s);
-    EpiTallSolve<T> e2{{p}};
-    gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, &p.ctrl->cnt_a, e2, s);
-    EpiTallPass2<T> e3{{p}};
-    gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.x, p.xh, &p.ctrl->cnt_a, e3, s);
-  } else {
-    EpiWidePass1<T> e1{{p}};
-    gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.cx, p.xh, &p.ctrl->cnt_a, e1, s);
-    EpiWideSolve<T> e2{{p}};
-    gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, &p.ctrl->cnt_a, e2, s);
-    EpiWidePass2<T> e3{{p}};
-    gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.yt, p.nu, splits, rps, p.part, ncolp, p.tile_cnt,
-                    &p.ctrl->cnt_b, e3, s);
-  }
+  for (int w = 0; w < 4; ++w) launch_iteration_part<T>(p, w, splits, rps, ncolp, s);
 }
 
 template <typename T>
@@ -483,6 +503,7 @@ void launch_prox_eval(const uint8_t *h, const T *a, const T *b, const T *c, cons
 
 #define POGS_INST(T)                                                                                   \
   template void launch_iteration<T>(const IterArgs<T> &, int, int, int, hipStream_t);                  \
+  template void launch_iteration_part<T>(const IterArgs<T> &, int, int, int, int, hipStream_t);        \
   template void launch_project<T>(const IterArgs<T> &, int, int, int, const T *, const T *, T *, T *,  \
                                   hipStream_t);                                                        \
   template void launch_scale_fn<T>(const uint8_t *, const double *, const double *, const double *,    \

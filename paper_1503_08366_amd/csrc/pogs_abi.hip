@@ -123,6 +123,7 @@ struct pogs_ctx {
   double ms_setup = 0.0;
   hipGraphExec_t graph = nullptr;
   int graph_chunk = 0;
+  bool solved = false;  // functions uploaded by a previous solve
 
   size_t esz() const { return dt == POGS_F32 ? 4 : 8; }
   template <typename T> T *vecp(int idx) const {
@@ -480,6 +481,52 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   out->status = r.done - 1;
   out->ms_setup = c->ms_setup;
   out->ms_solve = now_ms() - t0;
+  c->solved = true;
+  return POGS_OK;
+}
+
+template <typename T> int profile_impl(pogs_ctx *c, int reps, double *ms) {
+  hipStream_t s = c->stream;
+  Ctrl h{};
+  h.rho = 1.0;
+  h.rescale = 1.0;
+  h.eps_abs = 0.0;  // stop test never passes
+  h.eps_rel = 0.0;
+  h.alpha = c->params.alpha;
+  h.delta = c->params.delta;
+  h.tau = c->params.tau;
+  h.max_iter = 0x7fffffff;
+  h.adaptive = 0;
+  *c->ctrl_host = h;
+  POGS_HIP_TRY(hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  const int chunk = std::max(1, c->params.chunk_iters > 0 ? c->params.chunk_iters : 20);
+  int rc;
+  if ((rc = ensure_graph<T>(c, chunk))) return rc;
+  hipEvent_t e0, e1;
+  POGS_HIP_TRY(hipEventCreate(&e0));
+  POGS_HIP_TRY(hipEventCreate(&e1));
+  float t = 0.f;
+  const int launches = (int)cdiv(reps, chunk);
+  POGS_HIP_TRY(hipGraphLaunch(c->graph, s));  // warm
+  POGS_HIP_TRY(hipEventRecord(e0, s));
+  for (int i = 0; i < launches; ++i) POGS_HIP_TRY(hipGraphLaunch(c->graph, s));
+  POGS_HIP_TRY(hipEventRecord(e1, s));
+  POGS_HIP_TRY(hipEventSynchronize(e1));
+  POGS_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+  ms[0] = (double)t / ((double)launches * chunk);
+  const IterArgs<T> p = c->iter_args<T>();
+  for (int w = 0; w < 4; ++w) {
+    launch_iteration_part<T>(p, w, c->splits, c->rps, c->ncolp, s);  // warm
+    POGS_HIP_TRY(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) launch_iteration_part<T>(p, w, c->splits, c->rps, c->ncolp, s);
+    POGS_HIP_TRY(hipEventRecord(e1, s));
+    POGS_HIP_TRY(hipEventSynchronize(e1));
+    POGS_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    ms[1 + w] = (double)t / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  POGS_HIP_TRY(hipGetLastError());
   return POGS_OK;
 }
 
@@ -497,6 +544,11 @@ extern "C" int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, con
   if ((rc = expand_fn(f, ctx->m, &hf))) return rc;
   if ((rc = expand_fn(g, ctx->n, &hg))) return rc;
   return ctx->dt == POGS_F32 ? solve_impl<float>(ctx, hf, hg, p, out) : solve_impl<double>(ctx, hf, hg, p, out);
+}
+
+extern "C" int pogs_profile_iteration(pogs_ctx *ctx, int32_t reps, double *ms) {
+  if (!ctx || reps < 1 || !ms || !ctx->solved) return POGS_EINVAL;
+  return ctx->dt == POGS_F32 ? profile_impl<float>(ctx, reps, ms) : profile_impl<double>(ctx, reps, ms);
 }
 
 extern "C" int pogs_get_scaling(pogs_ctx *ctx, double *D, double *E, pogs_mem mem) {

@@ -17,25 +17,30 @@ __device__ inline float fexp(float x) { return __expf(x); }
 __device__ inline double fexp(double x) { return exp(x); }
 
 // Root of sigma(u) + r (u - z) = 0, i.e. argmin_u log(1 + e^u) + (r/2)(u - z)^2.
-// The left side increases in u and changes sign on [z - 1/r, z]; Newton's
-// method is kept inside that bracket (bisection when a step leaves it), so it
-// always converges.  Fixed cap on the iteration count.
+// The left side increases in u and changes sign on [z - 1/r, z].  Safeguarded
+// Newton: each evaluation shrinks the bracket; a Newton step is taken only if
+// it stays inside the bracket and is less than half the previous step,
+// otherwise the bracket is bisected.  So the bracket at least halves every
+// two iterations and the loop cannot cycle.  Fixed cap on the iteration count.
 template <typename T> __device__ inline T prox_logistic(T z, T r) {
   T lo = z - T(1) / r, hi = z;
   // first guess: one fixed-point step from z
   T u = z - (T(1) / (T(1) + fexp(-z))) / r;
   if (!(u > lo && u < hi)) u = T(0.5) * (lo + hi);
   const T tol = sizeof(T) == 4 ? T(1e-7) : T(1e-15);
-  for (int it = 0; it < 60; ++it) {
+  T last = hi - lo;  // length of the previous step
+  for (int it = 0; it < 100; ++it) {
     const T s = T(1) / (T(1) + fexp(-u));
     const T g = s + r * (u - z);
+    if (g == T(0)) break;
     if (g > T(0)) hi = u; else lo = u;
-    const T gp = s * (T(1) - s) + r;
-    T un = u - g / gp;
-    if (!(un > lo && un < hi)) un = T(0.5) * (lo + hi);
-    const T du = fabs(un - u);
+    const T newton = g / (s * (T(1) - s) + r);
+    T un = u - newton;
+    if (!(un > lo && un < hi) || T(2) * fabs(newton) > last) un = T(0.5) * (lo + hi);
+    last = fabs(un - u);
     u = un;
-    if (du <= tol * fmax(T(1), fabs(u)) || hi - lo <= tol * fmax(T(1), fabs(u))) break;
+    const T scale = fmax(T(1), fabs(u));
+    if (last <= tol * scale || hi - lo <= tol * scale) break;
   }
   return u;
 }

@@ -88,6 +88,7 @@ _SIGS = {
     "pogs_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "pogs_prox": (C.c_int, [C.POINTER(pogs_fn), C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
                             C.c_void_p]),
+    "pogs_profile_iteration": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "pogs_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(pogs_batch_cfg)]),
     "pogs_batch_submit": (C.c_int, [C.c_void_p, C.POINTER(pogs_problem), C.POINTER(C.c_uint64)]),
     "pogs_batch_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(pogs_result)]),
@@ -332,6 +333,12 @@ class Context:
         rc = _lib().pogs_solve_path(self._h(), R, farr, garr, C.byref(params) if params is not None else None, res)
         _check(rc, "pogs_solve_path")
         return [Result(res[r], *outs[r]) for r in range(R)]
+
+    def profile_iteration(self, reps: int = 50):
+        """Average ms of a full iteration and of each iteration kernel (HIP events)."""
+        ms = (C.c_double * 5)()
+        _check(_lib().pogs_profile_iteration(self._h(), reps, ms), "pogs_profile_iteration")
+        return {"iteration": ms[0], "prox": ms[1], "pass1": ms[2], "solve": ms[3], "pass2": ms[4]}
 
     def scaling(self):
         D = np.empty(self.m)
