@@ -1,0 +1,265 @@
+// Workgroup-level building blocks of the setup (256 threads = 4 waves):
+//   * Gram tiles on f32 MFMA (128 x 128 output tile, 4 waves in 2 x 2),
+//   * float64 64 x 64 block products on f64 MFMA,
+//   * the diagonal-block Cholesky / triangular inverse, panel solve, trailing
+//     update, blocked inverse steps and the K^{-1} = L^{-T} L^{-1} product.
+// The multi-workgroup setup launches one workgroup per tile; the batched
+// solver calls the same functions in loops inside one workgroup per problem.
+#pragma once
+
+#include "common.hpp"
+#include "mfma.hpp"
+
+namespace pogs {
+
+constexpr int NB = 64;        // Cholesky block size
+constexpr int LSF = NB + 2;   // row stride of the float64 LDS stages
+
+struct F64Stage {             // 16.9 KB
+  double a[16][LSF];
+  double b[16][LSF];
+};
+struct CholLds {              // 66.6 KB
+  double L[NB][NB + 1];
+  double X[NB][NB + 1];
+};
+constexpr int kGramTB = 128;  // f32 Gram tile
+struct GramStage {            // 16.9 KB
+  float a[16][kGramTB + 4];
+  float b[16][kGramTB + 4];
+};
+
+// Tile pair t of a lower triangle (ti >= tj), row by row.
+__device__ inline void tri_index(int t, int *ti, int *tj) {
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  *ti = i;
+  *tj = t - i * (i + 1) / 2;
+}
+
+typedef float GramAcc __attribute__((ext_vector_type(4)));
+
+// Gram tile (ti, tj) over k in [k0, k1): TALL: sum_k A[k][i] A[k][j] (A^T A),
+// else sum_k A[i][k] A[j][k] (A A^T).  Each wave owns a 64 x 64 quarter as
+// 4 x 4 f32 MFMA 16x16x4 blocks; out(row, col, value) visits the tile's
+// elements (tile-local indices).  Reads beyond m / n are zero.
+template <bool TALL, class Out>
+__device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld, int ti, int tj, int k0, int k1,
+                              GramStage &st, Out out) {
+  constexpr int TB = kGramTB, KC = 16;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  const bool diag = ti == tj;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  GramAcc acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = GramAcc{0.f, 0.f, 0.f, 0.f};
+
+  for (int kk0 = k0; kk0 < k1; kk0 += KC) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int f = t + h * 256;  // float4 index in the 16 x 128 stage
+      if (TALL) {
+        const int k = f >> 5, c = (f & 31) * 4;
+        const int row = kk0 + k;
+        f4 va = f4{0.f, 0.f, 0.f, 0.f}, vb = f4{0.f, 0.f, 0.f, 0.f};
+        if (row < k1) {
+          const int ca = ti * TB + c, cb = tj * TB + c;
+          if (ca < n) va = *reinterpret_cast<const f4 *>(A + (size_t)row * ld + ca);
+          if (!diag && cb < n) vb = *reinterpret_cast<const f4 *>(A + (size_t)row * ld + cb);
+        }
+        *reinterpret_cast<f4 *>(&st.a[k][c]) = va;
+        if (!diag) *reinterpret_cast<f4 *>(&st.b[k][c]) = vb;
+      } else {
+        const int r = f & 127, kq = (f >> 7) * 4;
+        const int kc = kk0 + kq;  // kc + 3 < ld (kk0 % 16 == 0, ld % 64 == 0, kk0 < n <= ld)
+        const int ra = ti * TB + r, rb = tj * TB + r;
+        f4 va = f4{0.f, 0.f, 0.f, 0.f}, vb = f4{0.f, 0.f, 0.f, 0.f};
+        if (ra < m) va = *reinterpret_cast<const f4 *>(A + (size_t)ra * ld + kc);
+        if (!diag && rb < m) vb = *reinterpret_cast<const f4 *>(A + (size_t)rb * ld + kc);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool ok = kc + u < k1;
+          st.a[kq + u][r] = ok ? va[u] : 0.f;
+          if (!diag) st.b[kq + u][r] = ok ? vb[u] : 0.f;
+        }
+      }
+    }
+    __syncthreads();
+    const float(*pb)[TB + 4] = diag ? st.a : st.b;
+#pragma unroll
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      float av[4], bv[4];
+      const int kr = k4 + (lane >> 4), cl = lane & 15;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        av[b] = st.a[kr][wi * 64 + b * 16 + cl];
+        bv[b] = pb[kr][wj * 64 + b * 16 + cl];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // f32 16x16x4 result layout: lane l, element r -> row 4 (l / 16) + r, column l % 16
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out(wi * 64 + i * 16 + 4 * (lane >> 4) + r, wj * 64 + j * 16 + (lane & 15), acc[i][j][r]);
+}
+
+// acc += sum_{k < K} opA(i, k) opB(k, j) for a 64 x 64 float64 tile, with
+// opA(i, k) = pa[i * sai + k * sak], opB(k, j) = pb[k * sbk + j * sbj]
+// (K a multiple of 16).  Ends with a barrier: the stages may be reused and
+// the operands overwritten afterwards.
+__device__ inline void block_product(F64Acc acc[2][2], const double *pa, int64_t sai, int64_t sak, const double *pb,
+                                     int64_t sbk, int64_t sbj, int K, F64Stage &st) {
+  const int t = threadIdx.x, w = t >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int f = t; f < 16 * NB; f += 256) {
+      const int k = f / NB, i = f % NB;
+      st.a[k][i] = pa[(int64_t)i * sai + (int64_t)(k0 + k) * sak];
+      st.b[k][i] = pb[(int64_t)(k0 + k) * sbk + (int64_t)i * sbj];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 16; k4 += 4) f64_tile_step<LSF>(acc, st.a, st.b, k4, wi * 32, wj * 32);
+    __syncthreads();
+  }
+}
+
+__device__ inline void acc_zero(F64Acc acc[2][2]) {
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64acc_zero();
+}
+
+template <class Fn> __device__ inline void acc_store(const F64Acc acc[2][2], Fn fn) {
+  const int w = threadIdx.x >> 6;
+  f64_tile_store(acc, (w >> 1) * 32, (w & 1) * 32, fn);
+}
+
+// Factor diagonal block kb of K (Q x Q, row-major, lower) in LDS by the
+// unblocked right-looking Cholesky and invert the triangular factor by column
+// substitution.  Writes L_kk (upper part zeroed) back into K and L_kk^{-1}
+// into Dinv block kb.  A non-positive pivot counts in *bad (replaced by 1).
+__device__ inline void potrf_diag(double *K, int Q, int kb, double *Dinv, unsigned *bad, CholLds &s) {
+  const int t = threadIdx.x;
+  double *blk = K + (size_t)kb * NB * Q + (size_t)kb * NB;
+  for (int e = t; e < NB * NB; e += 256) s.L[e / NB][e % NB] = blk[(size_t)(e / NB) * Q + e % NB];
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    if (t == 0) {
+      double v = s.L[j][j];
+      if (!(v > 0.0) || !isfinite(v)) {
+        atomicAdd(bad, 1u);
+        v = 1.0;
+      }
+      s.L[j][j] = sqrt(v);
+    }
+    __syncthreads();
+    const double djj = s.L[j][j];
+    for (int r = j + 1 + t; r < NB; r += 256) s.L[r][j] /= djj;
+    __syncthreads();
+    const int nr = NB - 1 - j;
+    for (int e = t; e < nr * nr; e += 256) {
+      const int r = j + 1 + e / nr, c = j + 1 + e % nr;
+      if (c <= r) s.L[r][c] -= s.L[r][j] * s.L[c][j];
+    }
+    __syncthreads();
+  }
+  if (t < NB) {
+    const int c = t;
+    for (int r = 0; r < c; ++r) s.X[r][c] = 0.0;
+    s.X[c][c] = 1.0 / s.L[c][c];
+    for (int r = c + 1; r < NB; ++r) {
+      double acc = 0.0;
+      for (int k = c; k < r; ++k) acc += s.L[r][k] * s.X[k][c];
+      s.X[r][c] = -acc / s.L[r][r];
+    }
+  }
+  __syncthreads();
+  double *dv = Dinv + (size_t)kb * NB * NB;
+  for (int e = t; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e % NB;
+    blk[(size_t)r * Q + c] = c <= r ? s.L[r][c] : 0.0;
+    dv[e] = s.X[r][c];
+  }
+  __syncthreads();
+}
+
+// L_ib,kb = K_ib,kb L_kb,kb^{-T}   (in place)
+__device__ inline void trsm_tile(double *K, int Q, int kb, int ib, const double *Dinv, F64Stage &st) {
+  double *blk = K + (size_t)ib * NB * Q + (size_t)kb * NB;
+  const double *dv = Dinv + (size_t)kb * NB * NB;
+  F64Acc acc[2][2];
+  acc_zero(acc);
+  block_product(acc, blk, Q, 1, dv, 1, NB, NB, st);
+  acc_store(acc, [&](int r, int c, double v) { blk[(size_t)r * Q + c] = v; });
+}
+
+// K_I,J -= L_I,kb L_J,kb^T
+__device__ inline void syrk_tile(double *K, int Q, int kb, int I, int J, F64Stage &st) {
+  const double *LI = K + (size_t)I * NB * Q + (size_t)kb * NB;
+  const double *LJ = K + (size_t)J * NB * Q + (size_t)kb * NB;
+  double *C = K + (size_t)I * NB * Q + (size_t)J * NB;
+  F64Acc acc[2][2];
+  acc_zero(acc);
+  block_product(acc, LI, Q, 1, LJ, 1, Q, NB, st);
+  acc_store(acc, [&](int r, int c, double v) { C[(size_t)r * Q + c] -= v; });
+}
+
+// Blocked L^{-1}, step ib: X_ib,jb <- sum_{k=jb}^{ib-1} L_ib,k X_k,jb   (jb < ib)
+__device__ inline void inv_accum_tile(const double *K, double *X, int Q, int ib, int jb, F64Stage &st) {
+  F64Acc acc[2][2];
+  acc_zero(acc);
+  const double *pa = K + (size_t)ib * NB * Q + (size_t)jb * NB;
+  const double *pb = X + (size_t)jb * NB * Q + (size_t)jb * NB;
+  block_product(acc, pa, Q, 1, pb, Q, 1, (ib - jb) * NB, st);
+  double *C = X + (size_t)ib * NB * Q + (size_t)jb * NB;
+  acc_store(acc, [&](int r, int c, double v) { C[(size_t)r * Q + c] = v; });
+}
+
+// X_ib,jb <- -L_ib,ib^{-1} X_ib,jb   (in place)
+__device__ inline void inv_scale_tile(const double *Dinv, double *X, int Q, int ib, int jb, F64Stage &st) {
+  F64Acc acc[2][2];
+  acc_zero(acc);
+  double *C = X + (size_t)ib * NB * Q + (size_t)jb * NB;
+  block_product(acc, Dinv + (size_t)ib * NB * NB, NB, 1, C, Q, 1, NB, st);
+  acc_store(acc, [&](int r, int c, double v) { C[(size_t)r * Q + c] = -v; });
+}
+
+// X_ii = L_ii^{-1}
+__device__ inline void inv_diag_copy(const double *Dinv, double *X, int Q, int b) {
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x)
+    X[(size_t)(b * NB + e / NB) * Q + b * NB + e % NB] = Dinv[(size_t)b * NB * NB + e];
+}
+
+// K^{-1}_I,J = sum_{k >= I} X_k,I^T X_k,J for I >= J, written and mirrored as T
+// (entries of index >= q skipped).
+template <typename T>
+__device__ inline void kinv_tile(const double *X, int Q, int nbt, int q, T *Kinv, int ldk, int I, int J,
+                                 F64Stage &st) {
+  F64Acc acc[2][2];
+  acc_zero(acc);
+  const double *pa = X + (size_t)I * NB * Q + (size_t)I * NB;
+  const double *pb = X + (size_t)I * NB * Q + (size_t)J * NB;
+  block_product(acc, pa, 1, Q, pb, Q, 1, (nbt - I) * NB, st);
+  acc_store(acc, [&](int r, int c, double v) {
+    const int gi = I * NB + r, gj = J * NB + c;
+    if (gi < q && gj < q) {
+      Kinv[(size_t)gi * ldk + gj] = (T)v;
+      Kinv[(size_t)gj * ldk + gi] = (T)v;
+    }
+  });
+}
+
+}  // namespace pogs

@@ -10,6 +10,7 @@
 
 #include "internal.hpp"
 #include "prox.hpp"
+#include "hostutil.hpp"
 
 using namespace pogs;
 
@@ -43,52 +44,6 @@ struct DevArena {
     for (void *p : ptrs) (void)hipFree(p);
   }
 };
-
-bool finite(double v) { return std::isfinite(v); }
-
-// Expand a pogs_fn into per-element float64 arrays (host); validate it.
-struct HostFn {
-  std::vector<uint8_t> h;
-  std::vector<double> a, b, c, d, e;
-};
-
-int expand_fn(const pogs_fn *fn, int64_t len, HostFn *out) {
-  if (!fn || fn->len != len || !fn->h || (fn->stride != 0 && fn->stride != 1)) return POGS_EINVAL;
-  out->h.resize(len);
-  out->a.resize(len);
-  out->b.resize(len);
-  out->c.resize(len);
-  out->d.resize(len);
-  out->e.resize(len);
-  for (int64_t i = 0; i < len; ++i) {
-    const int64_t k = fn->stride ? i : 0;
-    const uint8_t h = fn->h[k];
-    const double a = fn->a ? fn->a[k] : 1.0;
-    const double b = fn->b ? fn->b[k] : 0.0;
-    const double c = fn->c ? fn->c[k] : 1.0;
-    const double d = fn->d ? fn->d[k] : 0.0;
-    const double e = fn->e ? fn->e[k] : 0.0;
-    if (h >= kNumH) return POGS_EINVAL;
-    if (!finite(a) || !finite(b) || !finite(c) || !finite(d) || !finite(e)) return POGS_EINVAL;
-    if (c < 0.0 || e < 0.0) return POGS_EINVAL;   // convexity (Section 5: c, e >= 0)
-    if (c > 0.0 && a == 0.0) return POGS_EINVAL;  // h term would be constant
-    out->h[i] = h;
-    out->a[i] = a;
-    out->b[i] = b;
-    out->c[i] = c;
-    out->d[i] = d;
-    out->e[i] = e;
-  }
-  return POGS_OK;
-}
-
-int check_params(const pogs_params &p) {
-  if (!(p.eps_abs >= 0.0) || !(p.eps_rel >= 0.0) || p.max_iter <= 0 || !(p.rho0 > 0.0) || !(p.alpha > 0.0) ||
-      !(p.alpha < 2.0) || !(p.delta >= 1.0) || !(p.tau > 0.0) || !(p.tau <= 1.0) || p.equil_iters < 0 ||
-      p.chunk_iters < 0 || !finite(p.eps_abs) || !finite(p.eps_rel) || !finite(p.rho0) || !finite(p.delta))
-    return POGS_EINVAL;
-  return POGS_OK;
-}
 
 }  // namespace
 

@@ -11,7 +11,7 @@
 //                 K^{-1} = L^{-T} L^{-1}, stored in T for the iterations.
 #include "gemv.hpp"
 #include "internal.hpp"
-#include "mfma.hpp"
+#include "factor.hpp"
 
 namespace pogs {
 
@@ -202,100 +202,19 @@ int run_equilibrate(T *A, int m, int n, int ld, int iters, double eps_cmp, doubl
 // ---------------------------------------------------------------------------
 // Gram matrix on MFMA
 // ---------------------------------------------------------------------------
-// Tile pair t of the lower triangle (ti >= tj).
-__device__ inline void tri_index(int t, int *ti, int *tj) {
-  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  while (i * (i + 1) / 2 > t) --i;
-  *ti = i;
-  *tj = t - i * (i + 1) / 2;
-}
-
-// G tile (ti, tj) partial over the K range of split blockIdx.y.
-// TALL: G = A^T A, k runs over rows; else G = A A^T, k runs over columns.
-// float: 128 x 128 tile, 4 waves in 2 x 2, each 64 x 64 = 4 x 4 MFMA 16x16x4 f32.
+// G tile (ti, tj) partial over the K range of split blockIdx.y (f32 MFMA).
 template <bool TALL>
 __global__ __launch_bounds__(256) void gram_f32_kernel(const float *__restrict__ A, int m, int n, int ld,
                                                        int kchunk, int ntp, float *__restrict__ part) {
-  constexpr int TB = 128, KC = 16, LS = TB + 4;
-  __shared__ float sa[KC][LS];
-  __shared__ float sb[KC][LS];
+  __shared__ GramStage st;
   int ti, tj;
   tri_index(blockIdx.x, &ti, &tj);
   const int kdim = TALL ? m : n;
-  const int qdim = TALL ? n : m;
   const int k0 = blockIdx.y * kchunk;
   const int k1 = min(kdim, k0 + kchunk);
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wi = w >> 1, wj = w & 1;
-  const bool diag = ti == tj;
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  f4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-
-  for (int kk0 = k0; kk0 < k1; kk0 += KC) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int f = t + h * 256;  // float4 index in the 16 x 128 stage
-      if (TALL) {
-        const int k = f >> 5, c = (f & 31) * 4;
-        const int row = kk0 + k;
-        f4 va = f4{0.f, 0.f, 0.f, 0.f}, vb = f4{0.f, 0.f, 0.f, 0.f};
-        if (row < k1) {
-          const int ca = ti * TB + c, cb = tj * TB + c;
-          if (ca < n) va = *reinterpret_cast<const f4 *>(A + (size_t)row * ld + ca);
-          if (!diag && cb < n) vb = *reinterpret_cast<const f4 *>(A + (size_t)row * ld + cb);
-        }
-        *reinterpret_cast<f4 *>(&sa[k][c]) = va;
-        if (!diag) *reinterpret_cast<f4 *>(&sb[k][c]) = vb;
-      } else {
-        const int r = f & 127, kq = (f >> 7) * 4;
-        const int kc = kk0 + kq;  // kc + 3 < ld always (kk0 % 16 == 0, ld % 64 == 0, kk0 < n <= ld)
-        const int ra = ti * TB + r, rb = tj * TB + r;
-        f4 va = f4{0.f, 0.f, 0.f, 0.f}, vb = f4{0.f, 0.f, 0.f, 0.f};
-        if (ra < m) va = *reinterpret_cast<const f4 *>(A + (size_t)ra * ld + kc);
-        if (!diag && rb < m) vb = *reinterpret_cast<const f4 *>(A + (size_t)rb * ld + kc);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const bool ok = kc + u < k1;
-          sa[kq + u][r] = ok ? va[u] : 0.f;
-          if (!diag) sb[kq + u][r] = ok ? vb[u] : 0.f;
-        }
-      }
-    }
-    __syncthreads();
-    const float(*pb)[LS] = diag ? sa : sb;
-#pragma unroll
-    for (int k4 = 0; k4 < KC; k4 += 4) {
-      float av[4], bv[4];
-      const int kr = k4 + (lane >> 4), cl = lane & 15;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        av[b] = sa[kr][wi * 64 + b * 16 + cl];
-        bv[b] = pb[kr][wj * 64 + b * 16 + cl];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  float *out = part + ((size_t)blockIdx.y * ntp + blockIdx.x) * TB * TB;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = wi * 64 + i * 16 + 4 * (lane >> 4) + r;
-        const int col = wj * 64 + j * 16 + (lane & 15);
-        out[row * TB + col] = acc[i][j][r];
-      }
-  (void)qdim;
+  float *out = part + ((size_t)blockIdx.y * ntp + blockIdx.x) * kGramTB * kGramTB;
+  gram_tile_f32<TALL>(A, m, n, ld, ti, tj, k0, k1, st,
+                      [&](int r, int c, float v) { out[r * kGramTB + c] = v; });
 }
 
 // float64 matrices: the same scheme with 64 x 64 tiles on f64 MFMA.
@@ -411,173 +330,41 @@ int run_gram(const T *A, int m, int n, int ld, double *K, int Q, float *ws32, do
 // ---------------------------------------------------------------------------
 // Blocked Cholesky and explicit inverse (float64, 64 x 64 blocks)
 // ---------------------------------------------------------------------------
-constexpr int NB = 64;
-
-// Factor the diagonal block kb in LDS (unblocked right-looking Cholesky) and
-// invert the triangular factor by column substitution.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double *K, int Q, int kb, double *Dinv, unsigned *bad) {
-  __shared__ double L[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  const int t = threadIdx.x;
-  double *blk = K + (size_t)kb * NB * Q + (size_t)kb * NB;
-  for (int e = t; e < NB * NB; e += 256) L[e / NB][e % NB] = blk[(size_t)(e / NB) * Q + e % NB];
-  __syncthreads();
-  for (int j = 0; j < NB; ++j) {
-    if (t == 0) {
-      double v = L[j][j];
-      if (!(v > 0.0) || !isfinite(v)) {
-        atomicAdd(bad, 1u);
-        v = 1.0;
-      }
-      L[j][j] = sqrt(v);
-    }
-    __syncthreads();
-    const double djj = L[j][j];
-    for (int r = j + 1 + t; r < NB; r += 256) L[r][j] /= djj;
-    __syncthreads();
-    const int nr = NB - 1 - j;
-    for (int e = t; e < nr * nr; e += 256) {
-      const int r = j + 1 + e / nr, c = j + 1 + e % nr;
-      if (c <= r) L[r][c] -= L[r][j] * L[c][j];
-    }
-    __syncthreads();
-  }
-  if (t < NB) {
-    const int c = t;
-    for (int r = 0; r < c; ++r) X[r][c] = 0.0;
-    X[c][c] = 1.0 / L[c][c];
-    for (int r = c + 1; r < NB; ++r) {
-      double s = 0.0;
-      for (int k = c; k < r; ++k) s += L[r][k] * X[k][c];
-      X[r][c] = -s / L[r][r];
-    }
-  }
-  __syncthreads();
-  double *dv = Dinv + (size_t)kb * NB * NB;
-  for (int e = t; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    blk[(size_t)r * Q + c] = c <= r ? L[r][c] : 0.0;
-    dv[e] = X[r][c];
-  }
+  __shared__ CholLds s;
+  potrf_diag(K, Q, kb, Dinv, bad, s);
 }
 
-// Generic 64 x 64 float64 block product on MFMA:
-//   C = beta C + alpha sum_k opA(i, k) opB(k, j), k in [0, K)
-// with opA(i, k) = pa[i * sai + k * sak] and opB(k, j) = pb[k * sbk + j * sbj].
-__device__ void block_product(F64Acc acc[2][2], const double *pa, int64_t sai, int64_t sak, const double *pb,
-                              int64_t sbk, int64_t sbj, int K, double (*sa)[NB + 2], double (*sb)[NB + 2]) {
-  const int t = threadIdx.x, w = t >> 6;
-  const int wi = w >> 1, wj = w & 1;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int f = t; f < 16 * NB; f += 256) {
-      const int k = f / NB, i = f % NB;
-      sa[k][i] = pa[(int64_t)i * sai + (int64_t)(k0 + k) * sak];
-      sb[k][i] = pb[(int64_t)(k0 + k) * sbk + (int64_t)i * sbj];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k4 = 0; k4 < 16; k4 += 4) f64_tile_step(acc, sa, sb, k4, wi * 32, wj * 32);
-    __syncthreads();
-  }
-}
-
-// L_ik = K_ik L_kk^{-T} for block rows i > kb.
 __global__ __launch_bounds__(256) void trsm_panel_kernel(double *K, int Q, int kb, const double *Dinv) {
-  __shared__ double sa[16][NB + 2];
-  __shared__ double sb[16][NB + 2];
-  const int ib = kb + 1 + blockIdx.x;
-  double *blk = K + (size_t)ib * NB * Q + (size_t)kb * NB;
-  const double *dv = Dinv + (size_t)kb * NB * NB;
-  F64Acc acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64acc_zero();
-  // out(r, c) = sum_t K_ik(r, t) Dinv(c, t)
-  block_product(acc, blk, Q, 1, dv, 1, NB, NB, sa, sb);
-  const int w = threadIdx.x >> 6;
-  f64_tile_store(acc, (w >> 1) * 32, (w & 1) * 32, [&](int r, int c, double v) { blk[(size_t)r * Q + c] = v; });
+  __shared__ F64Stage st;
+  trsm_tile(K, Q, kb, kb + 1 + blockIdx.x, Dinv, st);
 }
 
-// K_IJ -= L_Ik L_Jk^T for kb < J <= I.
 __global__ __launch_bounds__(256) void syrk_update_kernel(double *K, int Q, int kb) {
-  __shared__ double sa[16][NB + 2];
-  __shared__ double sb[16][NB + 2];
+  __shared__ F64Stage st;
   int I, J;
   tri_index(blockIdx.x, &I, &J);
-  I += kb + 1;
-  J += kb + 1;
-  const double *LI = K + (size_t)I * NB * Q + (size_t)kb * NB;
-  const double *LJ = K + (size_t)J * NB * Q + (size_t)kb * NB;
-  double *C = K + (size_t)I * NB * Q + (size_t)J * NB;
-  F64Acc acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64acc_zero();
-  block_product(acc, LI, Q, 1, LJ, 1, Q, NB, sa, sb);
-  __syncthreads();
-  const int w = threadIdx.x >> 6;
-  f64_tile_store(acc, (w >> 1) * 32, (w & 1) * 32,
-                 [&](int r, int c, double v) { C[(size_t)r * Q + c] -= v; });
+  syrk_tile(K, Q, kb, I + kb + 1, J + kb + 1, st);
 }
 
-// X_ii = L_ii^{-1}
-__global__ void inv_diag_copy_kernel(const double *Dinv, double *X, int Q, int nbt) {
-  const int b = blockIdx.x;
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x)
-    X[(size_t)(b * NB + e / NB) * Q + b * NB + e % NB] = Dinv[(size_t)b * NB * NB + e];
-  (void)nbt;
-}
+__global__ void inv_diag_copy_kernel(const double *Dinv, double *X, int Q) { inv_diag_copy(Dinv, X, Q, blockIdx.x); }
 
-// Step i of L^{-1} by blocks: X_ij <- sum_{k=j}^{i-1} L_ik X_kj  (j < i)
 __global__ __launch_bounds__(256) void inv_accum_kernel(const double *K, double *X, int Q, int ib) {
-  __shared__ double sa[16][NB + 2];
-  __shared__ double sb[16][NB + 2];
-  const int jb = blockIdx.x;
-  F64Acc acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64acc_zero();
-  const double *pa = K + (size_t)ib * NB * Q + (size_t)jb * NB;  // L_i,j.. (row ib, cols from jb)
-  const double *pb = X + (size_t)jb * NB * Q + (size_t)jb * NB;  // X_j..,j
-  block_product(acc, pa, Q, 1, pb, Q, 1, (ib - jb) * NB, sa, sb);
-  double *C = X + (size_t)ib * NB * Q + (size_t)jb * NB;
-  const int w = threadIdx.x >> 6;
-  f64_tile_store(acc, (w >> 1) * 32, (w & 1) * 32, [&](int r, int c, double v) { C[(size_t)r * Q + c] = v; });
+  __shared__ F64Stage st;
+  inv_accum_tile(K, X, Q, ib, blockIdx.x, st);
 }
 
-// X_ij <- -L_ii^{-1} X_ij (in place, j < i)
 __global__ __launch_bounds__(256) void inv_scale_kernel(const double *Dinv, double *X, int Q, int ib) {
-  __shared__ double sa[16][NB + 2];
-  __shared__ double sb[16][NB + 2];
-  const int jb = blockIdx.x;
-  F64Acc acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64acc_zero();
-  double *C = X + (size_t)ib * NB * Q + (size_t)jb * NB;
-  block_product(acc, Dinv + (size_t)ib * NB * NB, NB, 1, C, Q, 1, NB, sa, sb);
-  __syncthreads();
-  const int w = threadIdx.x >> 6;
-  f64_tile_store(acc, (w >> 1) * 32, (w & 1) * 32, [&](int r, int c, double v) { C[(size_t)r * Q + c] = -v; });
+  __shared__ F64Stage st;
+  inv_scale_tile(Dinv, X, Q, ib, blockIdx.x, st);
 }
 
-// K^{-1}_IJ = sum_{k >= I} X_kI^T X_kJ for I >= J; written (and mirrored) as T.
 template <typename T>
 __global__ __launch_bounds__(256) void kinv_kernel(const double *X, int Q, int nbt, int q, T *Kinv, int ldk) {
-  __shared__ double sa[16][NB + 2];
-  __shared__ double sb[16][NB + 2];
+  __shared__ F64Stage st;
   int I, J;
   tri_index(blockIdx.x, &I, &J);
-  F64Acc acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64acc_zero();
-  const double *pa = X + (size_t)I * NB * Q + (size_t)I * NB;  // (i, k) -> X[(I*NB + k) * Q + I*NB + i]
-  const double *pb = X + (size_t)I * NB * Q + (size_t)J * NB;  // (k, j) -> X[(I*NB + k) * Q + J*NB + j]
-  block_product(acc, pa, 1, Q, pb, Q, 1, (nbt - I) * NB, sa, sb);
-  const int w = threadIdx.x >> 6;
-  f64_tile_store(acc, (w >> 1) * 32, (w & 1) * 32, [&](int r, int c, double v) {
-    const int gi = I * NB + r, gj = J * NB + c;
-    if (gi < q && gj < q) {
-      Kinv[(size_t)gi * ldk + gj] = (T)v;
-      Kinv[(size_t)gj * ldk + gi] = (T)v;
-    }
-  });
+  kinv_tile<T>(X, Q, nbt, q, Kinv, ldk, I, J, st);
 }
 
 template <typename T>
@@ -593,7 +380,7 @@ int run_factor_inverse(double *K, int q, int Q, T *Kinv, int ldk, double *ws, un
       hipLaunchKernelGGL(syrk_update_kernel, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, K, Q, kb);
     }
   }
-  hipLaunchKernelGGL(inv_diag_copy_kernel, dim3(nbt), dim3(256), 0, s, (const double *)Dinv, X, Q, nbt);
+  hipLaunchKernelGGL(inv_diag_copy_kernel, dim3(nbt), dim3(256), 0, s, (const double *)Dinv, X, Q);
   for (int ib = 1; ib < nbt; ++ib) {
     hipLaunchKernelGGL(inv_accum_kernel, dim3(ib), dim3(256), 0, s, (const double *)K, X, Q, ib);
     hipLaunchKernelGGL(inv_scale_kernel, dim3(ib), dim3(256), 0, s, (const double *)Dinv, X, Q, ib);
