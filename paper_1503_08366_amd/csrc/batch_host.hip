@@ -630,8 +630,3 @@ extern "C" int pogs_batch_destroy(pogs_batch *b) {
   delete b;
   return POGS_OK;
 }
-
-extern "C" int pogs_solve_path(pogs_ctx *, int32_t, const pogs_fn *, const pogs_fn *, const pogs_params *,
-                               pogs_result *) {
-  return POGS_EUNSUPPORTED;
-}

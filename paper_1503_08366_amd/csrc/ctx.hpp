@@ -1,0 +1,129 @@
+// The context object behind pogs_ctx (shared by the C ABI translation units).
+#pragma once
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace pogs {
+
+// Device allocations owned by a context, freed together.
+struct DevArena {
+  std::vector<void *> ptrs;
+  int alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      *p = nullptr;
+      return POGS_ENOMEM;
+    }
+    ptrs.push_back(*p);
+    return POGS_OK;
+  }
+  void release(void *p) {
+    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    if (it != ptrs.end()) {
+      (void)hipFree(*it);
+      ptrs.erase(it);
+    }
+  }
+  ~DevArena() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+};
+
+
+}  // namespace pogs
+
+using namespace pogs;
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct pogs_ctx {
+  int64_t m = 0, n = 0;
+  int ld = 0, q = 0, Q = 0, ldk = 0;
+  pogs_dtype dt = POGS_F32;
+  pogs_params params{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevArena arena;
+  void *A = nullptr;     // scaled matrix, T
+  void *Kinv = nullptr;  // (I + G)^{-1}, T
+  double *D = nullptr, *E = nullptr;
+  // iteration state (T): x y xt yt xh yh mu nu cx dy rhs, outputs xo yo muo nuo
+  void *vec = nullptr;
+  // scaled functions (T) and original functions (float64)
+  uint8_t *fh = nullptr, *gh = nullptr, *fh0 = nullptr, *gh0 = nullptr;
+  void *fs = nullptr, *gs = nullptr;     // 5 arrays each, T
+  double *f0 = nullptr, *g0 = nullptr;   // 5 arrays each, float64
+  double *part = nullptr, *slots = nullptr;
+  unsigned *counters = nullptr;
+  Ctrl *ctrl = nullptr;
+  Ctrl *ctrl_host = nullptr;   // pinned
+  double *obj_host = nullptr;  // pinned
+  double *obj_dev = nullptr;
+  int splits = 0, rps = 0, ncolp = 0;
+  int nbx = 0, nby = 0, n_pri = 0, n_dual = 0;
+  double ms_setup = 0.0;
+  hipGraphExec_t graph = nullptr;
+  int graph_chunk = 0;
+  bool solved = false;  // functions uploaded by a previous solve
+
+  size_t esz() const { return dt == POGS_F32 ? 4 : 8; }
+  template <typename T> T *vecp(int idx) const {
+    // vectors 0..3: x, y, xt, yt; 4..7: xh, yh, mu, nu; 8: cx, 9: dy, 10: rhs; 11..14: outputs
+    static const int kind[15] = {0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 2, 0, 1, 0, 1};  // 0: n, 1: m, 2: q
+    size_t off = 0;
+    const size_t L[3] = {(size_t)round_up(n, 64), (size_t)round_up(m, 64), (size_t)round_up(q, 64)};
+    for (int i = 0; i < idx; ++i) off += L[kind[i]];
+    return reinterpret_cast<T *>(vec) + off;
+  }
+  size_t vec_elems() const {  // the 15 vectors of vecp: 7 of length n, 7 of m, 1 of q
+    return 7 * (size_t)round_up(n, 64) + 7 * (size_t)round_up(m, 64) + (size_t)round_up(q, 64);
+  }
+  template <typename T> IterArgs<T> iter_args() const {
+    IterArgs<T> p{};
+    p.m = (int)m;
+    p.n = (int)n;
+    p.ld = ld;
+    p.q = q;
+    p.ldk = ldk;
+    p.A = (const T *)A;
+    p.Kinv = (const T *)Kinv;
+    const T *fsp = (const T *)fs;
+    const T *gsp = (const T *)gs;
+    p.f = FnDev<T>{fh, fsp, fsp + m, fsp + 2 * m, fsp + 3 * m, fsp + 4 * m};
+    p.g = FnDev<T>{gh, gsp, gsp + n, gsp + 2 * n, gsp + 3 * n, gsp + 4 * n};
+    p.x = vecp<T>(0);
+    p.y = vecp<T>(1);
+    p.xt = vecp<T>(2);
+    p.yt = vecp<T>(3);
+    p.xh = vecp<T>(4);
+    p.yh = vecp<T>(5);
+    p.mu = vecp<T>(6);
+    p.nu = vecp<T>(7);
+    p.cx = vecp<T>(8);
+    p.dy = vecp<T>(9);
+    p.rhs = vecp<T>(10);
+    p.part = part;
+    p.nbx = nbx;
+    p.nby = nby;
+    p.s_mu = slots;
+    p.s_yh = slots + nbx;
+    p.s_pri = slots + nbx + nby;
+    p.s_dual = slots + nbx + nby + n_pri;
+    p.n_pri = n_pri;
+    p.n_dual = n_dual;
+    p.ctrl = ctrl;
+    return p;
+  }
+  ~pogs_ctx() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (ctrl_host) (void)hipHostFree(ctrl_host);
+    if (obj_host) (void)hipHostFree(obj_host);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+

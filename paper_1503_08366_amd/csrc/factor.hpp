@@ -116,6 +116,78 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
         out(wi * 64 + i * 16 + 4 * (lane >> 4) + r, wj * 64 + j * 16 + (lane & 15), acc[i][j][r]);
 }
 
+// General f32 MFMA tile product: tile (i0.., j0..) of sum_{k in [k0, k1)} opA(i, k) B(k, j)
+// with opA(i, k) = A[k * lda + i] (A_T: A stored K x M) or A[i * lda + k]
+// (A stored M x K), B stored K x N row-major (ldb % 4 == 0).  Rows >= M,
+// columns >= N and k >= k1 read as zero; lda and ldb are multiples of 4 and
+// the rows of A and B are readable up to the next multiple of 16 elements
+// past M (A_T), k1 (not A_T) and N.  out(row, col, value) gets tile-local
+// indices.  128 x 128 tile, 4 waves in 2 x 2, f32 MFMA 16x16x4.
+template <bool A_T, class Out>
+__device__ void gemm_tile_f32(const float *__restrict__ A, int lda, int M, const float *__restrict__ B, int ldb,
+                              int N, int i0, int j0, int k0, int k1, GramStage &st, Out out) {
+  constexpr int TB = kGramTB, KC = 16;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  GramAcc acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = GramAcc{0.f, 0.f, 0.f, 0.f};
+  for (int kk0 = k0; kk0 < k1; kk0 += KC) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int f = t + h * 256;  // float4 index in a 16 x 128 stage
+      // B: rows kk0 + k, columns j0 + c .. c + 3
+      {
+        const int k = f >> 5, c = (f & 31) * 4;
+        const int row = kk0 + k, col = j0 + c;
+        f4 vb = f4{0.f, 0.f, 0.f, 0.f};
+        if (row < k1 && col < N) vb = *reinterpret_cast<const f4 *>(B + (size_t)row * ldb + col);
+        *reinterpret_cast<f4 *>(&st.b[k][c]) = vb;
+      }
+      if (A_T) {
+        const int k = f >> 5, c = (f & 31) * 4;
+        const int row = kk0 + k, col = i0 + c;
+        f4 va = f4{0.f, 0.f, 0.f, 0.f};
+        if (row < k1 && col < M) va = *reinterpret_cast<const f4 *>(A + (size_t)row * lda + col);
+        *reinterpret_cast<f4 *>(&st.a[k][c]) = va;
+      } else {
+        const int r = f & 127, kq = (f >> 7) * 4;
+        const int row = i0 + r, kc = kk0 + kq;
+        f4 va = f4{0.f, 0.f, 0.f, 0.f};
+        if (row < M && kc < k1) va = *reinterpret_cast<const f4 *>(A + (size_t)row * lda + kc);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) st.a[kq + u][r] = kc + u < k1 ? va[u] : 0.f;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      float av[4], bv[4];
+      const int kr = k4 + (lane >> 4), cl = lane & 15;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        av[b] = st.a[kr][wi * 64 + b * 16 + cl];
+        bv[b] = st.b[kr][wj * 64 + b * 16 + cl];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out(wi * 64 + i * 16 + 4 * (lane >> 4) + r, wj * 64 + j * 16 + (lane & 15), acc[i][j][r]);
+}
+
 // acc += sum_{k < K} opA(i, k) opB(k, j) for a 64 x 64 float64 tile, with
 // opA(i, k) = pa[i * sai + k * sak], opB(k, j) = pb[k * sbk + j * sbj]
 // (K a multiple of 16).  Ends with a barrier: the stages may be reused and

@@ -2,9 +2,12 @@
 // 64-element-aligned leading dimension (entries past column n are zero).
 //
 // gemv_t: column sums  out_r[j] = sum_i op(A_ij) v_r[i]   (A^T v), split over
-//         row ranges; each split writes float64 partials, the last split of a
-//         column tile reduces them in split order (deterministic) and hands
-//         each column to an epilogue.
+//         row ranges; each split writes float64 partials.  A second, small
+//         kernel (gemv_t_finish) sums the partials in split order
+//         (deterministic) and hands each column to an epilogue.  The split
+//         is a kernel boundary rather than a "last workgroup" handshake: on
+//         gfx950 a device-scope fence writes back and invalidates the whole
+//         L2, which costs far more per workgroup than one extra launch.
 // gemv_n: row dots     out_r[i] = sum_j op(A_ij) v_r[j]   (A v), LPR lanes per
 //         row, the vectors staged in LDS, float64 accumulation.
 //
@@ -26,24 +29,18 @@ template <bool SQUARE> __device__ inline double elem_op(double a) {
 // gemv_t
 // ---------------------------------------------------------------------------
 // Epilogue interface (Epi):
-//   bool skip() const                      -> exit at once (solver stopped)
+//   bool skip() const                          -> exit at once (solver stopped)
 //   double column(int j, double s0, double s1) -> per-column finish, j < n;
-//                                            returns a value summed per tile
-//   void tile_done(int tile, double sum)   -> called by thread 0 of the tile's
-//                                            reducing workgroup
-//   static constexpr bool kFinal           -> call final() in the last tile
-//   void final(double *lds)                -> whole workgroup, after all tiles
+//                                                returns a value summed per tile
+//   void tile_done(int tile, double sum)       -> thread 0 of the tile's workgroup
 template <typename TA, typename TV, int NRHS, bool SQUARE, class Epi>
 __global__ __launch_bounds__(kBlock) void gemv_t_kernel(
     const TA *__restrict__ A, int m, int n, int ld, const TV *__restrict__ v0,
-    const TV *__restrict__ v1, int rows_per_split, double *__restrict__ part, int ncolp,
-    unsigned *tile_cnt, unsigned *fin_cnt, Epi epi) {
+    const TV *__restrict__ v1, int rows_per_split, double *__restrict__ part, int ncolp, Epi epi) {
   using V = typename Vec16<TA>::type;
   constexpr int VN = Vec16<TA>::N;
   constexpr int TILE = kWave * VN;
   __shared__ double red[4][NRHS][TILE];
-  __shared__ double bs[kBlock / kWave];
-  __shared__ int flag;
   if (epi.skip()) return;
 
   const int lane = threadIdx.x & (kWave - 1);
@@ -63,17 +60,17 @@ __global__ __launch_bounds__(kBlock) void gemv_t_kernel(
   if (col < n) {
     const TA *base = A + col;
     int i = r0 + w;
-    for (; i + 12 < r1; i += 16) {
-      V a[4];
-      double s[4][NRHS];
+    for (; i + 28 < r1; i += 32) {
+      V a[8];
+      double s[8][NRHS];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         a[u] = *reinterpret_cast<const V *>(base + (size_t)(i + 4 * u) * ld);
         s[u][0] = (double)v0[i + 4 * u];
         if constexpr (NRHS > 1) s[u][1] = (double)v1[i + 4 * u];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int c = 0; c < VN; ++c) {
           const double e = elem_op<SQUARE>((double)a[u][c]);
@@ -108,23 +105,39 @@ __global__ __launch_bounds__(kBlock) void gemv_t_kernel(
       part[(size_t)(split * NRHS + r) * ncolp + cg] = v;
     }
   }
-  if (!arrive_last(&tile_cnt[tile], gridDim.y, &flag)) return;
+}
 
-  // Last split of this tile: reduce the partials in split order.
-  double contrib = 0.0;
-  if (threadIdx.x < TILE) {
-    const int cg = tile * TILE + threadIdx.x;
-    double s[2] = {0.0, 0.0};
-    for (int sp = 0; sp < (int)gridDim.y; ++sp)
+// Sum the split partials of 64 columns (block blockIdx.x): each of the four
+// waves sums every fourth split, then the four sums are added in wave order
+// (a fixed order, so results are deterministic); each column is finished by
+// the epilogue and the block's sum goes to tile_done(blockIdx.x, .).
+template <int NRHS, class Epi>
+__global__ __launch_bounds__(kBlock) void gemv_t_finish_kernel(int n, int splits, const double *__restrict__ part,
+                                                                int ncolp, Epi epi) {
+  __shared__ double red[4][2][kFinishCols];
+  __shared__ double bs[kBlock / kWave];
+  if (epi.skip()) return;
+  const int c = threadIdx.x & (kFinishCols - 1);
+  const int g = threadIdx.x >> 6;
+  const int cg = blockIdx.x * kFinishCols + c;
+  double s[2] = {0.0, 0.0};
+  if (cg < ncolp) {
+#pragma unroll 4
+    for (int sp = g; sp < splits; sp += 4)
 #pragma unroll
-      for (int r = 0; r < NRHS; ++r) s[r] += load_agent(part + (size_t)(sp * NRHS + r) * ncolp + cg);
-    if (cg < n) contrib = epi.column(cg, s[0], s[1]);
+      for (int r = 0; r < NRHS; ++r) s[r] += part[(size_t)(sp * NRHS + r) * ncolp + cg];
+  }
+  red[g][0][c] = s[0];
+  red[g][1][c] = s[1];
+  __syncthreads();
+  double contrib = 0.0;
+  if (g == 0 && cg < n) {
+    const double t0 = (red[0][0][c] + red[1][0][c]) + (red[2][0][c] + red[3][0][c]);
+    const double t1 = (red[0][1][c] + red[1][1][c]) + (red[2][1][c] + red[3][1][c]);
+    contrib = epi.column(cg, t0, t1);
   }
   const double tsum = block_sum(contrib, bs);
-  if (threadIdx.x == 0) epi.tile_done(tile, tsum);
-  if constexpr (Epi::kFinal) {
-    if (arrive_last(fin_cnt, gridDim.x, &flag)) epi.final(bs);
-  }
+  if (threadIdx.x == 0) epi.tile_done(blockIdx.x, tsum);
 }
 
 // ---------------------------------------------------------------------------
@@ -135,13 +148,12 @@ __global__ __launch_bounds__(kBlock) void gemv_t_kernel(
 //   double row(int i, double s0, double s1)  -> per-row finish (i < m); value
 //                                             summed per workgroup
 //   void block_done(int block, double sum)   -> thread 0 of each workgroup
-//   static constexpr bool kFinal; void final(double *lds)
 template <typename TV> struct GemvNChunk { static constexpr int value = 8192 / sizeof(TV) * 2; };
 
 template <typename TA, typename TV, int NRHS, bool SQUARE, int LPR, int RPT, class Epi>
 __global__ __launch_bounds__(kBlock) void gemv_n_kernel(
     const TA *__restrict__ A, int m, int n, int ld, const TV *__restrict__ v0,
-    const TV *__restrict__ v1, unsigned *cnt, Epi epi) {
+    const TV *__restrict__ v1, Epi epi) {
   using V = typename Vec16<TA>::type;
   constexpr int VN = Vec16<TA>::N;
   constexpr int CH = GemvNChunk<TV>::value;  // vector elements staged per chunk
@@ -149,7 +161,6 @@ __global__ __launch_bounds__(kBlock) void gemv_n_kernel(
   constexpr int ROWS = (kBlock / kWave) * GPW * RPT;
   __shared__ TV vs[NRHS][CH];
   __shared__ double bs[kBlock / kWave];
-  __shared__ int flag;
   if (epi.skip()) return;
 
   const int lane = threadIdx.x & (kWave - 1);
@@ -215,9 +226,6 @@ __global__ __launch_bounds__(kBlock) void gemv_n_kernel(
   }
   const double bsum = block_sum(contrib, bs);
   if (threadIdx.x == 0) epi.block_done(blockIdx.x, bsum);
-  if constexpr (Epi::kFinal) {
-    if (arrive_last(cnt, gridDim.x, &flag)) epi.final(bs);
-  }
 }
 
 template <int LPR, int RPT> constexpr int gemv_n_rows_per_block() {

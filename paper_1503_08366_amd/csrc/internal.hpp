@@ -41,7 +41,6 @@ template <typename T> struct IterArgs {
   T *cx, *dy;            // projection inputs c = x_r + x~, d = y_r + y~
   T *rhs;                // right-hand side of the reduced system (length q)
   double *part;          // gemv_t split partials
-  unsigned *tile_cnt;    // gemv_t tile counters
   double *s_mu, *s_yh;   // prox-block partial sums of mu_h^2, y_h^2
   double *s_pri, *s_dual;// partial sums of the residuals
   int nbx, nby;          // prox blocks over x (n) and y (m)

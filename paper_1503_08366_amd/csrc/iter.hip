@@ -1,6 +1,7 @@
 // One ADMM iteration of the single-problem pipeline on gfx950 (Algorithm 1 with
 // the Section 3.2 over-relaxation, Section 3.3 half-step duals, Section 3.4
-// residual stopping and Algorithm 3 adaptive rho), as four launches:
+// residual stopping and Algorithm 3 adaptive rho), as five steps (six
+// launches: the pass that sums columns of A finishes in a second small kernel):
 //
 //   1. prox      : x_h = prox_g^(x - x~), y_h = prox_f^(y - y~), mu_h, nu_h,
 //                  relaxed c = x_r + x~, d = y_r + y~, partial ||mu_h||^2, ||y_h||^2
@@ -10,8 +11,8 @@
 //                  m <  n: y = d + K^{-1} rhs, y~ = d - y
 //   4. pass 2    : m >= n: [y, t] = A [x, x_h] -> y~ = d - y, (t - y_h)^2
 //                  m <  n: [z, s] = A^T [y~, nu_h] -> x = c + z, x~ = c - x, (s + mu_h)^2
-//                  then the last workgroup sums every partial in a fixed order
-//                  and runs the stopping test and Algorithm 3.
+//   5. control   : one workgroup sums every partial in a fixed order and runs
+//                  the stopping test and Algorithm 3.
 //
 // The reduced update is the one of Section 3.5 with K = I + A^T A (m >= n) or
 // I + A A^T (m < n); K^{-1} is formed once from the float64 Cholesky factor.
@@ -76,6 +77,13 @@ __device__ void control_step(const IterArgs<T> &p, double *lds) {
   q->done = done;
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void control_kernel(IterArgs<T> p) {
+  __shared__ double bs[kBlock / kWave];
+  if (p.ctrl->done) return;
+  control_step(p, bs);
+}
+
 // ---------------------------------------------------------------------------
 // 1. prox step
 // ---------------------------------------------------------------------------
@@ -124,7 +132,6 @@ template <typename T> struct EpiBase {
 
 // m >= n, pass 1: [w, s] = A^T [d, nu_h]
 template <typename T> struct EpiTallPass1 : EpiBase<T> {
-  static constexpr bool kFinal = false;
   __device__ double column(int j, double w, double s) const {
     const IterArgs<T> &p = this->p;
     p.rhs[j] = (T)((double)p.cx[j] + w);
@@ -132,12 +139,10 @@ template <typename T> struct EpiTallPass1 : EpiBase<T> {
     return r * r;
   }
   __device__ void tile_done(int tile, double v) const { this->p.s_dual[tile] = v; }
-  __device__ void final(double *) const {}
 };
 
 // m >= n, solve: x = K^{-1} rhs
 template <typename T> struct EpiTallSolve : EpiBase<T> {
-  static constexpr bool kFinal = false;
   __device__ double row(int j, double x, double) const {
     const IterArgs<T> &p = this->p;
     const T xv = (T)x;
@@ -146,12 +151,10 @@ template <typename T> struct EpiTallSolve : EpiBase<T> {
     return 0.0;
   }
   __device__ void block_done(int, double) const {}
-  __device__ void final(double *) const {}
 };
 
 // m >= n, pass 2: [y, t] = A [x, x_h]; then the stopping test
 template <typename T> struct EpiTallPass2 : EpiBase<T> {
-  static constexpr bool kFinal = true;
   __device__ double row(int i, double y, double t) const {
     const IterArgs<T> &p = this->p;
     const T yv = (T)y;
@@ -161,12 +164,10 @@ template <typename T> struct EpiTallPass2 : EpiBase<T> {
     return r * r;
   }
   __device__ void block_done(int b, double v) const { this->p.s_pri[b] = v; }
-  __device__ void final(double *lds) const { control_step(this->p, lds); }
 };
 
 // m < n, pass 1: [u, t] = A [c, x_h]
 template <typename T> struct EpiWidePass1 : EpiBase<T> {
-  static constexpr bool kFinal = false;
   __device__ double row(int i, double u, double t) const {
     const IterArgs<T> &p = this->p;
     p.rhs[i] = (T)(u - (double)p.dy[i]);
@@ -174,12 +175,10 @@ template <typename T> struct EpiWidePass1 : EpiBase<T> {
     return r * r;
   }
   __device__ void block_done(int b, double v) const { this->p.s_pri[b] = v; }
-  __device__ void final(double *) const {}
 };
 
 // m < n, solve: y = d + K^{-1} rhs, y~ = d - y
 template <typename T> struct EpiWideSolve : EpiBase<T> {
-  static constexpr bool kFinal = false;
   __device__ double row(int i, double z, double) const {
     const IterArgs<T> &p = this->p;
     const T yv = (T)((double)p.dy[i] + z);
@@ -188,12 +187,10 @@ template <typename T> struct EpiWideSolve : EpiBase<T> {
     return 0.0;
   }
   __device__ void block_done(int, double) const {}
-  __device__ void final(double *) const {}
 };
 
 // m < n, pass 2: [z, s] = A^T [y~, nu_h]; x = c + z, x~ = c - x; then stop test
 template <typename T> struct EpiWidePass2 : EpiBase<T> {
-  static constexpr bool kFinal = true;
   __device__ double column(int j, double z, double s) const {
     const IterArgs<T> &p = this->p;
     const T xv = (T)((double)p.cx[j] + z);
@@ -203,7 +200,6 @@ template <typename T> struct EpiWidePass2 : EpiBase<T> {
     return r * r;
   }
   __device__ void tile_done(int tile, double v) const { this->p.s_dual[tile] = v; }
-  __device__ void final(double *lds) const { control_step(this->p, lds); }
 };
 
 // Standalone projection (no solver state): outputs go to caller buffers.
@@ -217,49 +213,37 @@ template <typename T> struct EpiNoSkip {
 };
 template <typename T> struct EpiProjTall1 : EpiNoSkip<T> {  // rhs = c + A^T d
   ProjArgs<T> a;
-  static constexpr bool kFinal = false;
   __device__ double column(int j, double w, double) const { a.rhs[j] = (T)((double)a.c[j] + w); return 0.0; }
   __device__ void tile_done(int, double) const {}
-  __device__ void final(double *) const {}
 };
 template <typename T> struct EpiProjTallSolve : EpiNoSkip<T> {  // x = K^{-1} rhs
   ProjArgs<T> a;
-  static constexpr bool kFinal = false;
   __device__ double row(int j, double x, double) const { a.x[j] = (T)x; return 0.0; }
   __device__ void block_done(int, double) const {}
-  __device__ void final(double *) const {}
 };
 template <typename T> struct EpiProjTall2 : EpiNoSkip<T> {  // y = A x
   ProjArgs<T> a;
-  static constexpr bool kFinal = false;
   __device__ double row(int i, double y, double) const { a.y[i] = (T)y; return 0.0; }
   __device__ void block_done(int, double) const {}
-  __device__ void final(double *) const {}
 };
 template <typename T> struct EpiProjWide1 : EpiNoSkip<T> {  // rhs = A c - d
   ProjArgs<T> a;
-  static constexpr bool kFinal = false;
   __device__ double row(int i, double u, double) const { a.rhs[i] = (T)(u - (double)a.d[i]); return 0.0; }
   __device__ void block_done(int, double) const {}
-  __device__ void final(double *) const {}
 };
 template <typename T> struct EpiProjWideSolve : EpiNoSkip<T> {  // y = d + K^{-1} rhs; rhs <- d - y
   ProjArgs<T> a;
-  static constexpr bool kFinal = false;
   __device__ double row(int i, double z, double) const {
     const T yv = (T)((double)a.d[i] + z);
     a.y[i] = yv;
     return 0.0;
   }
   __device__ void block_done(int, double) const {}
-  __device__ void final(double *) const {}
 };
 template <typename T> struct EpiProjWide2 : EpiNoSkip<T> {  // x = c + A^T (d - y)
   ProjArgs<T> a;
-  static constexpr bool kFinal = false;
   __device__ double column(int j, double z, double) const { a.x[j] = (T)((double)a.c[j] + z); return 0.0; }
   __device__ void tile_done(int, double) const {}
-  __device__ void final(double *) const {}
 };
 
 template <typename T>
@@ -287,18 +271,20 @@ void gemv_t_geometry(int m, int ncols, int elem_size, int *splits, int *rows_per
 
 template <typename T, typename TV, int NRHS, class Epi>
 static void gemv_t(const T *A, int m, int n, int ld, const TV *v0, const TV *v1, int splits, int rps,
-                   double *part, int ncolp, unsigned *tile_cnt, unsigned *fin_cnt, const Epi &epi,
-                   hipStream_t s) {
-  const int tiles = (int)cdiv(n, gemv_t_tile(sizeof(T)));
+                   double *part, int ncolp, const Epi &epi, hipStream_t s) {
+  const int tile = gemv_t_tile(sizeof(T));
+  const int tiles = (int)cdiv(n, tile);
   dim3 grid(tiles, splits);
-  hipLaunchKernelGGL((gemv_t_kernel<T, TV, NRHS, false, Epi>), grid, dim3(kBlock), 0, s, A, m, n,
-                     ld, v0, v1, rps, part, ncolp, tile_cnt, fin_cnt, epi);
+  hipLaunchKernelGGL((gemv_t_kernel<T, TV, NRHS, false, Epi>), grid, dim3(kBlock), 0, s, A, m, n, ld, v0, v1, rps,
+                     part, ncolp, epi);
+  hipLaunchKernelGGL((gemv_t_finish_kernel<NRHS, Epi>), dim3(cdiv(n, kFinishCols)), dim3(kBlock), 0, s, n, splits,
+                     (const double *)part, ncolp, epi);
 }
 
 // Pick lanes-per-row and rows-per-thread from the row length and row count.
 template <typename T, typename TV, int NRHS, class Epi>
-static void gemv_n(const T *A, int m, int n, int ld, const TV *v0, const TV *v1, unsigned *cnt,
-                   const Epi &epi, hipStream_t s, int *nblocks_out = nullptr) {
+static void gemv_n(const T *A, int m, int n, int ld, const TV *v0, const TV *v1, const Epi &epi, hipStream_t s,
+                   int *nblocks_out = nullptr) {
   constexpr int VN = Vec16<T>::N;
   const int vpr = (int)cdiv(n, VN);
   const bool wide_rows = vpr >= 128;
@@ -308,22 +294,22 @@ static void gemv_n(const T *A, int m, int n, int ld, const TV *v0, const TV *v1,
     if (cdiv(m, rows1) > 2048) {
       nb = (int)cdiv(m, gemv_n_rows_per_block<64, 4>());
       hipLaunchKernelGGL((gemv_n_kernel<T, TV, NRHS, false, 64, 4, Epi>), dim3(nb), dim3(kBlock), 0, s,
-                         A, m, n, ld, v0, v1, cnt, epi);
+                         A, m, n, ld, v0, v1, epi);
     } else {
       nb = (int)cdiv(m, rows1);
       hipLaunchKernelGGL((gemv_n_kernel<T, TV, NRHS, false, 64, 1, Epi>), dim3(nb), dim3(kBlock), 0, s,
-                         A, m, n, ld, v0, v1, cnt, epi);
+                         A, m, n, ld, v0, v1, epi);
     }
   } else {
     const int rows1 = gemv_n_rows_per_block<16, 1>();
     if (cdiv(m, rows1) > 2048) {
       nb = (int)cdiv(m, gemv_n_rows_per_block<16, 4>());
       hipLaunchKernelGGL((gemv_n_kernel<T, TV, NRHS, false, 16, 4, Epi>), dim3(nb), dim3(kBlock), 0, s,
-                         A, m, n, ld, v0, v1, cnt, epi);
+                         A, m, n, ld, v0, v1, epi);
     } else {
       nb = (int)cdiv(m, rows1);
       hipLaunchKernelGGL((gemv_n_kernel<T, TV, NRHS, false, 16, 1, Epi>), dim3(nb), dim3(kBlock), 0, s,
-                         A, m, n, ld, v0, v1, cnt, epi);
+                         A, m, n, ld, v0, v1, epi);
     }
   }
   if (nblocks_out) *nblocks_out = nb;
@@ -340,7 +326,7 @@ int gemv_n_blocks(int m, int ncols, int elem_size, int) {
   return cdiv(m, rows1) > 2048 ? (int)cdiv(m, gemv_n_rows_per_block<16, 4>()) : (int)cdiv(m, rows1);
 }
 
-// which: 0 prox, 1 first pass over A, 2 solve, 3 second pass over A.
+// which: 0 prox, 1 first pass over A, 2 solve, 3 second pass over A, 4 control.
 template <typename T>
 void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps, int ncolp, hipStream_t s) {
   const bool tall = p.m >= p.n;
@@ -351,28 +337,31 @@ void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps,
     case 1:
       if (tall) {
         EpiTallPass1<T> e{{p}};
-        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.dy, p.nu, splits, rps, p.part, ncolp, p.tile_cnt, &p.ctrl->cnt_b, e, s);
+        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.dy, p.nu, splits, rps, p.part, ncolp, e, s);
       } else {
         EpiWidePass1<T> e{{p}};
-        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.cx, p.xh, &p.ctrl->cnt_a, e, s);
+        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.cx, p.xh, e, s);
       }
       break;
     case 2:
       if (tall) {
         EpiTallSolve<T> e{{p}};
-        gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, &p.ctrl->cnt_a, e, s);
+        gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, e, s);
       } else {
         EpiWideSolve<T> e{{p}};
-        gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, &p.ctrl->cnt_a, e, s);
+        gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, e, s);
       }
+      break;
+    case 4:
+      hipLaunchKernelGGL(control_kernel<T>, dim3(1), dim3(kBlock), 0, s, p);
       break;
     default:
       if (tall) {
         EpiTallPass2<T> e{{p}};
-        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.x, p.xh, &p.ctrl->cnt_a, e, s);
+        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.x, p.xh, e, s);
       } else {
         EpiWidePass2<T> e{{p}};
-        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.yt, p.nu, splits, rps, p.part, ncolp, p.tile_cnt, &p.ctrl->cnt_b, e, s);
+        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.yt, p.nu, splits, rps, p.part, ncolp, e, s);
       }
       break;
   }
@@ -380,7 +369,7 @@ void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps,
 
 template <typename T>
 void launch_iteration(const IterArgs<T> &p, int splits, int rps, int ncolp, hipStream_t s) {
-  for (int w = 0; w < 4; ++w) launch_iteration_part<T>(p, w, splits, rps, ncolp, s);
+  for (int w = 0; w < 5; ++w) launch_iteration_part<T>(p, w, splits, rps, ncolp, s);
 }
 
 template <typename T>
@@ -389,21 +378,20 @@ void launch_project(const IterArgs<T> &p, int splits, int rps, int ncolp, const 
   ProjArgs<T> a{c, d, x, y, p.rhs};
   if (p.m >= p.n) {
     EpiProjTall1<T> e1; e1.a = a;
-    gemv_t<T, T, 1>(p.A, p.m, p.n, p.ld, d, d, splits, rps, p.part, ncolp, p.tile_cnt, &p.ctrl->cnt_b, e1, s);
+    gemv_t<T, T, 1>(p.A, p.m, p.n, p.ld, d, d, splits, rps, p.part, ncolp, e1, s);
     EpiProjTallSolve<T> e2; e2.a = a;
-    gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, &p.ctrl->cnt_a, e2, s);
+    gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, e2, s);
     EpiProjTall2<T> e3; e3.a = a;
-    gemv_n<T, T, 1>(p.A, p.m, p.n, p.ld, x, x, &p.ctrl->cnt_a, e3, s);
+    gemv_n<T, T, 1>(p.A, p.m, p.n, p.ld, x, x, e3, s);
   } else {
     EpiProjWide1<T> e1; e1.a = a;
-    gemv_n<T, T, 1>(p.A, p.m, p.n, p.ld, c, c, &p.ctrl->cnt_a, e1, s);
+    gemv_n<T, T, 1>(p.A, p.m, p.n, p.ld, c, c, e1, s);
     EpiProjWideSolve<T> e2; e2.a = a;
-    gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, &p.ctrl->cnt_a, e2, s);
+    gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, e2, s);
     // rhs <- d - y, then x = c + A^T rhs
     hipLaunchKernelGGL(sub_kernel<T>, dim3(cdiv(p.m, kBlock)), dim3(kBlock), 0, s, d, (const T *)y, p.rhs, p.m);
     EpiProjWide2<T> e3; e3.a = a;
-    gemv_t<T, T, 1>(p.A, p.m, p.n, p.ld, p.rhs, p.rhs, splits, rps, p.part, ncolp, p.tile_cnt,
-                    &p.ctrl->cnt_b, e3, s);
+    gemv_t<T, T, 1>(p.A, p.m, p.n, p.ld, p.rhs, p.rhs, splits, rps, p.part, ncolp, e3, s);
   }
 }
 

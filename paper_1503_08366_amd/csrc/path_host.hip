@@ -1,0 +1,212 @@
+// pogs_solve_path: R problems on one context's matrix, iterated together with
+// stacked right-hand sides (matrix products on MFMA) until every problem has
+// stopped.  Host side: packing the per-problem functions column-interleaved,
+// state allocation, graph-captured iteration chunks, results.
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "ctx.hpp"
+#include "hostutil.hpp"
+#include "path.hpp"
+
+using namespace pogs;
+
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Per-problem functions packed as [len][Rp] (problem index fastest), float64
+// a, b, c, d, e planes followed by the h codes.
+void pack_fns(const std::vector<HostFn> &fs, int len, int Rp, std::vector<double> *prm, std::vector<uint8_t> *h) {
+  const size_t tot = (size_t)len * Rp;
+  prm->assign(5 * tot, 0.0);
+  h->assign(tot, 0);
+  for (size_t r = 0; r < fs.size(); ++r) {
+    const HostFn &F = fs[r];
+    const std::vector<double> *arr[5] = {&F.a, &F.b, &F.c, &F.d, &F.e};
+    for (int i = 0; i < len; ++i) {
+      const size_t e = (size_t)i * Rp + r;
+      for (int k = 0; k < 5; ++k) (*prm)[k * tot + e] = (*arr[k])[i];
+      (*h)[e] = F.h[i];
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const pogs_fn *g, const pogs_params *params,
+                               pogs_result *out) {
+  if (!ctx || !f || !g || !out || R < 1 || R > 256) return POGS_EINVAL;
+  if (ctx->dt != POGS_F32 || ctx->m < ctx->n) return POGS_EUNSUPPORTED;
+  pogs_params prm = params ? *params : ctx->params;
+  if (check_params(prm)) return POGS_EINVAL;
+  const double t0 = now_ms();
+  const int m = (int)ctx->m, n = (int)ctx->n;
+  std::vector<HostFn> hf(R), hg(R);
+  int rc;
+  for (int r = 0; r < R; ++r) {
+    if ((rc = expand_fn(&f[r], m, &hf[r]))) return rc;
+    if ((rc = expand_fn(&g[r], n, &hg[r]))) return rc;
+    if (out[r].mem != POGS_HOST && out[r].mem != POGS_DEVICE) return POGS_EINVAL;
+  }
+  hipStream_t s = ctx->stream;
+  const int Rp = (int)round_up(R, 64);
+  std::vector<double> fprm, gprm;
+  std::vector<uint8_t> fhh, ghh;
+  pack_fns(hf, m, Rp, &fprm, &fhh);
+  pack_fns(hg, n, Rp, &gprm, &ghh);
+
+  PathArgs p{};
+  p.m = m;
+  p.n = n;
+  p.ld = ctx->ld;
+  p.q = ctx->q;
+  p.ldk = ctx->ldk;
+  p.R = R;
+  p.Rp = Rp;
+  p.rows_per_block = 64;
+  p.nbx = (int)cdiv(n, p.rows_per_block);
+  p.nby = (int)cdiv(m, p.rows_per_block);
+  p.nb_pri = p.nby;
+  p.nb_dual = p.nbx;
+  p.alpha = (float)prm.alpha;
+  p.delta = prm.delta;
+  p.tau = prm.tau;
+  p.eps_abs = prm.eps_abs;
+  p.eps_rel = prm.eps_rel;
+  p.max_iter = prm.max_iter;
+  p.adaptive = prm.adaptive_rho ? 1 : 0;
+  p.A = (const float *)ctx->A;
+  p.Kinv = (const float *)ctx->Kinv;
+
+  DevArena tmp;
+  const size_t tf = (size_t)m * Rp, tg = (size_t)n * Rp;
+  double *f0, *g0;
+  uint8_t *fh0, *gh0, *fh, *gh;
+  float *fs, *gs, *state, *part, *outs;
+  double *slots, *percol, *obj;
+  int *ints;
+  const size_t state_floats = 2 * tg + 3 * tg + 2 * tf + 3 * tf + tg;
+  const size_t nslots = (size_t)(p.nbx + p.nby + p.nb_pri + p.nb_dual) * Rp;
+  if ((rc = tmp.alloc((void **)&f0, 5 * tf * 8)) || (rc = tmp.alloc((void **)&g0, 5 * tg * 8)) ||
+      (rc = tmp.alloc((void **)&fh0, tf)) || (rc = tmp.alloc((void **)&gh0, tg)) || (rc = tmp.alloc((void **)&fh, tf)) ||
+      (rc = tmp.alloc((void **)&gh, tg)) || (rc = tmp.alloc((void **)&fs, 5 * tf * 4)) ||
+      (rc = tmp.alloc((void **)&gs, 5 * tg * 4)) || (rc = tmp.alloc((void **)&state, state_floats * 4)) ||
+      (rc = tmp.alloc((void **)&part, path_part_floats(m, n, Rp) * 4)) ||
+      (rc = tmp.alloc((void **)&outs, (size_t)R * 2 * (m + n) * 4)) || (rc = tmp.alloc((void **)&slots, nslots * 8)) ||
+      (rc = tmp.alloc((void **)&percol, (size_t)6 * Rp * 8)) || (rc = tmp.alloc((void **)&obj, (size_t)Rp * 8)) ||
+      (rc = tmp.alloc((void **)&ints, (size_t)(5 * Rp + 64) * 4)))
+    return rc;
+  POGS_HIP_TRY(hipMemcpyAsync(f0, fprm.data(), 5 * tf * 8, hipMemcpyHostToDevice, s));
+  POGS_HIP_TRY(hipMemcpyAsync(g0, gprm.data(), 5 * tg * 8, hipMemcpyHostToDevice, s));
+  POGS_HIP_TRY(hipMemcpyAsync(fh0, fhh.data(), tf, hipMemcpyHostToDevice, s));
+  POGS_HIP_TRY(hipMemcpyAsync(gh0, ghh.data(), tg, hipMemcpyHostToDevice, s));
+  launch_path_scale_fn(f0, fh0, m, Rp, ctx->D, true, fh, fs, fs + tf, fs + 2 * tf, fs + 3 * tf, fs + 4 * tf, s);
+  launch_path_scale_fn(g0, gh0, n, Rp, ctx->E, false, gh, gs, gs + tg, gs + 2 * tg, gs + 3 * tg, gs + 4 * tg, s);
+  p.fh = fh;
+  p.gh = gh;
+  p.fa = fs;
+  p.fb = fs + tf;
+  p.fc = fs + 2 * tf;
+  p.fd = fs + 3 * tf;
+  p.fe = fs + 4 * tf;
+  p.ga = gs;
+  p.gb = gs + tg;
+  p.gc = gs + 2 * tg;
+  p.gd = gs + 3 * tg;
+  p.ge = gs + 4 * tg;
+  float *sp = state;
+  p.XX = sp; sp += 2 * tg;
+  p.Xt = sp; sp += tg;
+  p.Mu = sp; sp += tg;
+  p.Cx = sp; sp += tg;
+  p.DN = sp; sp += 2 * tf;
+  p.Y = sp; sp += tf;
+  p.Yt = sp; sp += tf;
+  p.Yh = sp; sp += tf;
+  p.Rhs = sp; sp += tg;
+  POGS_HIP_TRY(hipMemsetAsync(state, 0, state_floats * 4, s));
+  p.s_mu = slots;
+  p.s_yh = p.s_mu + (size_t)p.nbx * Rp;
+  p.s_pri = p.s_yh + (size_t)p.nby * Rp;
+  p.s_dual = p.s_pri + (size_t)p.nb_pri * Rp;
+  p.rho = percol;
+  p.rescale = percol + Rp;
+  p.r_pri = percol + 2 * Rp;
+  p.r_dual = percol + 3 * Rp;
+  p.eps_pri = percol + 4 * Rp;
+  p.eps_dual = percol + 5 * Rp;
+  p.l = ints;
+  p.u = ints + Rp;
+  p.iters = ints + 2 * Rp;
+  p.done = ints + 3 * Rp;
+  p.status = ints + 4 * Rp;
+  p.all_done = ints + 5 * Rp;
+  {
+    std::vector<double> hc(6 * (size_t)Rp, 0.0);
+    for (int r = 0; r < Rp; ++r) {
+      hc[r] = prm.rho0;
+      hc[Rp + r] = 1.0;
+    }
+    std::vector<int> hi(5 * (size_t)Rp + 64, 0);
+    for (int r = 0; r < Rp; ++r) hi[4 * Rp + r] = -1;
+    POGS_HIP_TRY(hipMemcpyAsync(percol, hc.data(), hc.size() * 8, hipMemcpyHostToDevice, s));
+    POGS_HIP_TRY(hipMemcpyAsync(ints, hi.data(), hi.size() * 4, hipMemcpyHostToDevice, s));
+    POGS_HIP_TRY(hipStreamSynchronize(s));
+  }
+  // iterate in captured chunks until every problem has stopped
+  const int chunk = std::max(1, prm.chunk_iters > 0 ? prm.chunk_iters : 20);
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  POGS_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < chunk; ++i) launch_path_iteration(p, part, s);
+  POGS_HIP_TRY(hipStreamEndCapture(s, &graph));
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return POGS_EDEVICE;
+  }
+  (void)hipGraphDestroy(graph);
+  int all_done = 0;
+  int guard = 0;
+  const int max_launches = (int)cdiv(prm.max_iter, chunk) + 1;
+  while (!all_done && guard++ < max_launches) {
+    if (hipGraphLaunch(exec, s) != hipSuccess) break;
+    if (hipMemcpyAsync(&all_done, p.all_done, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) break;
+    if (hipStreamSynchronize(s) != hipSuccess) break;
+  }
+  (void)hipGraphExecDestroy(exec);
+  POGS_HIP_TRY(hipGetLastError());
+  launch_path_unscale(p, ctx->D, ctx->E, f0, fh0, g0, gh0, outs, obj, s);
+  std::vector<double> hc(6 * (size_t)Rp), hobj(Rp);
+  std::vector<int> hi(5 * (size_t)Rp);
+  POGS_HIP_TRY(hipMemcpyAsync(hc.data(), percol, hc.size() * 8, hipMemcpyDeviceToHost, s));
+  POGS_HIP_TRY(hipMemcpyAsync(hi.data(), ints, hi.size() * 4, hipMemcpyDeviceToHost, s));
+  POGS_HIP_TRY(hipMemcpyAsync(hobj.data(), obj, (size_t)Rp * 8, hipMemcpyDeviceToHost, s));
+  for (int r = 0; r < R; ++r) {
+    const float *o = outs + (size_t)r * 2 * (m + n);
+    const hipMemcpyKind k = out[r].mem == POGS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (out[r].x) POGS_HIP_TRY(hipMemcpyAsync(out[r].x, o, (size_t)n * 4, k, s));
+    if (out[r].y) POGS_HIP_TRY(hipMemcpyAsync(out[r].y, o + n, (size_t)m * 4, k, s));
+    if (out[r].mu) POGS_HIP_TRY(hipMemcpyAsync(out[r].mu, o + n + m, (size_t)n * 4, k, s));
+    if (out[r].nu) POGS_HIP_TRY(hipMemcpyAsync(out[r].nu, o + 2 * n + m, (size_t)m * 4, k, s));
+  }
+  POGS_HIP_TRY(hipStreamSynchronize(s));
+  POGS_HIP_TRY(hipGetLastError());
+  const double ms = now_ms() - t0;
+  for (int r = 0; r < R; ++r) {
+    out[r].optval = hobj[r];
+    out[r].rho = hc[r];
+    out[r].r_pri = hc[2 * Rp + r];
+    out[r].r_dual = hc[3 * Rp + r];
+    out[r].eps_pri = hc[4 * Rp + r];
+    out[r].eps_dual = hc[5 * Rp + r];
+    out[r].iters = hi[2 * Rp + r];
+    out[r].status = hi[4 * Rp + r] < 0 ? POGS_MAXITER : hi[4 * Rp + r];
+    out[r].ms_setup = ctx->ms_setup;
+    out[r].ms_solve = ms;
+  }
+  return POGS_OK;
+}

@@ -84,17 +84,15 @@ struct EqArgs {
 // d_i = n / (sum_j A_ij^2 e_j + gamma/m)
 struct EpiEqRow {
   EqArgs a;
-  static constexpr bool kFinal = false;
   __device__ bool skip() const { return false; }
   __device__ double row(int i, double s, double) const { a.d[i] = a.nf / (s + a.gamma_m); return 0.0; }
   __device__ void block_done(int, double) const {}
-  __device__ void final(double *) const {}
 };
 
-// e_j = m / (sum_i A_ij^2 d_i + gamma/n); also sum_j e_j colsum_j = ||D A E||_F^2
+// e_j = m / (sum_i A_ij^2 d_i + gamma/n); the per-tile sums of e_j colsum_j
+// give ||D A E||_F^2 after the last sweep.
 struct EpiEqCol {
   EqArgs a;
-  static constexpr bool kFinal = true;
   __device__ bool skip() const { return false; }
   __device__ double column(int j, double s, double) const {
     const double e = a.mf / (s + a.gamma_n);
@@ -102,12 +100,6 @@ struct EpiEqCol {
     return e * s;
   }
   __device__ void tile_done(int tile, double v) const { a.slots[tile] = v; }
-  __device__ void final(double *lds) const {
-    double t = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) t += load_agent(a.slots + i);
-    const double tot = block_sum(t, lds);
-    if (threadIdx.x == 0) *a.fro2 = tot;
-  }
 };
 
 __global__ void fill_kernel(double *p, double v, int len) {
@@ -117,10 +109,12 @@ __global__ void fill_kernel(double *p, double v, int len) {
 
 // D_i = sqrt(d_i / s), E_j = sqrt(e_j / s) with s = sqrt(fro2 / q): the
 // Frobenius norm of D A E over sqrt(min(m, n)) becomes 1 (Section 4.1.2).
-__global__ void equil_finish_kernel(const double *d, const double *e, const double *fro2, int m, int n,
+__global__ void equil_finish_kernel(const double *d, const double *e, const double *slots, int ntiles, int m, int n,
                                     int q, double *D, double *E) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const double s = sqrt(*fro2 / (double)q);
+  double fro2 = 0.0;
+  for (int t = 0; t < ntiles; ++t) fro2 += slots[t];
+  const double s = sqrt(fro2 / (double)q);
   if (i < m) D[i] = sqrt(d[i] / s);
   else if (i < m + n) E[i - m] = sqrt(e[i - m] / s);
 }
@@ -168,8 +162,7 @@ int run_equilibrate(T *A, int m, int n, int ld, int iters, double eps_cmp, doubl
   a.nf = n;
   hipLaunchKernelGGL(fill_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, a.e, 1.0, n);
   const int tiles = (int)cdiv(n, gemv_t_tile(sizeof(T)));
-  unsigned *tile_cnt = counters;  // counters holds tiles + 1 (zeroed) entries
-  unsigned *fin_cnt = counters + tiles;
+  (void)counters;
   for (int it = 0; it < iters; ++it) {
     // rows: d = n / (|A|^2 e + gamma/m)
     {
@@ -177,23 +170,25 @@ int run_equilibrate(T *A, int m, int n, int ld, int iters, double eps_cmp, doubl
       constexpr int VN = Vec16<T>::N;
       if (cdiv(n, VN) >= 128)
         hipLaunchKernelGGL((gemv_n_kernel<T, double, 1, true, 64, 1, EpiEqRow>),
-                           dim3(cdiv(m, gemv_n_rows_per_block<64, 1>())), dim3(kBlock), 0, s, A, m, n, ld,
-                           a.e, a.e, fin_cnt, er);
+                           dim3(cdiv(m, gemv_n_rows_per_block<64, 1>())), dim3(kBlock), 0, s, A, m, n, ld, a.e, a.e,
+                           er);
       else
         hipLaunchKernelGGL((gemv_n_kernel<T, double, 1, true, 16, 1, EpiEqRow>),
-                           dim3(cdiv(m, gemv_n_rows_per_block<16, 1>())), dim3(kBlock), 0, s, A, m, n, ld,
-                           a.e, a.e, fin_cnt, er);
+                           dim3(cdiv(m, gemv_n_rows_per_block<16, 1>())), dim3(kBlock), 0, s, A, m, n, ld, a.e, a.e,
+                           er);
     }
     // columns: e = m / (|A^T|^2 d + gamma/n)
     {
       EpiEqCol ec{a};
-      hipLaunchKernelGGL((gemv_t_kernel<T, double, 1, true, EpiEqCol>), dim3(tiles, splits), dim3(kBlock),
-                         0, s, A, m, n, ld, a.d, a.d, rps, part, ncolp, tile_cnt, fin_cnt, ec);
+      hipLaunchKernelGGL((gemv_t_kernel<T, double, 1, true, EpiEqCol>), dim3(tiles, splits), dim3(kBlock), 0, s, A,
+                         m, n, ld, a.d, a.d, rps, part, ncolp, ec);
+      hipLaunchKernelGGL((gemv_t_finish_kernel<1, EpiEqCol>), dim3(cdiv(n, kFinishCols)), dim3(kBlock), 0, s, n,
+                         splits, (const double *)part, ncolp, ec);
     }
   }
   const int q = std::min(m, n);
-  hipLaunchKernelGGL(equil_finish_kernel, dim3(cdiv(m + n, 256)), dim3(256), 0, s, a.d, a.e, a.fro2, m, n, q,
-                     D, E);
+  hipLaunchKernelGGL(equil_finish_kernel, dim3(cdiv(m + n, 256)), dim3(256), 0, s, a.d, a.e, a.slots,
+                     (int)cdiv(n, kFinishCols), m, n, q, D, E);
   hipLaunchKernelGGL((scale_matrix_kernel<T>), dim3(cdiv(n, 256), std::min(m, 32768)), dim3(256), 0, s, A, m, n,
                      ld, D, E);
   return POGS_OK;

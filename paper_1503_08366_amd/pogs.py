@@ -99,11 +99,26 @@ _SIGS = {
 }
 
 
+def _init_torch_first():
+    """torch's ROCm wheel carries its own HIP runtime; it must initialise the
+    device before libpogs's runtime does, or torch later reports no GPU."""
+    try:
+        import torch
+    except ImportError:
+        return
+    try:
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except Exception:
+        pass
+
+
 def _lib():
     global _LIB
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built (python -m paper_1503_08366_amd.build)")
+        _init_torch_first()
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(lib, name)

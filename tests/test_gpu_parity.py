@@ -205,7 +205,7 @@ def test_maxiter_status_and_repeat_solves():
         # a second solve on the same context starts from zero again
         r2 = ctx.solve(prob.f, prob.g, prm)
         np.testing.assert_array_equal(r.x, r2.x)
-        full = ctx.solve(prob.f, prob.g)
+        full = ctx.solve(prob.f, prob.g, P.default_params())
         assert full.converged
 
 
