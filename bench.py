@@ -69,19 +69,117 @@ def cpu_baseline(prob, budget_s: float = 30.0):
                       f"{dt:.1f} s)", "iter_per_s": iters / dt}
 
 
+def bench_batch(args):
+    """512 uneven Lasso/logistic problems: one batched call vs one problem per launch sequence."""
+    from paper_1503_08366_amd import pogs as P
+    from paper_1503_08366_amd import workloads as W
+    probs = W.batch_mix(count=args.count)
+    P.pogs_solve_batch(probs[:8])  # warm
+    t = time.perf_counter()
+    res = P.pogs_solve_batch(probs)
+    tb = time.perf_counter() - t
+    conv = sum(r.converged for r in res)
+    nplain = min(len(probs), args.plain_count)
+    t = time.perf_counter()
+    plain_conv = 0
+    for p in probs[:nplain]:
+        with P.Context(p.A) as ctx:
+            plain_conv += ctx.solve(p.f, p.g).converged
+    tp = time.perf_counter() - t
+    return {"metric": "solves/s at rel tol 1e-3, batched (one persistent launch) vs plain",
+            "value": conv / tb, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "config": {"workload": f"{len(probs)} problems, even Lasso / odd logistic, m~U[64,4096], n~U[32,1024], "
+                                   "float32, host inputs (PCIe copy inside the timed region for both legs)"},
+            "batched": {"solves_per_s": conv / tb, "seconds": tb, "converged": f"{conv}/{len(res)}",
+                        "iters_mean": float(np.mean([r.iters for r in res]))},
+            "plain": {"solves_per_s": plain_conv / tp, "seconds": tp, "problems": nplain},
+            "speedup": (conv / tb) / max(plain_conv / tp, 1e-30)}
+
+
+def bench_path(args):
+    """64-point lambda path on one 8000x1000 A: stacked right-hand sides on MFMA vs one solve per lambda."""
+    from paper_1503_08366_amd import pogs as P
+    from paper_1503_08366_amd import workloads as W
+    probs = W.lambda_path(R=args.R)
+    with P.Context(probs[0].A) as ctx:
+        ctx.solve_path([p.f for p in probs[:2]], [p.g for p in probs[:2]])  # warm
+        t = time.perf_counter()
+        res = ctx.solve_path([p.f for p in probs], [p.g for p in probs])
+        tpath = time.perf_counter() - t
+        t = time.perf_counter()
+        alone = [ctx.solve(p.f, p.g) for p in probs]
+        tplain = time.perf_counter() - t
+        setup_ms = alone[0].ms_setup
+    conv = sum(r.converged for r in res)
+    return {"metric": "solves/s at rel tol 1e-3, lambda path (stacked RHS, MFMA) vs plain",
+            "value": conv / tpath, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "config": {"workload": f"{len(probs)} Lasso lambdas log-spaced over [1e-3, 1] lam_max, A 8000x1000 float32, "
+                                   "shared setup excluded from both legs", "setup_ms": setup_ms},
+            "path": {"seconds": tpath, "converged": f"{conv}/{len(res)}", "iters_max": max(r.iters for r in res)},
+            "plain": {"seconds": tplain, "solves_per_s": sum(r.converged for r in alone) / tplain,
+                      "iters_sum": sum(r.iters for r in alone)},
+            "speedup": tplain / tpath}
+
+
+def bench_serve(args):
+    """Poisson arrivals of mixed Lasso/NNLS/SVM/LP requests into the serving engine."""
+    from paper_1503_08366_amd import pogs as P
+    from paper_1503_08366_amd import workloads as W
+    stream = list(W.serving_stream(args.count, args.qps))
+    eng = P.BatchEngine(chunk_iters=25)
+    try:
+        start = time.perf_counter()
+        pending = {}
+        lat = []
+        statuses = []
+        i = 0
+        while i < len(stream) or pending:
+            now = time.perf_counter() - start
+            while i < len(stream) and stream[i][0] <= now:
+                t_arr, p = stream[i]
+                pending[eng.submit(p)] = t_arr
+                i += 1
+            for tk in list(pending):
+                r = eng.poll(tk)
+                if r is not None:
+                    lat.append(time.perf_counter() - start - pending.pop(tk))
+                    statuses.append(r.status)
+            time.sleep(0.0005)
+        wall = time.perf_counter() - start
+    finally:
+        eng.close()
+    conv = sum(s == P.POGS_CONVERGED for s in statuses)
+    return {"metric": "served solves/s at rel tol 1e-3 with p50/p99 latency (continuous batching)",
+            "value": conv / wall, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "config": {"workload": f"{args.count} requests, Poisson at {args.qps}/s, Lasso/NNLS/SVM/LP, "
+                                   "m~logU[100,50000], n~logU[50,5000], float32 host inputs"},
+            "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
+            "converged": f"{conv}/{len(statuses)}", "wall_s": wall}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lasso", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="lasso", choices=sorted(WORKLOADS) + ["batch", "path", "serve"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--profile-reps", type=int, default=100)
+    ap.add_argument("--count", type=int, default=512, help="batch / serve: number of problems")
+    ap.add_argument("--plain-count", type=int, default=512, help="batch: problems in the plain leg")
+    ap.add_argument("--R", type=int, default=64, help="path: number of lambdas")
+    ap.add_argument("--qps", type=float, default=200.0, help="serve: arrival rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
               "described in DESIGN.md and not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload in ("batch", "path", "serve"):
+        import torch
+        torch.cuda.set_device(0)
+        out = {"batch": bench_batch, "path": bench_path, "serve": bench_serve}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
 
     import torch
     from paper_1503_08366_amd import pogs as P

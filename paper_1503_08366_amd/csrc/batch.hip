@@ -256,13 +256,14 @@ __device__ void wg_setup(BProb &P, double *ws, char *lds, WgShared &sh) {
       for (int J = kb + 1; J <= I; ++J) syrk_tile(K, Q, kb, I, J, fst);
     __syncthreads();
   }
-  // ---- L^{-1} by blocks, then K^{-1} ----
-  for (int b = 0; b < nbt; ++b) inv_diag_copy(Dinv, X, Q, b);
+  // ---- L^{-1} (right-looking blocks), then K^{-1} ----
+  trtri_init_rows(X, Q, 0, Q);
   __syncthreads();
-  for (int ib = 1; ib < nbt; ++ib) {
-    for (int jb = 0; jb < ib; ++jb) inv_accum_tile(K, X, Q, ib, jb, fst);
+  for (int i = 0; i < nbt; ++i) {
+    for (int j = 0; j <= i; ++j) trtri_scale_tile(Dinv, X, Q, i, j, fst);
     __syncthreads();
-    for (int jb = 0; jb < ib; ++jb) inv_scale_tile(Dinv, X, Q, ib, jb, fst);
+    for (int r = i + 1; r < nbt; ++r)
+      for (int j = 0; j <= i; ++j) trtri_update_tile(K, X, Q, i, r, j, fst);
     __syncthreads();
   }
   for (int i = 0; i < q; ++i)

@@ -19,9 +19,8 @@ struct F64Stage {             // 16.9 KB
   double a[16][LSF];
   double b[16][LSF];
 };
-struct CholLds {              // 66.6 KB
-  double L[NB][NB + 1];
-  double X[NB][NB + 1];
+struct CholLds {              // 33.8 KB
+  double L[NB][NB + 2];
 };
 constexpr int kGramTB = 128;  // f32 Gram tile
 struct GramStage {            // 16.9 KB
@@ -219,51 +218,61 @@ template <class Fn> __device__ inline void acc_store(const F64Acc acc[2][2], Fn 
   f64_tile_store(acc, (w >> 1) * 32, (w & 1) * 32, fn);
 }
 
-// Factor diagonal block kb of K (Q x Q, row-major, lower) in LDS by the
-// unblocked right-looking Cholesky and invert the triangular factor by column
-// substitution.  Writes L_kk (upper part zeroed) back into K and L_kk^{-1}
-// into Dinv block kb.  A non-positive pivot counts in *bad (replaced by 1).
+// Factor diagonal block kb of K (Q x Q, row-major, lower) and invert the
+// factor, with one wave: the block sits in LDS; lane r owns row r and runs the
+// left-looking Cholesky (column j: L_rj = (K_rj - sum_{k<j} L_rk L_jk) / L_jj,
+// the pivot broadcast from lane j); then lane c solves L x = e_c by forward
+// substitution with x in registers, giving column c of L^{-1}.  Writes L_kk
+// (upper part zeroed) back into K and L_kk^{-1} into Dinv block kb.  A
+// non-positive pivot counts in *bad and is replaced by 1.  LDS operations of
+// one wave complete in issue order, so the steps need no barrier, only a
+// compiler fence.
 __device__ inline void potrf_diag(double *K, int Q, int kb, double *Dinv, unsigned *bad, CholLds &s) {
   const int t = threadIdx.x;
   double *blk = K + (size_t)kb * NB * Q + (size_t)kb * NB;
-  for (int e = t; e < NB * NB; e += 256) s.L[e / NB][e % NB] = blk[(size_t)(e / NB) * Q + e % NB];
+  for (int e = t; e < NB * NB; e += blockDim.x) s.L[e / NB][e % NB] = blk[(size_t)(e / NB) * Q + e % NB];
   __syncthreads();
-  for (int j = 0; j < NB; ++j) {
-    if (t == 0) {
-      double v = s.L[j][j];
-      if (!(v > 0.0) || !isfinite(v)) {
-        atomicAdd(bad, 1u);
-        v = 1.0;
-      }
-      s.L[j][j] = sqrt(v);
-    }
-    __syncthreads();
-    const double djj = s.L[j][j];
-    for (int r = j + 1 + t; r < NB; r += 256) s.L[r][j] /= djj;
-    __syncthreads();
-    const int nr = NB - 1 - j;
-    for (int e = t; e < nr * nr; e += 256) {
-      const int r = j + 1 + e / nr, c = j + 1 + e % nr;
-      if (c <= r) s.L[r][c] -= s.L[r][j] * s.L[c][j];
-    }
-    __syncthreads();
-  }
   if (t < NB) {
-    const int c = t;
-    for (int r = 0; r < c; ++r) s.X[r][c] = 0.0;
-    s.X[c][c] = 1.0 / s.L[c][c];
-    for (int r = c + 1; r < NB; ++r) {
-      double acc = 0.0;
-      for (int k = c; k < r; ++k) acc += s.L[r][k] * s.X[k][c];
-      s.X[r][c] = -acc / s.L[r][r];
+    const int r = t;
+    for (int j = 0; j < NB; ++j) {
+      double a0 = 0.0, a1 = 0.0;
+      int k = 0;
+      for (; k + 1 < j; k += 2) {
+        a0 = fma(s.L[r][k], s.L[j][k], a0);
+        a1 = fma(s.L[r][k + 1], s.L[j][k + 1], a1);
+      }
+      if (k < j) a0 = fma(s.L[r][k], s.L[j][k], a0);
+      const double v = s.L[r][j] - (a0 + a1);
+      double piv = __shfl(v, j, 64);
+      const bool badp = !(piv > 0.0) || !isfinite(piv);
+      if (badp) piv = 1.0;
+      const double d = sqrt(piv);
+      if (r == j) s.L[r][j] = d;
+      else if (r > j) s.L[r][j] = v / d;
+      if (badp && r == 0) atomicAdd(bad, 1u);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
+    // column c = r of L^{-1}
+    double x[NB];
+#pragma unroll
+    for (int rr = 0; rr < NB; ++rr) {
+      double b0 = 0.0, b1 = 0.0;
+#pragma unroll
+      for (int q = 0; q + 1 < rr; q += 2) {
+        b0 = fma(s.L[rr][q], x[q], b0);
+        b1 = fma(s.L[rr][q + 1], x[q + 1], b1);
+      }
+      if (rr & 1) b0 = fma(s.L[rr][rr - 1], x[rr - 1], b0);
+      x[rr] = ((rr == r ? 1.0 : 0.0) - (b0 + b1)) / s.L[rr][rr];
+    }
+    double *dv = Dinv + (size_t)kb * NB * NB;
+#pragma unroll
+    for (int rr = 0; rr < NB; ++rr) dv[rr * NB + r] = x[rr];
   }
   __syncthreads();
-  double *dv = Dinv + (size_t)kb * NB * NB;
-  for (int e = t; e < NB * NB; e += 256) {
+  for (int e = t; e < NB * NB; e += blockDim.x) {
     const int r = e / NB, c = e % NB;
     blk[(size_t)r * Q + c] = c <= r ? s.L[r][c] : 0.0;
-    dv[e] = s.X[r][c];
   }
   __syncthreads();
 }
@@ -289,30 +298,33 @@ __device__ inline void syrk_tile(double *K, int Q, int kb, int I, int J, F64Stag
   acc_store(acc, [&](int r, int c, double v) { C[(size_t)r * Q + c] -= v; });
 }
 
-// Blocked L^{-1}, step ib: X_ib,jb <- sum_{k=jb}^{ib-1} L_ib,k X_k,jb   (jb < ib)
-__device__ inline void inv_accum_tile(const double *K, double *X, int Q, int ib, int jb, F64Stage &st) {
+// Blocked L^{-1} by right-looking block forward substitution of L X = I:
+// X holds B = I - sum_{k<i} L_.k X_k. (initialised to the identity); step i
+// sets X_ij = L_ii^{-1} B_ij for j <= i (trtri_scale_tile), then
+// B_rj -= L_ri X_ij for r > i, j <= i (trtri_update_tile).  Every launch of a
+// step is many independent 64 x 64 x 64 products.
+__device__ inline void trtri_scale_tile(const double *Dinv, double *X, int Q, int i, int j, F64Stage &st) {
   F64Acc acc[2][2];
   acc_zero(acc);
-  const double *pa = K + (size_t)ib * NB * Q + (size_t)jb * NB;
-  const double *pb = X + (size_t)jb * NB * Q + (size_t)jb * NB;
-  block_product(acc, pa, Q, 1, pb, Q, 1, (ib - jb) * NB, st);
-  double *C = X + (size_t)ib * NB * Q + (size_t)jb * NB;
+  double *C = X + (size_t)i * NB * Q + (size_t)j * NB;
+  block_product(acc, Dinv + (size_t)i * NB * NB, NB, 1, C, Q, 1, NB, st);
   acc_store(acc, [&](int r, int c, double v) { C[(size_t)r * Q + c] = v; });
 }
 
-// X_ib,jb <- -L_ib,ib^{-1} X_ib,jb   (in place)
-__device__ inline void inv_scale_tile(const double *Dinv, double *X, int Q, int ib, int jb, F64Stage &st) {
+__device__ inline void trtri_update_tile(const double *K, double *X, int Q, int i, int r, int j, F64Stage &st) {
   F64Acc acc[2][2];
   acc_zero(acc);
-  double *C = X + (size_t)ib * NB * Q + (size_t)jb * NB;
-  block_product(acc, Dinv + (size_t)ib * NB * NB, NB, 1, C, Q, 1, NB, st);
-  acc_store(acc, [&](int r, int c, double v) { C[(size_t)r * Q + c] = -v; });
+  const double *pa = K + (size_t)r * NB * Q + (size_t)i * NB;  // L_ri
+  const double *pb = X + (size_t)i * NB * Q + (size_t)j * NB;  // X_ij
+  block_product(acc, pa, Q, 1, pb, Q, 1, NB, st);
+  double *C = X + (size_t)r * NB * Q + (size_t)j * NB;
+  acc_store(acc, [&](int rr, int cc, double v) { C[(size_t)rr * Q + cc] -= v; });
 }
 
-// X_ii = L_ii^{-1}
-__device__ inline void inv_diag_copy(const double *Dinv, double *X, int Q, int b) {
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x)
-    X[(size_t)(b * NB + e / NB) * Q + b * NB + e % NB] = Dinv[(size_t)b * NB * NB + e];
+// X <- I on the lower block triangle (upper blocks are never read).
+__device__ inline void trtri_init_rows(double *X, int Q, int row0, int row1) {
+  for (int i = row0; i < row1; ++i)
+    for (int j = threadIdx.x; j <= i; j += blockDim.x) X[(size_t)i * Q + j] = i == j ? 1.0 : 0.0;
 }
 
 // K^{-1}_I,J = sum_{k >= I} X_k,I^T X_k,J for I >= J, written and mirrored as T

@@ -184,33 +184,49 @@ __global__ __launch_bounds__(kBlock) void gemv_n_kernel(
       if constexpr (NRHS > 1) vs[1][t] = j < n ? v1[j] : TV(0);
     }
     __syncthreads();
+    // RPT rows side by side, two column steps per trip: up to 2 * RPT
+    // independent 16-byte loads in flight per lane.  Rows past m read row
+    // m - 1 (valid memory) and are discarded.
+    const TA *rowp[RPT];
 #pragma unroll
-    for (int t = 0; t < RPT; ++t) {
-      const int i = row_base + t;
-      if (i < m) {
-        const TA *rowp = A + (size_t)i * ld + c0;
-        int c = sub * VN;
-        for (; c + 3 * LPR * VN < clen; c += 4 * LPR * VN) {
-          V a[4];
+    for (int t = 0; t < RPT; ++t) rowp[t] = A + (size_t)min(row_base + t, m - 1) * ld + c0;
+    constexpr int STEP = LPR * VN;
+    int c = sub * VN;
+    for (; c + STEP < clen; c += 2 * STEP) {
+      V a[2][RPT];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) a[u] = *reinterpret_cast<const V *>(rowp + c + u * LPR * VN);
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
+        for (int t = 0; t < RPT; ++t) a[u][t] = *reinterpret_cast<const V *>(rowp[t] + c + u * STEP);
 #pragma unroll
-            for (int k = 0; k < VN; ++k) {
-              const double e = elem_op<SQUARE>((double)a[u][k]);
-              acc[t][0] = fma(e, (double)vs[0][c + u * LPR * VN + k], acc[t][0]);
-              if constexpr (NRHS > 1) acc[t][1] = fma(e, (double)vs[1][c + u * LPR * VN + k], acc[t][1]);
-            }
-        }
-        for (; c < clen; c += LPR * VN) {
-          const V a = *reinterpret_cast<const V *>(rowp + c);
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-          for (int k = 0; k < VN; ++k) {
-            const double e = elem_op<SQUARE>((double)a[k]);
-            acc[t][0] = fma(e, (double)vs[0][c + k], acc[t][0]);
-            if constexpr (NRHS > 1) acc[t][1] = fma(e, (double)vs[1][c + k], acc[t][1]);
+        for (int k = 0; k < VN; ++k) {
+          const double x0 = (double)vs[0][c + u * STEP + k];
+          double x1 = 0.0;
+          if constexpr (NRHS > 1) x1 = (double)vs[1][c + u * STEP + k];
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) {
+            const double e = elem_op<SQUARE>((double)a[u][t][k]);
+            acc[t][0] = fma(e, x0, acc[t][0]);
+            if constexpr (NRHS > 1) acc[t][1] = fma(e, x1, acc[t][1]);
           }
+        }
+    }
+    if (c < clen) {
+      V a[RPT];
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) a[t] = *reinterpret_cast<const V *>(rowp[t] + c);
+#pragma unroll
+      for (int k = 0; k < VN; ++k) {
+        const double x0 = (double)vs[0][c + k];
+        double x1 = 0.0;
+        if constexpr (NRHS > 1) x1 = (double)vs[1][c + k];
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          const double e = elem_op<SQUARE>((double)a[t][k]);
+          acc[t][0] = fma(e, x0, acc[t][0]);
+          if constexpr (NRHS > 1) acc[t][1] = fma(e, x1, acc[t][1]);
         }
       }
     }

@@ -335,23 +335,35 @@ __global__ __launch_bounds__(256) void trsm_panel_kernel(double *K, int Q, int k
   trsm_tile(K, Q, kb, kb + 1 + blockIdx.x, Dinv, st);
 }
 
-__global__ __launch_bounds__(256) void syrk_update_kernel(double *K, int Q, int kb) {
-  __shared__ F64Stage st;
+// Trailing update of step kb; the workgroup that updates the next diagonal
+// block (tile 0) then factors it, saving a launch per step.
+__global__ __launch_bounds__(256) void syrk_update_kernel(double *K, int Q, int kb, double *Dinv, unsigned *bad) {
+  __shared__ union {
+    F64Stage st;
+    CholLds cl;
+  } lds;
   int I, J;
   tri_index(blockIdx.x, &I, &J);
-  syrk_tile(K, Q, kb, I + kb + 1, J + kb + 1, st);
+  syrk_tile(K, Q, kb, I + kb + 1, J + kb + 1, lds.st);
+  if (blockIdx.x == 0) {
+    __syncthreads();
+    potrf_diag(K, Q, kb + 1, Dinv, bad, lds.cl);
+  }
 }
 
-__global__ void inv_diag_copy_kernel(const double *Dinv, double *X, int Q) { inv_diag_copy(Dinv, X, Q, blockIdx.x); }
-
-__global__ __launch_bounds__(256) void inv_accum_kernel(const double *K, double *X, int Q, int ib) {
-  __shared__ F64Stage st;
-  inv_accum_tile(K, X, Q, ib, blockIdx.x, st);
+__global__ __launch_bounds__(256) void trtri_init_kernel(double *X, int Q) {
+  trtri_init_rows(X, Q, blockIdx.x * 8, min(Q, (int)blockIdx.x * 8 + 8));
 }
 
-__global__ __launch_bounds__(256) void inv_scale_kernel(const double *Dinv, double *X, int Q, int ib) {
+__global__ __launch_bounds__(256) void trtri_scale_kernel(const double *Dinv, double *X, int Q, int i) {
   __shared__ F64Stage st;
-  inv_scale_tile(Dinv, X, Q, ib, blockIdx.x, st);
+  trtri_scale_tile(Dinv, X, Q, i, blockIdx.x, st);
+}
+
+__global__ __launch_bounds__(256) void trtri_update_kernel(const double *K, double *X, int Q, int i) {
+  __shared__ F64Stage st;
+  const int w = blockIdx.x;
+  trtri_update_tile(K, X, Q, i, i + 1 + w / (i + 1), w % (i + 1), st);
 }
 
 template <typename T>
@@ -367,18 +379,20 @@ int run_factor_inverse(double *K, int q, int Q, T *Kinv, int ldk, double *ws, un
   const int nbt = Q / NB;
   double *X = ws;                        // Q x Q
   double *Dinv = ws + (size_t)Q * Q;     // nbt blocks of 64 x 64
-  for (int kb = 0; kb < nbt; ++kb) {
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, K, Q, kb, Dinv, bad);
+  // Cholesky: diagonal factor, panel solve, trailing update (+ next diagonal factor)
+  hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, K, Q, 0, Dinv, bad);
+  for (int kb = 0; kb + 1 < nbt; ++kb) {
     const int rest = nbt - kb - 1;
-    if (rest > 0) {
-      hipLaunchKernelGGL(trsm_panel_kernel, dim3(rest), dim3(256), 0, s, K, Q, kb, (const double *)Dinv);
-      hipLaunchKernelGGL(syrk_update_kernel, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, K, Q, kb);
-    }
+    hipLaunchKernelGGL(trsm_panel_kernel, dim3(rest), dim3(256), 0, s, K, Q, kb, (const double *)Dinv);
+    hipLaunchKernelGGL(syrk_update_kernel, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, K, Q, kb, Dinv, bad);
   }
-  hipLaunchKernelGGL(inv_diag_copy_kernel, dim3(nbt), dim3(256), 0, s, (const double *)Dinv, X, Q);
-  for (int ib = 1; ib < nbt; ++ib) {
-    hipLaunchKernelGGL(inv_accum_kernel, dim3(ib), dim3(256), 0, s, (const double *)K, X, Q, ib);
-    hipLaunchKernelGGL(inv_scale_kernel, dim3(ib), dim3(256), 0, s, (const double *)Dinv, X, Q, ib);
+  // L^{-1}, right-looking
+  hipLaunchKernelGGL(trtri_init_kernel, dim3(cdiv(Q, 8)), dim3(256), 0, s, X, Q);
+  for (int i = 0; i < nbt; ++i) {
+    hipLaunchKernelGGL(trtri_scale_kernel, dim3(i + 1), dim3(256), 0, s, (const double *)Dinv, X, Q, i);
+    if (i + 1 < nbt)
+      hipLaunchKernelGGL(trtri_update_kernel, dim3((nbt - 1 - i) * (i + 1)), dim3(256), 0, s, (const double *)K, X, Q,
+                         i);
   }
   // padding columns of K^{-1} are read (times zero) by the row-dot kernels: keep them zero
   (void)hipMemsetAsync(Kinv, 0, (size_t)q * ldk * sizeof(T), s);
