@@ -110,10 +110,11 @@ struct pogs_ctx {
     p.part = part;
     p.nbx = nbx;
     p.nby = nby;
-    p.s_mu = slots;
-    p.s_yh = slots + nbx;
-    p.s_pri = slots + nbx + nby;
-    p.s_dual = slots + nbx + nby + n_pri;
+    p.s_mu = slots;                    // 2 x nbx (by iteration parity)
+    p.s_yh = slots + 2 * nbx;          // 2 x nby
+    p.s_pri = slots + 2 * (nbx + nby);
+    p.s_dual = p.s_pri + n_pri;
+    p.par = 0;
     p.n_pri = n_pri;
     p.n_dual = n_dual;
     p.ctrl = ctrl;

@@ -321,10 +321,14 @@ __device__ inline void trtri_update_tile(const double *K, double *X, int Q, int 
   acc_store(acc, [&](int rr, int cc, double v) { C[(size_t)rr * Q + cc] -= v; });
 }
 
-// X <- I on the lower block triangle (upper blocks are never read).
+// X <- I on the lower block triangle, diagonal blocks included whole (the
+// block products read full 64 x 64 blocks; blocks above the diagonal are
+// never read).
 __device__ inline void trtri_init_rows(double *X, int Q, int row0, int row1) {
-  for (int i = row0; i < row1; ++i)
-    for (int j = threadIdx.x; j <= i; j += blockDim.x) X[(size_t)i * Q + j] = i == j ? 1.0 : 0.0;
+  for (int i = row0; i < row1; ++i) {
+    const int jend = (i / NB + 1) * NB;
+    for (int j = threadIdx.x; j < jend; j += blockDim.x) X[(size_t)i * Q + j] = i == j ? 1.0 : 0.0;
+  }
 }
 
 // K^{-1}_I,J = sum_{k >= I} X_k,I^T X_k,J for I >= J, written and mirrored as T

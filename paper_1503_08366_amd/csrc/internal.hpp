@@ -6,21 +6,29 @@
 
 namespace pogs {
 
-// Device control block of one solve: penalty, counters, stop flag and the
-// last residuals.  Written only by the final workgroup of each iteration.
-struct Ctrl {
-  double rho;       // current penalty rho^k
-  double rescale;   // factor applied to (x~, y~) by the next prox step
-  double r_pri, r_dual, eps_pri, eps_dual;
-  double eps_abs, eps_rel, alpha, delta, tau;
-  int k;            // iterations completed
+// Solver state between iterations (Algorithm 3 and the stop test).
+struct CtrlState {
+  double rho;       // penalty for the next prox step
+  double rescale;   // factor the next prox step applies to (x~, y~) (Section 3.2)
+  double r_pri, r_dual, eps_pri, eps_dual;  // residuals of the last finished iteration
+  int k;            // iterations whose stop test has run
   int l, u;         // Algorithm 3 markers
   int done;         // 0 running, else 1 + pogs status
+  int pending;      // 1: the partial sums of iteration k wait for their stop test
+  int pad;
+};
+
+// Device control block of one solve.  The state is double-buffered by the
+// parity of the iteration: the prox step of iteration i reads st[1 - i % 2]
+// (the state after iteration i - 1's kernels), runs iteration i - 1's stop
+// test and Algorithm 3 itself (every workgroup computes the same values from
+// the same partial sums; workgroup 0 stores them) and writes st[i % 2].  So
+// no separate control launch is needed per iteration.
+struct Ctrl {
+  double eps_abs, eps_rel, alpha, delta, tau;
   int max_iter;
   int adaptive;
-  int pad0, pad1;
-  unsigned cnt_a, cnt_b;  // last-workgroup counters
-  unsigned pad2, pad3;
+  CtrlState st[2];
 };
 
 // Separable function as device arrays (per element).
@@ -41,11 +49,12 @@ template <typename T> struct IterArgs {
   T *cx, *dy;            // projection inputs c = x_r + x~, d = y_r + y~
   T *rhs;                // right-hand side of the reduced system (length q)
   double *part;          // gemv_t split partials
-  double *s_mu, *s_yh;   // prox-block partial sums of mu_h^2, y_h^2
+  double *s_mu, *s_yh;   // prox-block partial sums of mu_h^2, y_h^2 (2 x nbx, 2 x nby: by parity)
   double *s_pri, *s_dual;// partial sums of the residuals
   int nbx, nby;          // prox blocks over x (n) and y (m)
   int n_pri, n_dual;     // number of residual partial slots
   Ctrl *ctrl;
+  int par;               // parity of this iteration (selects st[] and the prox slots)
 };
 
 // ---- launchers (setup.hip) ------------------------------------------------
@@ -83,6 +92,9 @@ template <typename T> void launch_scale_fn(const uint8_t *h, const double *a, co
                                            T *oa, T *ob, T *oc, T *od, T *oe, hipStream_t s);
 template <typename T> void launch_iteration(const IterArgs<T> &p, int splits, int rows_per_split,
                                             int ncolp, hipStream_t s);
+// Run the stop test of the last iteration of a launch sequence whose last
+// iteration had parity `par` (writes st[1 - par]); for the host's check.
+template <typename T> void launch_control_preview(const IterArgs<T> &p, int par, hipStream_t s);
 template <typename T> void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rows_per_split,
                                                  int ncolp, hipStream_t s);
 template <typename T> void launch_project(const IterArgs<T> &p, int splits, int rows_per_split,

@@ -1,6 +1,6 @@
 // One ADMM iteration of the single-problem pipeline on gfx950 (Algorithm 1 with
 // the Section 3.2 over-relaxation, Section 3.3 half-step duals, Section 3.4
-// residual stopping and Algorithm 3 adaptive rho), as five steps (six
+// residual stopping and Algorithm 3 adaptive rho), as four steps (five
 // launches: the pass that sums columns of A finishes in a second small kernel):
 //
 //   1. prox      : x_h = prox_g^(x - x~), y_h = prox_f^(y - y~), mu_h, nu_h,
@@ -11,8 +11,10 @@
 //                  m <  n: y = d + K^{-1} rhs, y~ = d - y
 //   4. pass 2    : m >= n: [y, t] = A [x, x_h] -> y~ = d - y, (t - y_h)^2
 //                  m <  n: [z, s] = A^T [y~, nu_h] -> x = c + z, x~ = c - x, (s + mu_h)^2
-//   5. control   : one workgroup sums every partial in a fixed order and runs
-//                  the stopping test and Algorithm 3.
+// The stop test and Algorithm 3 of iteration i run at the start of iteration
+// i + 1's prox step, in every workgroup, from the partial sums in a fixed order
+// (see Ctrl); a one-workgroup kernel runs it after the last iteration of a
+// launch sequence so the host can see the stop flag.
 //
 // The reduced update is the one of Section 3.5 with K = I + A^T A (m >= n) or
 // I + A A^T (m < n); K^{-1} is formed once from the float64 Cholesky factor.
@@ -25,74 +27,99 @@
 namespace pogs {
 
 // ---------------------------------------------------------------------------
-// Stopping test and adaptive penalty (run by one workgroup per iteration)
+// Stopping test and adaptive penalty for the iteration whose partial sums are
+// in the slots (Section 3.4, Algorithm 3).  Every thread of the workgroup
+// takes part in the fixed-order sums; `st` (LDS) is updated by thread 0 and
+// valid in every thread after the call.  Slots of the prox step are read from
+// parity `spar`.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ void control_step(const IterArgs<T> &p, double *lds) {
+__device__ void control_compute(const IterArgs<T> &p, int spar, CtrlState &st, double *lds) {
+  const double *s_mu = p.s_mu + (size_t)spar * p.nbx;
+  const double *s_yh = p.s_yh + (size_t)spar * p.nby;
   double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
-  for (int i = threadIdx.x; i < p.nbx; i += blockDim.x) a += load_agent(p.s_mu + i);
-  for (int i = threadIdx.x; i < p.nby; i += blockDim.x) b += load_agent(p.s_yh + i);
-  for (int i = threadIdx.x; i < p.n_pri; i += blockDim.x) c += load_agent(p.s_pri + i);
-  for (int i = threadIdx.x; i < p.n_dual; i += blockDim.x) d += load_agent(p.s_dual + i);
+  for (int i = threadIdx.x; i < p.nbx; i += blockDim.x) a += s_mu[i];
+  for (int i = threadIdx.x; i < p.nby; i += blockDim.x) b += s_yh[i];
+  for (int i = threadIdx.x; i < p.n_pri; i += blockDim.x) c += p.s_pri[i];
+  for (int i = threadIdx.x; i < p.n_dual; i += blockDim.x) d += p.s_dual[i];
   const double mu2 = block_sum(a, lds);
   const double yh2 = block_sum(b, lds);
   const double pri2 = block_sum(c, lds);
   const double dual2 = block_sum(d, lds);
-  if (threadIdx.x != 0) return;
-  Ctrl *q = p.ctrl;
-  const double r_pri = sqrt(pri2), r_dual = sqrt(dual2);
-  const double eps_pri = q->eps_abs + q->eps_rel * sqrt(yh2);
-  const double eps_dual = q->eps_abs + q->eps_rel * sqrt(mu2);
-  q->r_pri = r_pri;
-  q->r_dual = r_dual;
-  q->eps_pri = eps_pri;
-  q->eps_dual = eps_dual;
-  const int k = q->k;
-  double rescale = 1.0;
-  int done = 0;
-  if (!isfinite(r_pri) || !isfinite(r_dual)) {
-    done = 1 + POGS_NUMERICAL;
-  } else if (r_pri < eps_pri && r_dual < eps_dual) {
-    done = 1 + POGS_CONVERGED;
-  } else {
-    if (q->adaptive) {
-      const double rho = q->rho;
-      double rho_new = rho;
-      if (r_dual < eps_dual && q->tau * k > q->l) {
-        rho_new = q->delta * rho;
-        q->u = k;
-      } else if (r_pri < eps_pri && q->tau * k > q->u) {
-        rho_new = rho / q->delta;
-        q->l = k;
+  if (threadIdx.x == 0) {
+    const Ctrl &q = *p.ctrl;
+    const double r_pri = sqrt(pri2), r_dual = sqrt(dual2);
+    const double eps_pri = q.eps_abs + q.eps_rel * sqrt(yh2);
+    const double eps_dual = q.eps_abs + q.eps_rel * sqrt(mu2);
+    st.r_pri = r_pri;
+    st.r_dual = r_dual;
+    st.eps_pri = eps_pri;
+    st.eps_dual = eps_dual;
+    const int k = st.k;
+    double rescale = 1.0;
+    int done = 0;
+    if (!isfinite(r_pri) || !isfinite(r_dual)) {
+      done = 1 + POGS_NUMERICAL;
+    } else if (r_pri < eps_pri && r_dual < eps_dual) {
+      done = 1 + POGS_CONVERGED;
+    } else {
+      if (q.adaptive) {
+        const double rho = st.rho;
+        double rho_new = rho;
+        if (r_dual < eps_dual && q.tau * k > st.l) {
+          rho_new = q.delta * rho;
+          st.u = k;
+        } else if (r_pri < eps_pri && q.tau * k > st.u) {
+          rho_new = rho / q.delta;
+          st.l = k;
+        }
+        if (rho_new != rho) {
+          rescale = rho / rho_new;
+          st.rho = rho_new;
+        }
       }
-      if (rho_new != rho) {
-        rescale = rho / rho_new;
-        q->rho = rho_new;
-      }
+      if (k + 1 >= q.max_iter) done = 1 + POGS_MAXITER;
     }
-    if (k + 1 >= q->max_iter) done = 1 + POGS_MAXITER;
+    st.rescale = rescale;
+    st.k = k + 1;
+    st.done = done;
+    st.pending = 0;
   }
-  q->rescale = rescale;
-  q->k = k + 1;
-  q->done = done;
+  __syncthreads();
 }
 
+// Stop test of the last iteration of a launch sequence (parity `par`), so the
+// host sees the flag; the next prox step recomputes the same state (a pure
+// function of the stored state and the partial sums).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void control_kernel(IterArgs<T> p) {
+__global__ __launch_bounds__(kBlock) void control_preview_kernel(IterArgs<T> p, int par) {
   __shared__ double bs[kBlock / kWave];
-  if (p.ctrl->done) return;
-  control_step(p, bs);
+  __shared__ CtrlState st;
+  if (threadIdx.x == 0) st = p.ctrl->st[par];
+  __syncthreads();
+  if (!st.done && st.pending) control_compute(p, par, st, bs);
+  if (threadIdx.x == 0) p.ctrl->st[1 - par] = st;
 }
 
 // ---------------------------------------------------------------------------
-// 1. prox step
+// 1. prox step (runs the previous iteration's stop test first)
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void prox_kernel(IterArgs<T> p) {
   __shared__ double bs[kBlock / kWave];
-  if (p.ctrl->done) return;
-  const T rho = (T)p.ctrl->rho;
-  const T resc = (T)p.ctrl->rescale;
+  __shared__ CtrlState st;
+  const int par = p.par;
+  if (threadIdx.x == 0) st = p.ctrl->st[1 - par];
+  __syncthreads();
+  if (!st.done && st.pending) control_compute(p, 1 - par, st, bs);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    CtrlState out = st;
+    out.pending = st.done ? 0 : 1;
+    p.ctrl->st[par] = out;
+  }
+  if (st.done) return;
+  const T rho = (T)st.rho;
+  const T resc = (T)st.rescale;
   const T alpha = (T)p.ctrl->alpha;
   const bool xs = (int)blockIdx.x < p.nbx;
   const int blk = xs ? blockIdx.x : blockIdx.x - p.nbx;
@@ -119,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void prox_kernel(IterArgs<T> p) {
     contrib = xs ? (double)dual * (double)dual : (double)h * (double)h;
   }
   const double s = block_sum(contrib, bs);
-  if (threadIdx.x == 0) (xs ? p.s_mu[blk] : p.s_yh[blk]) = s;
+  if (threadIdx.x == 0) (xs ? p.s_mu + (size_t)par * p.nbx : p.s_yh + (size_t)par * p.nby)[blk] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -127,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void prox_kernel(IterArgs<T> p) {
 // ---------------------------------------------------------------------------
 template <typename T> struct EpiBase {
   IterArgs<T> p;
-  __device__ bool skip() const { return p.ctrl->done != 0; }
+  __device__ bool skip() const { return p.ctrl->st[p.par].done != 0; }
 };
 
 // m >= n, pass 1: [w, s] = A^T [d, nu_h]
@@ -326,7 +353,7 @@ int gemv_n_blocks(int m, int ncols, int elem_size, int) {
   return cdiv(m, rows1) > 2048 ? (int)cdiv(m, gemv_n_rows_per_block<16, 4>()) : (int)cdiv(m, rows1);
 }
 
-// which: 0 prox, 1 first pass over A, 2 solve, 3 second pass over A, 4 control.
+// which: 0 prox (with the previous stop test), 1 first pass over A, 2 solve, 3 second pass over A.
 template <typename T>
 void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps, int ncolp, hipStream_t s) {
   const bool tall = p.m >= p.n;
@@ -352,9 +379,6 @@ void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps,
         gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, e, s);
       }
       break;
-    case 4:
-      hipLaunchKernelGGL(control_kernel<T>, dim3(1), dim3(kBlock), 0, s, p);
-      break;
     default:
       if (tall) {
         EpiTallPass2<T> e{{p}};
@@ -369,7 +393,11 @@ void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps,
 
 template <typename T>
 void launch_iteration(const IterArgs<T> &p, int splits, int rps, int ncolp, hipStream_t s) {
-  for (int w = 0; w < 5; ++w) launch_iteration_part<T>(p, w, splits, rps, ncolp, s);
+  for (int w = 0; w < 4; ++w) launch_iteration_part<T>(p, w, splits, rps, ncolp, s);
+}
+
+template <typename T> void launch_control_preview(const IterArgs<T> &p, int par, hipStream_t s) {
+  hipLaunchKernelGGL(control_preview_kernel<T>, dim3(1), dim3(kBlock), 0, s, p, par);
 }
 
 template <typename T>
@@ -492,6 +520,7 @@ void launch_prox_eval(const uint8_t *h, const T *a, const T *b, const T *c, cons
 #define POGS_INST(T)                                                                                   \
   template void launch_iteration<T>(const IterArgs<T> &, int, int, int, hipStream_t);                  \
   template void launch_iteration_part<T>(const IterArgs<T> &, int, int, int, int, hipStream_t);        \
+  template void launch_control_preview<T>(const IterArgs<T> &, int, hipStream_t);                      \
   template void launch_project<T>(const IterArgs<T> &, int, int, int, const T *, const T *, T *, T *,  \
                                   hipStream_t);                                                        \
   template void launch_scale_fn<T>(const uint8_t *, const double *, const double *, const double *,    \

@@ -149,7 +149,8 @@ template <typename T> int alloc_iteration(pogs_ctx *c) {
   c->nby = (int)cdiv(m, kBlock);
   c->n_pri = gemv_n_blocks(m, n, sizeof(T), 0);
   c->n_dual = (int)cdiv(n, kFinishCols);
-  const int nslots = c->nbx + c->nby + c->n_pri + c->n_dual + c->nbx + c->nby;  // + unscale slots
+  // prox sums (two parities), residual sums, then the unscale kernel's sums
+  const int nslots = 2 * (c->nbx + c->nby) + c->n_pri + c->n_dual + c->nbx + c->nby;
   if ((rc = c->arena.alloc((void **)&c->slots, (size_t)nslots * 8))) return rc;
   const int ntiles = (int)cdiv(n, gemv_t_tile(sizeof(T)));
   if ((rc = c->arena.alloc((void **)&c->counters, (size_t)(ntiles + 64) * sizeof(unsigned)))) return rc;
@@ -238,16 +239,27 @@ template <typename T> int upload_fns(pogs_ctx *c, const HostFn &f, const HostFn 
   return POGS_OK;
 }
 
+// Iterations per captured launch sequence: positive and even (the control
+// state alternates between two buffers by iteration parity).
+int even_chunk(int requested) {
+  const int c = requested > 0 ? requested : 20;
+  return c + (c & 1);
+}
+
 template <typename T> int ensure_graph(pogs_ctx *c, int chunk) {
   if (c->graph && c->graph_chunk == chunk) return POGS_OK;
   if (c->graph) {
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
   }
-  const IterArgs<T> p = c->iter_args<T>();
+  IterArgs<T> p = c->iter_args<T>();
   hipGraph_t g;
   POGS_HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  for (int i = 0; i < chunk; ++i) launch_iteration<T>(p, c->splits, c->rps, c->ncolp, c->stream);
+  for (int i = 0; i < chunk; ++i) {  // chunk is even: iteration parity is i % 2
+    p.par = i & 1;
+    launch_iteration<T>(p, c->splits, c->rps, c->ncolp, c->stream);
+  }
+  launch_control_preview<T>(p, 1, c->stream);  // state after the chunk lands in st[0]
   POGS_HIP_TRY(hipStreamEndCapture(c->stream, &g));
   hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -266,8 +278,6 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   // zero state (Algorithm 1 starts from x = y = x~ = y~ = 0)
   POGS_HIP_TRY(hipMemsetAsync(c->vec, 0, c->vec_elems() * sizeof(T), s));
   Ctrl h{};
-  h.rho = p.rho0;
-  h.rescale = 1.0;
   h.eps_abs = p.eps_abs;
   h.eps_rel = p.eps_rel;
   h.alpha = p.alpha;
@@ -275,19 +285,23 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   h.tau = p.tau;
   h.max_iter = p.max_iter;
   h.adaptive = p.adaptive_rho ? 1 : 0;
+  for (int b = 0; b < 2; ++b) {  // iteration 0 reads st[1]: no stop test pending
+    h.st[b].rho = p.rho0;
+    h.st[b].rescale = 1.0;
+  }
   *c->ctrl_host = h;
   POGS_HIP_TRY(hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
-  const int chunk = std::max(1, p.chunk_iters > 0 ? p.chunk_iters : 20);
+  const int chunk = even_chunk(p.chunk_iters);
   if ((rc = ensure_graph<T>(c, chunk))) return rc;
   for (;;) {
     POGS_HIP_TRY(hipGraphLaunch(c->graph, s));
     POGS_HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     POGS_HIP_TRY(hipStreamSynchronize(s));
+    const CtrlState &cs = c->ctrl_host->st[0];
     if (p.verbose)
-      fprintf(stderr, "pogs: k=%d r_pri=%.3e eps_pri=%.3e r_dual=%.3e eps_dual=%.3e rho=%.4g\n", c->ctrl_host->k,
-              c->ctrl_host->r_pri, c->ctrl_host->eps_pri, c->ctrl_host->r_dual, c->ctrl_host->eps_dual,
-              c->ctrl_host->rho);
-    if (c->ctrl_host->done) break;
+      fprintf(stderr, "pogs: k=%d r_pri=%.3e eps_pri=%.3e r_dual=%.3e eps_dual=%.3e rho=%.4g\n", cs.k, cs.r_pri,
+              cs.eps_pri, cs.r_dual, cs.eps_dual, cs.rho);
+    if (cs.done) break;
   }
   // unscale into the caller's buffers (device) or staging (host)
   const IterArgs<T> ia = c->iter_args<T>();
@@ -300,7 +314,7 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   }
   double *fa = c->f0, *ga = c->g0;
   launch_unscale<T>(ia, c->D, c->E, c->fh0, fa, fa + m, fa + 2 * m, fa + 3 * m, fa + 4 * m, c->gh0, ga, ga + n,
-                    ga + 2 * n, ga + 3 * n, ga + 4 * n, xo, yo, muo, nuo, c->slots + ia.nbx + ia.nby + ia.n_pri + ia.n_dual,
+                    ga + 2 * n, ga + 3 * n, ga + 4 * n, xo, yo, muo, nuo, c->slots + 2 * (ia.nbx + ia.nby) + ia.n_pri + ia.n_dual,
                     c->obj_dev, c->counters + (int)cdiv(n, gemv_t_tile(sizeof(T))) + 8, s);
   POGS_HIP_TRY(hipMemcpyAsync(c->obj_host, c->obj_dev, sizeof(double), hipMemcpyDeviceToHost, s));
   if (out->mem == POGS_HOST) {
@@ -311,7 +325,7 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   }
   POGS_HIP_TRY(hipStreamSynchronize(s));
   POGS_HIP_TRY(hipGetLastError());
-  const Ctrl &r = *c->ctrl_host;
+  const CtrlState &r = c->ctrl_host->st[0];
   out->optval = *c->obj_host;
   out->r_pri = r.r_pri;
   out->r_dual = r.r_dual;
@@ -329,8 +343,6 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
 template <typename T> int profile_impl(pogs_ctx *c, int reps, double *ms) {
   hipStream_t s = c->stream;
   Ctrl h{};
-  h.rho = 1.0;
-  h.rescale = 1.0;
   h.eps_abs = 0.0;  // stop test never passes
   h.eps_rel = 0.0;
   h.alpha = c->params.alpha;
@@ -338,9 +350,13 @@ template <typename T> int profile_impl(pogs_ctx *c, int reps, double *ms) {
   h.tau = c->params.tau;
   h.max_iter = 0x7fffffff;
   h.adaptive = 0;
+  for (int b = 0; b < 2; ++b) {
+    h.st[b].rho = 1.0;
+    h.st[b].rescale = 1.0;
+  }
   *c->ctrl_host = h;
   POGS_HIP_TRY(hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
-  const int chunk = std::max(1, c->params.chunk_iters > 0 ? c->params.chunk_iters : 20);
+  const int chunk = even_chunk(c->params.chunk_iters);
   int rc;
   if ((rc = ensure_graph<T>(c, chunk))) return rc;
   hipEvent_t e0, e1;
