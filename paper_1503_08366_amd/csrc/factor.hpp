@@ -19,8 +19,10 @@ struct F64Stage {             // 16.9 KB
   double a[16][LSF];
   double b[16][LSF];
 };
-struct CholLds {              // 33.8 KB
-  double L[NB][NB + 2];
+struct CholLds {              // 68.6 KB
+  double L[NB][NB + 1];
+  double X[NB][NB + 1];
+  double red[4][NB];
 };
 constexpr int kGramTB = 128;  // f32 Gram tile
 struct GramStage {            // 16.9 KB
@@ -219,60 +221,67 @@ template <class Fn> __device__ inline void acc_store(const F64Acc acc[2][2], Fn 
 }
 
 // Factor diagonal block kb of K (Q x Q, row-major, lower) and invert the
-// factor, with one wave: the block sits in LDS; lane r owns row r and runs the
-// left-looking Cholesky (column j: L_rj = (K_rj - sum_{k<j} L_rk L_jk) / L_jj,
-// the pivot broadcast from lane j); then lane c solves L x = e_c by forward
-// substitution with x in registers, giving column c of L^{-1}.  Writes L_kk
-// (upper part zeroed) back into K and L_kk^{-1} into Dinv block kb.  A
-// non-positive pivot counts in *bad and is replaced by 1.  LDS operations of
-// one wave complete in issue order, so the steps need no barrier, only a
-// compiler fence.
+// factor, in LDS with the whole workgroup (4 waves).  Left-looking Cholesky:
+// at step j, row r needs v_r = K_rj - sum_{k<j} L_rk L_jk; wave w sums the
+// terms k in [16w, 16w + 16), wave 0 adds the four partial sums in wave order,
+// takes the pivot L_jj = sqrt(v_j) from lane j and stores L_rj = v_r / L_jj.
+// The inverse X = L^{-1} is built row by row the same way:
+// X_rc = (delta_rc - sum_{c<=q<r} L_rq X_qc) / L_rr for all columns c at once.
+// Writes L_kk (upper part zeroed) back into K and L_kk^{-1} into Dinv block
+// kb.  A non-positive pivot counts in *bad and is replaced by 1.
 __device__ inline void potrf_diag(double *K, int Q, int kb, double *Dinv, unsigned *bad, CholLds &s) {
   const int t = threadIdx.x;
+  const int lane = t & 63, part = t >> 6;
   double *blk = K + (size_t)kb * NB * Q + (size_t)kb * NB;
   for (int e = t; e < NB * NB; e += blockDim.x) s.L[e / NB][e % NB] = blk[(size_t)(e / NB) * Q + e % NB];
   __syncthreads();
-  if (t < NB) {
-    const int r = t;
-    for (int j = 0; j < NB; ++j) {
-      double a0 = 0.0, a1 = 0.0;
-      int k = 0;
-      for (; k + 1 < j; k += 2) {
-        a0 = fma(s.L[r][k], s.L[j][k], a0);
-        a1 = fma(s.L[r][k + 1], s.L[j][k + 1], a1);
-      }
-      if (k < j) a0 = fma(s.L[r][k], s.L[j][k], a0);
-      const double v = s.L[r][j] - (a0 + a1);
+  const int k0 = part * 16;
+  unsigned nbad = 0;
+  for (int j = 0; j < NB; ++j) {
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 2) {
+      if (k0 + kk < j) a0 = fma(s.L[lane][k0 + kk], s.L[j][k0 + kk], a0);
+      if (k0 + kk + 1 < j) a1 = fma(s.L[lane][k0 + kk + 1], s.L[j][k0 + kk + 1], a1);
+    }
+    s.red[part][lane] = a0 + a1;
+    __syncthreads();
+    if (part == 0) {
+      const double v = s.L[lane][j] - ((s.red[0][lane] + s.red[1][lane]) + (s.red[2][lane] + s.red[3][lane]));
       double piv = __shfl(v, j, 64);
-      const bool badp = !(piv > 0.0) || !isfinite(piv);
-      if (badp) piv = 1.0;
-      const double d = sqrt(piv);
-      if (r == j) s.L[r][j] = d;
-      else if (r > j) s.L[r][j] = v / d;
-      if (badp && r == 0) atomicAdd(bad, 1u);
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    }
-    // column c = r of L^{-1}
-    double x[NB];
-#pragma unroll
-    for (int rr = 0; rr < NB; ++rr) {
-      double b0 = 0.0, b1 = 0.0;
-#pragma unroll
-      for (int q = 0; q + 1 < rr; q += 2) {
-        b0 = fma(s.L[rr][q], x[q], b0);
-        b1 = fma(s.L[rr][q + 1], x[q + 1], b1);
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        ++nbad;
+        piv = 1.0;
       }
-      if (rr & 1) b0 = fma(s.L[rr][rr - 1], x[rr - 1], b0);
-      x[rr] = ((rr == r ? 1.0 : 0.0) - (b0 + b1)) / s.L[rr][rr];
+      const double d = sqrt(piv);
+      if (lane == j) s.L[lane][j] = d;
+      else if (lane > j) s.L[lane][j] = v / d;
     }
-    double *dv = Dinv + (size_t)kb * NB * NB;
-#pragma unroll
-    for (int rr = 0; rr < NB; ++rr) dv[rr * NB + r] = x[rr];
+    __syncthreads();
   }
-  __syncthreads();
+  if (nbad && t == 0) atomicAdd(bad, nbad);
+  for (int rr = 0; rr < NB; ++rr) {
+    // partial sums over q in [16 part, 16 part + 16) with c <= q < rr, column c = lane
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 2) {
+      const int q0 = k0 + kk, q1 = q0 + 1;
+      if (q0 < rr && q0 >= lane) a0 = fma(s.L[rr][q0], s.X[q0][lane], a0);
+      if (q1 < rr && q1 >= lane) a1 = fma(s.L[rr][q1], s.X[q1][lane], a1);
+    }
+    s.red[part][lane] = a0 + a1;
+    __syncthreads();
+    if (part == 0) {
+      const double acc = (s.red[0][lane] + s.red[1][lane]) + (s.red[2][lane] + s.red[3][lane]);
+      s.X[rr][lane] = lane > rr ? 0.0 : ((rr == lane ? 1.0 : 0.0) - acc) / s.L[rr][rr];
+    }
+    __syncthreads();
+  }
+  double *dv = Dinv + (size_t)kb * NB * NB;
   for (int e = t; e < NB * NB; e += blockDim.x) {
     const int r = e / NB, c = e % NB;
     blk[(size_t)r * Q + c] = c <= r ? s.L[r][c] : 0.0;
+    dv[e] = s.X[r][c];
   }
   __syncthreads();
 }
