@@ -11,7 +11,7 @@ namespace pogs {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
-constexpr int kFinishCols = 64;  // columns per workgroup when split column sums are finished
+constexpr int kFinishCols = 16;  // columns per workgroup when split column sums are finished
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }

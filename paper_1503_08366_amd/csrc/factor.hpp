@@ -15,14 +15,14 @@ namespace pogs {
 constexpr int NB = 64;        // Cholesky block size
 constexpr int LSF = NB + 2;   // row stride of the float64 LDS stages
 
-struct F64Stage {             // 16.9 KB
-  double a[16][LSF];
-  double b[16][LSF];
+constexpr int KCF = 64;       // k depth of one float64 block-product stage
+struct F64Stage {             // 67.6 KB
+  double a[KCF][LSF];
+  double b[KCF][LSF];
 };
-struct CholLds {              // 68.6 KB
+struct CholLds {              // 66.6 KB
   double L[NB][NB + 1];
   double X[NB][NB + 1];
-  double red[4][NB];
 };
 constexpr int kGramTB = 128;  // f32 Gram tile
 struct GramStage {            // 16.9 KB
@@ -189,25 +189,68 @@ __device__ void gemm_tile_f32(const float *__restrict__ A, int lda, int M, const
         out(wi * 64 + i * 16 + 4 * (lane >> 4) + r, wj * 64 + j * 16 + (lane & 15), acc[i][j][r]);
 }
 
+// One 64 (k) x 64 (index) chunk of op(k, x) = p[k * sk + x * sx], with
+// either sx == 1 (contiguous along x) or sk == 1 (contiguous along k), as
+// eight 16-byte loads per thread (every base address and stride is even).
+struct F64Chunk {
+  double2 v[8];
+};
+
+__device__ inline void chunk_load(F64Chunk &c, const double *p, int64_t sk, int64_t sx) {
+  const int t = threadIdx.x;
+  const int outer = t >> 5, pr = (t & 31) * 2;
+  if (sx == 1) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) c.v[r] = *reinterpret_cast<const double2 *>(p + (int64_t)(outer + 8 * r) * sk + pr);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) c.v[r] = *reinterpret_cast<const double2 *>(p + (int64_t)(outer + 8 * r) * sx + pr);
+  }
+}
+
+// Store a loaded chunk k-major: s[k][x].
+__device__ inline void chunk_store(const F64Chunk &c, double (*s)[LSF], bool xcontig) {
+  const int t = threadIdx.x;
+  const int outer = t >> 5, pr = (t & 31) * 2;
+  if (xcontig) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) *reinterpret_cast<double2 *>(&s[outer + 8 * r][pr]) = c.v[r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      s[pr][outer + 8 * r] = c.v[r].x;
+      s[pr + 1][outer + 8 * r] = c.v[r].y;
+    }
+  }
+}
+
 // acc += sum_{k < K} opA(i, k) opB(k, j) for a 64 x 64 float64 tile, with
-// opA(i, k) = pa[i * sai + k * sak], opB(k, j) = pb[k * sbk + j * sbj]
-// (K a multiple of 16).  Ends with a barrier: the stages may be reused and
+// opA(i, k) = pa[i * sai + k * sak], opB(k, j) = pb[k * sbk + j * sbj],
+// each operand contiguous along one of its two indices, K a multiple of 64.
+// Stages of 64 k; the next stage is loaded into registers while the MFMAs
+// of the current one run.  Ends with a barrier: the stages may be reused and
 // the operands overwritten afterwards.
 __device__ inline void block_product(F64Acc acc[2][2], const double *pa, int64_t sai, int64_t sak, const double *pb,
                                      int64_t sbk, int64_t sbj, int K, F64Stage &st) {
-  const int t = threadIdx.x, w = t >> 6;
+  const int w = threadIdx.x >> 6;
   const int wi = w >> 1, wj = w & 1;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int f = t; f < 16 * NB; f += 256) {
-      const int k = f / NB, i = f % NB;
-      st.a[k][i] = pa[(int64_t)i * sai + (int64_t)(k0 + k) * sak];
-      st.b[k][i] = pb[(int64_t)(k0 + k) * sbk + (int64_t)i * sbj];
+  const bool a_icontig = sai == 1, b_jcontig = sbj == 1;
+  F64Chunk ca, cb;
+  chunk_load(ca, pa, sak, sai);
+  chunk_load(cb, pb, sbk, sbj);
+  for (int k0 = 0; k0 < K; k0 += KCF) {
+    if (k0) __syncthreads();
+    chunk_store(ca, st.a, a_icontig);
+    chunk_store(cb, st.b, b_jcontig);
+    __syncthreads();
+    if (k0 + KCF < K) {
+      chunk_load(ca, pa + (int64_t)(k0 + KCF) * sak, sak, sai);
+      chunk_load(cb, pb + (int64_t)(k0 + KCF) * sbk, sbk, sbj);
     }
-    __syncthreads();
 #pragma unroll
-    for (int k4 = 0; k4 < 16; k4 += 4) f64_tile_step<LSF>(acc, st.a, st.b, k4, wi * 32, wj * 32);
-    __syncthreads();
+    for (int k4 = 0; k4 < KCF; k4 += 4) f64_tile_step<LSF>(acc, st.a, st.b, k4, wi * 32, wj * 32);
   }
+  __syncthreads();
 }
 
 __device__ inline void acc_zero(F64Acc acc[2][2]) {
@@ -220,68 +263,133 @@ template <class Fn> __device__ inline void acc_store(const F64Acc acc[2][2], Fn 
   f64_tile_store(acc, (w >> 1) * 32, (w & 1) * 32, fn);
 }
 
-// Factor diagonal block kb of K (Q x Q, row-major, lower) and invert the
-// factor, in LDS with the whole workgroup (4 waves).  Left-looking Cholesky:
-// at step j, row r needs v_r = K_rj - sum_{k<j} L_rk L_jk; wave w sums the
-// terms k in [16w, 16w + 16), wave 0 adds the four partial sums in wave order,
-// takes the pivot L_jj = sqrt(v_j) from lane j and stores L_rj = v_r / L_jj.
-// The inverse X = L^{-1} is built row by row the same way:
-// X_rc = (delta_rc - sum_{c<=q<r} L_rq X_qc) / L_rr for all columns c at once.
-// Writes L_kk (upper part zeroed) back into K and L_kk^{-1} into Dinv block
-// kb.  A non-positive pivot counts in *bad and is replaced by 1.
-__device__ inline void potrf_diag(double *K, int Q, int kb, double *Dinv, unsigned *bad, CholLds &s) {
-  const int t = threadIdx.x;
-  const int lane = t & 63, part = t >> 6;
+// Value of v in lane l (l uniform), as two 32-bit lane reads.
+__device__ inline double lane_bcast(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// acc += sum_{k < 16} a(i, k) b(k, j) for one 16 x 16 block (one wave,
+// f64 MFMA 16x16x4); result element r of lane l is (4 r + l / 16, l % 16).
+template <class FA, class FB> __device__ inline F64Acc mfma_block16(F64Acc acc, FA a, FB b) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int k4 = 0; k4 < 16; k4 += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a(i, k4 + kq), b(k4 + kq, i), acc, 0, 0, 0);
+  return acc;
+}
+
+// Factor diagonal block kb of K (Q x Q, row-major, lower part used) and
+// invert the factor, in LDS with the whole workgroup (4 waves).  The 64 x 64
+// block is factored recursively over 16 x 16 sub-blocks s = 0..3:
+//   leaf:   L_ss = chol(B_ss) and W_s = L_ss^{-1}, in the registers of every
+//           wave (row r of L_ss and column r of W_s in lane r % 16; the values
+//           other rows need are read from their lanes), no LDS round trips
+//           inside the 16-step chains;
+//   panel:  L_rs = B_rs W_s^T for the row blocks r > s (f64 MFMA, one wave per block);
+//   update: B_IJ -= L_Is L_Js^T for s < J <= I (f64 MFMA).
+// Then X = L^{-1} by block diagonals: X_ii = W_i, and for i > j
+// X_ij = -W_i sum_{j <= k < i} L_ik X_kj, the partial sums parked in the
+// (unused) upper blocks of X.  Writes L_kk (upper part zeroed) back into K and
+// L_kk^{-1} into Dinv block kb.  A non-positive pivot counts in *bad and is
+// replaced by 1.
+__device__ __forceinline__ void potrf_diag(double *K, int Q, int kb, double *Dinv, unsigned *bad, CholLds &s) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
   double *blk = K + (size_t)kb * NB * Q + (size_t)kb * NB;
   for (int e = t; e < NB * NB; e += blockDim.x) s.L[e / NB][e % NB] = blk[(size_t)(e / NB) * Q + e % NB];
   __syncthreads();
-  const int k0 = part * 16;
   unsigned nbad = 0;
-  for (int j = 0; j < NB; ++j) {
-    double a0 = 0.0, a1 = 0.0;
+  for (int sb = 0; sb < 4; ++sb) {
+    const int s0 = sb * 16;
+    // leaf (every wave computes the same values)
+    double a[16], x[16];
+    double rdiag = 0.0;  // 1 / L_jj, kept in lane j
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 2) {
-      if (k0 + kk < j) a0 = fma(s.L[lane][k0 + kk], s.L[j][k0 + kk], a0);
-      if (k0 + kk + 1 < j) a1 = fma(s.L[lane][k0 + kk + 1], s.L[j][k0 + kk + 1], a1);
-    }
-    s.red[part][lane] = a0 + a1;
-    __syncthreads();
-    if (part == 0) {
-      const double v = s.L[lane][j] - ((s.red[0][lane] + s.red[1][lane]) + (s.red[2][lane] + s.red[3][lane]));
-      double piv = __shfl(v, j, 64);
+    for (int k = 0; k < 16; ++k) a[k] = s.L[s0 + r16][s0 + k];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      double piv = lane_bcast(a[j], j);
       if (!(piv > 0.0) || !isfinite(piv)) {
         ++nbad;
         piv = 1.0;
       }
       const double d = sqrt(piv);
-      if (lane == j) s.L[lane][j] = d;
-      else if (lane > j) s.L[lane][j] = v / d;
+      const double rd = 1.0 / d;
+      if (r16 == j) rdiag = rd;
+      const double lj = r16 == j ? d : a[j] * rd;
+      a[j] = lj;
+#pragma unroll
+      for (int k = j + 1; k < 16; ++k) a[k] = fma(-lj, lane_bcast(lj, k), a[k]);
+    }
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      double acc = r16 == rr ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < rr; ++k) acc = fma(-lane_bcast(a[k], rr), x[k], acc);
+      x[rr] = acc * lane_bcast(rdiag, rr);
+    }
+    if (w == 0 && lane < 16) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s.L[s0 + lane][s0 + k] = a[k];
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) s.X[s0 + rr][s0 + lane] = x[rr];
+    }
+    __syncthreads();
+    // panel
+    const int nrb = 3 - sb;
+    if (w < nrb) {
+      const int rb = (sb + 1 + w) * 16;
+      F64Acc acc = mfma_block16(
+          f64acc_zero(), [&](int i, int k) { return s.L[rb + i][s0 + k]; },
+          [&](int k, int j) { return s.X[s0 + j][s0 + k]; });
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s.L[rb + 4 * r + q4][s0 + r16] = acc[r];
+    }
+    __syncthreads();
+    // trailing update of the lower blocks
+    const int ntr = nrb * (nrb + 1) / 2;
+    for (int b = w; b < ntr; b += 4) {
+      const int ii = b >= 3 ? 2 : (b >= 1 ? 1 : 0);
+      const int I = (sb + 1 + ii) * 16, J = (sb + 1 + b - ii * (ii + 1) / 2) * 16;
+      F64Acc acc = mfma_block16(
+          f64acc_zero(), [&](int i, int k) { return s.L[I + i][s0 + k]; },
+          [&](int k, int j) { return s.L[J + j][s0 + k]; });
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s.L[I + 4 * r + q4][J + r16] -= acc[r];
+    }
+    __syncthreads();
+  }
+  // X = L^{-1}: block diagonal d = i - j, pairs (i, j) one per wave
+  for (int d = 1; d < 4; ++d) {
+    const bool mine = w < 4 - d;
+    const int i = (d + w) * 16, j = w * 16;
+    if (mine) {
+      F64Acc acc = f64acc_zero();
+      for (int k = j; k < i; k += 16)
+        acc = mfma_block16(
+            acc, [&](int ii, int kk) { return s.L[i + ii][k + kk]; },
+            [&](int kk, int jj) { return s.X[k + kk][j + jj]; });
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s.X[j + 4 * r + q4][i + r16] = acc[r];  // T_ij, parked in block (j, i)
+    }
+    __syncthreads();
+    if (mine) {
+      F64Acc acc = mfma_block16(
+          f64acc_zero(), [&](int ii, int kk) { return s.X[i + ii][i + kk]; },
+          [&](int kk, int jj) { return s.X[j + kk][i + jj]; });
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s.X[i + 4 * r + q4][j + r16] = -acc[r];
     }
     __syncthreads();
   }
   if (nbad && t == 0) atomicAdd(bad, nbad);
-  for (int rr = 0; rr < NB; ++rr) {
-    // partial sums over q in [16 part, 16 part + 16) with c <= q < rr, column c = lane
-    double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 2) {
-      const int q0 = k0 + kk, q1 = q0 + 1;
-      if (q0 < rr && q0 >= lane) a0 = fma(s.L[rr][q0], s.X[q0][lane], a0);
-      if (q1 < rr && q1 >= lane) a1 = fma(s.L[rr][q1], s.X[q1][lane], a1);
-    }
-    s.red[part][lane] = a0 + a1;
-    __syncthreads();
-    if (part == 0) {
-      const double acc = (s.red[0][lane] + s.red[1][lane]) + (s.red[2][lane] + s.red[3][lane]);
-      s.X[rr][lane] = lane > rr ? 0.0 : ((rr == lane ? 1.0 : 0.0) - acc) / s.L[rr][rr];
-    }
-    __syncthreads();
-  }
   double *dv = Dinv + (size_t)kb * NB * NB;
   for (int e = t; e < NB * NB; e += blockDim.x) {
     const int r = e / NB, c = e % NB;
     blk[(size_t)r * Q + c] = c <= r ? s.L[r][c] : 0.0;
-    dv[e] = s.X[r][c];
+    dv[e] = (c >> 4) > (r >> 4) ? 0.0 : s.X[r][c];
   }
   __syncthreads();
 }

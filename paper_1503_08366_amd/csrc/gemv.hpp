@@ -107,23 +107,25 @@ __global__ __launch_bounds__(kBlock) void gemv_t_kernel(
   }
 }
 
-// Sum the split partials of 64 columns (block blockIdx.x): each of the four
-// waves sums every fourth split, then the four sums are added in wave order
-// (a fixed order, so results are deterministic); each column is finished by
-// the epilogue and the block's sum goes to tile_done(blockIdx.x, .).
+// Sum the split partials of kFinishCols columns (block blockIdx.x): the
+// threads form kBlock / kFinishCols split groups, group g sums the splits
+// g, g + groups, ...; the group sums are then added in group order (a fixed
+// order, so results are deterministic); each column is finished by the
+// epilogue and the block's sum goes to tile_done(blockIdx.x, .).
 template <int NRHS, class Epi>
 __global__ __launch_bounds__(kBlock) void gemv_t_finish_kernel(int n, int splits, const double *__restrict__ part,
                                                                 int ncolp, Epi epi) {
-  __shared__ double red[4][2][kFinishCols];
+  constexpr int G = kBlock / kFinishCols;
+  __shared__ double red[G][2][kFinishCols];
   __shared__ double bs[kBlock / kWave];
   if (epi.skip()) return;
-  const int c = threadIdx.x & (kFinishCols - 1);
-  const int g = threadIdx.x >> 6;
+  const int c = threadIdx.x % kFinishCols;
+  const int g = threadIdx.x / kFinishCols;
   const int cg = blockIdx.x * kFinishCols + c;
   double s[2] = {0.0, 0.0};
   if (cg < ncolp) {
 #pragma unroll 4
-    for (int sp = g; sp < splits; sp += 4)
+    for (int sp = g; sp < splits; sp += G)
 #pragma unroll
       for (int r = 0; r < NRHS; ++r) s[r] += part[(size_t)(sp * NRHS + r) * ncolp + cg];
   }
@@ -132,8 +134,12 @@ __global__ __launch_bounds__(kBlock) void gemv_t_finish_kernel(int n, int splits
   __syncthreads();
   double contrib = 0.0;
   if (g == 0 && cg < n) {
-    const double t0 = (red[0][0][c] + red[1][0][c]) + (red[2][0][c] + red[3][0][c]);
-    const double t1 = (red[0][1][c] + red[1][1][c]) + (red[2][1][c] + red[3][1][c]);
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      t0 += red[k][0][c];
+      t1 += red[k][1][c];
+    }
     contrib = epi.column(cg, t0, t1);
   }
   const double tsum = block_sum(contrib, bs);

@@ -28,26 +28,49 @@ namespace pogs {
 
 // ---------------------------------------------------------------------------
 // Stopping test and adaptive penalty for the iteration whose partial sums are
-// in the slots (Section 3.4, Algorithm 3).  Every thread of the workgroup
-// takes part in the fixed-order sums; `st` (LDS) is updated by thread 0 and
-// valid in every thread after the call.  Slots of the prox step are read from
-// parity `spar`.
+// in the slots (Section 3.4, Algorithm 3), in two parts so the slot loads can
+// be issued together with the caller's other loads:
+//   control_partials: this thread's share of the four slot sums (parity spar);
+//   control_apply:    fixed-order block sums, then thread 0 updates `st`
+//                     (LDS), valid in every thread after the call.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ void control_compute(const IterArgs<T> &p, int spar, CtrlState &st, double *lds) {
+__device__ inline void control_partials(const IterArgs<T> &p, int spar, double part[4]) {
   const double *s_mu = p.s_mu + (size_t)spar * p.nbx;
   const double *s_yh = p.s_yh + (size_t)spar * p.nby;
-  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
-  for (int i = threadIdx.x; i < p.nbx; i += blockDim.x) a += s_mu[i];
-  for (int i = threadIdx.x; i < p.nby; i += blockDim.x) b += s_yh[i];
-  for (int i = threadIdx.x; i < p.n_pri; i += blockDim.x) c += p.s_pri[i];
-  for (int i = threadIdx.x; i < p.n_dual; i += blockDim.x) d += p.s_dual[i];
-  const double mu2 = block_sum(a, lds);
-  const double yh2 = block_sum(b, lds);
-  const double pri2 = block_sum(c, lds);
-  const double dual2 = block_sum(d, lds);
+  part[0] = part[1] = part[2] = part[3] = 0.0;
+  for (int i = threadIdx.x; i < p.nbx; i += blockDim.x) part[0] += s_mu[i];
+  for (int i = threadIdx.x; i < p.nby; i += blockDim.x) part[1] += s_yh[i];
+  for (int i = threadIdx.x; i < p.n_pri; i += blockDim.x) part[2] += p.s_pri[i];
+  for (int i = threadIdx.x; i < p.n_dual; i += blockDim.x) part[3] += p.s_dual[i];
+}
+
+// Four block-wide sums at once (one barrier pair); results valid in thread 0.
+// Fixed order: wave shuffle tree, then the waves in index order.
+__device__ inline void block_sum4(double v[4], double *scratch /* 4 * waves */) {
+  const int nw = blockDim.x / kWave, w = threadIdx.x / kWave;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v[c] = wave_sum(v[c]);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) scratch[c * nw + w] = v[c];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double t = 0.0;
+      for (int i = 0; i < nw; ++i) t += scratch[c * nw + i];
+      v[c] = t;
+    }
+}
+
+template <typename T>
+__device__ void control_apply(const IterArgs<T> &p, double part[4], CtrlState &st, double *lds) {
+  block_sum4(part, lds);
   if (threadIdx.x == 0) {
     const Ctrl &q = *p.ctrl;
+    const double mu2 = part[0], yh2 = part[1], pri2 = part[2], dual2 = part[3];
     const double r_pri = sqrt(pri2), r_dual = sqrt(dual2);
     const double eps_pri = q.eps_abs + q.eps_rel * sqrt(yh2);
     const double eps_dual = q.eps_abs + q.eps_rel * sqrt(mu2);
@@ -93,11 +116,13 @@ __device__ void control_compute(const IterArgs<T> &p, int spar, CtrlState &st, d
 // function of the stored state and the partial sums).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void control_preview_kernel(IterArgs<T> p, int par) {
-  __shared__ double bs[kBlock / kWave];
+  __shared__ double bs[4 * (kBlock / kWave)];
   __shared__ CtrlState st;
   if (threadIdx.x == 0) st = p.ctrl->st[par];
+  double part[4];
+  control_partials(p, par, part);
   __syncthreads();
-  if (!st.done && st.pending) control_compute(p, par, st, bs);
+  if (!st.done && st.pending) control_apply(p, part, st, bs);
   if (threadIdx.x == 0) p.ctrl->st[1 - par] = st;
 }
 
@@ -106,12 +131,34 @@ __global__ __launch_bounds__(kBlock) void control_preview_kernel(IterArgs<T> p, 
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void prox_kernel(IterArgs<T> p) {
-  __shared__ double bs[kBlock / kWave];
+  __shared__ double bs[4 * (kBlock / kWave)];
   __shared__ CtrlState st;
   const int par = p.par;
+  const bool xs = (int)blockIdx.x < p.nbx;
+  const int blk = xs ? blockIdx.x : blockIdx.x - p.nbx;
+  const int i = blk * kBlock + threadIdx.x;
+  const int len = xs ? p.n : p.m;
+  // every load that does not depend on the control state goes out first
   if (threadIdx.x == 0) st = p.ctrl->st[1 - par];
+  double part[4];
+  control_partials(p, 1 - par, part);
+  const FnDev<T> &F = xs ? p.g : p.f;
+  T *v = xs ? p.x : p.y;
+  T *vt = xs ? p.xt : p.yt;
+  T vi = T(0), vti = T(0), fa = T(0), fb = T(0), fc = T(0), fd = T(0), fe = T(0);
+  int fh = 0;
+  if (i < len) {
+    vi = v[i];
+    vti = vt[i];
+    fh = F.h[i];
+    fa = F.a[i];
+    fb = F.b[i];
+    fc = F.c[i];
+    fd = F.d[i];
+    fe = F.e[i];
+  }
   __syncthreads();
-  if (!st.done && st.pending) control_compute(p, 1 - par, st, bs);
+  if (!st.done && st.pending) control_apply(p, part, st, bs);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     CtrlState out = st;
     out.pending = st.done ? 0 : 1;
@@ -121,23 +168,14 @@ __global__ __launch_bounds__(kBlock) void prox_kernel(IterArgs<T> p) {
   const T rho = (T)st.rho;
   const T resc = (T)st.rescale;
   const T alpha = (T)p.ctrl->alpha;
-  const bool xs = (int)blockIdx.x < p.nbx;
-  const int blk = xs ? blockIdx.x : blockIdx.x - p.nbx;
-  const int i = blk * kBlock + threadIdx.x;
-  const int len = xs ? p.n : p.m;
   double contrib = 0.0;
   if (i < len) {
-    const FnDev<T> &F = xs ? p.g : p.f;
-    T *v = xs ? p.x : p.y;
-    T *vt = xs ? p.xt : p.yt;
-    T vti = vt[i];
     if (resc != T(1)) {
       vti *= resc;
       vt[i] = vti;
     }
-    const T vi = v[i];
     const T arg = vi - vti;
-    const T h = prox_param<T>(F.h[i], F.a[i], F.b[i], F.c[i], F.d[i], F.e[i], arg, rho);
+    const T h = prox_param<T>(fh, fa, fb, fc, fd, fe, arg, rho);
     const T dual = -rho * (h - arg);
     const T rel = alpha * h + (T(1) - alpha) * vi;
     (xs ? p.xh : p.yh)[i] = h;

@@ -330,40 +330,49 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double *K, int Q, int k
   potrf_diag(K, Q, kb, Dinv, bad, s);
 }
 
-__global__ __launch_bounds__(256) void trsm_panel_kernel(double *K, int Q, int kb, const double *Dinv) {
+// Step kb, first half: panel solve L_ib,kb = K_ib,kb L_kb,kb^{-T} for ib > kb
+// (workgroups [0, rest)) and the blocked-inverse step X_kb,j = L_kb,kb^{-1} B_kb,j
+// for j <= kb (workgroups [rest, rest + kb + 1)).  The two groups touch
+// disjoint blocks.
+__global__ __launch_bounds__(256) void factor_panel_kernel(double *K, double *X, int Q, int nbt, int kb,
+                                                           const double *Dinv) {
   __shared__ F64Stage st;
-  trsm_tile(K, Q, kb, kb + 1 + blockIdx.x, Dinv, st);
+  const int rest = nbt - kb - 1;
+  const int b = blockIdx.x;
+  if (b < rest) trsm_tile(K, Q, kb, kb + 1 + b, Dinv, st);
+  else trtri_scale_tile(Dinv, X, Q, kb, b - rest, st);
 }
 
-// Trailing update of step kb; the workgroup that updates the next diagonal
-// block (tile 0) then factors it, saving a launch per step.
-__global__ __launch_bounds__(256) void syrk_update_kernel(double *K, int Q, int kb, double *Dinv, unsigned *bad) {
+// Step kb, second half: trailing update K_I,J -= L_I,kb L_J,kb^T for
+// kb < J <= I (workgroups [0, T)), the workgroup of the next diagonal block
+// then factors it (saving a launch per step); and the blocked-inverse update
+// B_r,j -= L_r,kb X_kb,j for r > kb, j <= kb (workgroups [T, T + rest (kb + 1))),
+// which reads block column kb of L, untouched by the trailing update.
+__global__ __launch_bounds__(256) void factor_update_kernel(double *K, double *X, int Q, int nbt, int kb,
+                                                            double *Dinv, unsigned *bad) {
   __shared__ union {
     F64Stage st;
     CholLds cl;
   } lds;
-  int I, J;
-  tri_index(blockIdx.x, &I, &J);
-  syrk_tile(K, Q, kb, I + kb + 1, J + kb + 1, lds.st);
-  if (blockIdx.x == 0) {
-    __syncthreads();
-    potrf_diag(K, Q, kb + 1, Dinv, bad, lds.cl);
+  const int rest = nbt - kb - 1;
+  const int T = rest * (rest + 1) / 2;
+  const int b = blockIdx.x;
+  if (b < T) {
+    int I, J;
+    tri_index(b, &I, &J);
+    syrk_tile(K, Q, kb, I + kb + 1, J + kb + 1, lds.st);
+    if (b == 0) {
+      __syncthreads();
+      potrf_diag(K, Q, kb + 1, Dinv, bad, lds.cl);
+    }
+  } else {
+    const int w = b - T;
+    trtri_update_tile(K, X, Q, kb, kb + 1 + w / (kb + 1), w % (kb + 1), lds.st);
   }
 }
 
 __global__ __launch_bounds__(256) void trtri_init_kernel(double *X, int Q) {
   trtri_init_rows(X, Q, blockIdx.x * 8, min(Q, (int)blockIdx.x * 8 + 8));
-}
-
-__global__ __launch_bounds__(256) void trtri_scale_kernel(const double *Dinv, double *X, int Q, int i) {
-  __shared__ F64Stage st;
-  trtri_scale_tile(Dinv, X, Q, i, blockIdx.x, st);
-}
-
-__global__ __launch_bounds__(256) void trtri_update_kernel(const double *K, double *X, int Q, int i) {
-  __shared__ F64Stage st;
-  const int w = blockIdx.x;
-  trtri_update_tile(K, X, Q, i, i + 1 + w / (i + 1), w % (i + 1), st);
 }
 
 template <typename T>
@@ -379,20 +388,19 @@ int run_factor_inverse(double *K, int q, int Q, T *Kinv, int ldk, double *ws, un
   const int nbt = Q / NB;
   double *X = ws;                        // Q x Q
   double *Dinv = ws + (size_t)Q * Q;     // nbt blocks of 64 x 64
-  // Cholesky: diagonal factor, panel solve, trailing update (+ next diagonal factor)
-  hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, K, Q, 0, Dinv, bad);
-  for (int kb = 0; kb + 1 < nbt; ++kb) {
-    const int rest = nbt - kb - 1;
-    hipLaunchKernelGGL(trsm_panel_kernel, dim3(rest), dim3(256), 0, s, K, Q, kb, (const double *)Dinv);
-    hipLaunchKernelGGL(syrk_update_kernel, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, K, Q, kb, Dinv, bad);
-  }
-  // L^{-1}, right-looking
+  // X <- I; then per step kb: [panel solve + inverse scaling], [trailing
+  // update + next diagonal factor + inverse update].  Step kb of the blocked
+  // inverse needs block column kb of L and X_kb,. only, so it runs in the
+  // launches of Cholesky step kb.
   hipLaunchKernelGGL(trtri_init_kernel, dim3(cdiv(Q, 8)), dim3(256), 0, s, X, Q);
-  for (int i = 0; i < nbt; ++i) {
-    hipLaunchKernelGGL(trtri_scale_kernel, dim3(i + 1), dim3(256), 0, s, (const double *)Dinv, X, Q, i);
-    if (i + 1 < nbt)
-      hipLaunchKernelGGL(trtri_update_kernel, dim3((nbt - 1 - i) * (i + 1)), dim3(256), 0, s, (const double *)K, X, Q,
-                         i);
+  hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, K, Q, 0, Dinv, bad);
+  for (int kb = 0; kb < nbt; ++kb) {
+    const int rest = nbt - kb - 1;
+    hipLaunchKernelGGL(factor_panel_kernel, dim3(rest + kb + 1), dim3(256), 0, s, K, X, Q, nbt, kb,
+                       (const double *)Dinv);
+    if (rest > 0)
+      hipLaunchKernelGGL(factor_update_kernel, dim3(rest * (rest + 1) / 2 + rest * (kb + 1)), dim3(256), 0, s, K, X,
+                         Q, nbt, kb, Dinv, bad);
   }
   // padding columns of K^{-1} are read (times zero) by the row-dot kernels: keep them zero
   (void)hipMemsetAsync(Kinv, 0, (size_t)q * ldk * sizeof(T), s);
