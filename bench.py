@@ -169,7 +169,20 @@ def main():
     ap.add_argument("--plain-count", type=int, default=512, help="batch: problems in the plain leg")
     ap.add_argument("--R", type=int, default=64, help="path: number of lambdas")
     ap.add_argument("--qps", type=float, default=200.0, help="serve: arrival rate")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="only copy MB megabytes device-to-device three times (calibrates the HBM "
+                         "byte counters against a plain copy of known size)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
               "described in DESIGN.md and not built", file=sys.stderr)

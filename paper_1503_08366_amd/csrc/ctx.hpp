@@ -2,19 +2,28 @@
 #pragma once
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
 
 namespace pogs {
 
-// Device allocations owned by a context, freed together.
+// Device allocations owned by a context, freed together.  Allocation is
+// stream-ordered (hipMallocAsync / hipFreeAsync on the stream that uses the
+// memory) from the device's default pool, which keeps freed memory cached up
+// to a threshold: a context created after another one reuses its memory
+// without a device synchronisation or an operating-system call.
 struct DevArena {
+  hipStream_t stream = nullptr;
   std::vector<void *> ptrs;
+  explicit DevArena(hipStream_t s = nullptr) : stream(s) { configure_pool(); }
+  DevArena(const DevArena &) = delete;
+  DevArena &operator=(const DevArena &) = delete;
   int alloc(void **p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
-    if (hipMalloc(p, bytes) != hipSuccess) {
+    if (hipMallocAsync(p, bytes, stream) != hipSuccess) {
       *p = nullptr;
       return POGS_ENOMEM;
     }
@@ -24,15 +33,116 @@ struct DevArena {
   void release(void *p) {
     auto it = std::find(ptrs.begin(), ptrs.end(), p);
     if (it != ptrs.end()) {
-      (void)hipFree(*it);
+      (void)hipFreeAsync(*it, stream);
       ptrs.erase(it);
     }
   }
-  ~DevArena() {
-    for (void *p : ptrs) (void)hipFree(p);
+  void free_all() {
+    for (void *p : ptrs) (void)hipFreeAsync(p, stream);
+    ptrs.clear();
   }
+  ~DevArena() { free_all(); }
+
+  // Keep up to kPoolKeep bytes of freed memory cached in the current
+  // device's default pool (once per device).
+  static void configure_pool() {
+    static std::mutex mu;
+    static std::vector<int> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(mu);
+    if (std::find(done.begin(), done.end(), dev) != done.end()) return;
+    done.push_back(dev);
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
+    uint64_t keep = kPoolKeep;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  static constexpr uint64_t kPoolKeep = 16ull << 30;
 };
 
+// Small pinned host blocks (control-block read-backs), carved from pinned
+// pages that live until the process ends: pinning costs far more than a
+// small solve's host work.
+class PinnedSlab {
+ public:
+  static constexpr size_t kChunk = 1024, kPage = 64 * 1024;
+  void *get() {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (free_.empty()) {
+      void *pg = nullptr;
+      if (hipHostMalloc(&pg, kPage) != hipSuccess) return nullptr;
+      for (size_t i = 0; i < kPage / kChunk; ++i) free_.push_back((char *)pg + i * kChunk);
+    }
+    void *p = free_.back();
+    free_.pop_back();
+    return p;
+  }
+  void put(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.push_back(p);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<void *> free_;
+};
+inline PinnedSlab &pinned_slab() {
+  static PinnedSlab s;
+  return s;
+}
+
+// A grow-only pinned staging buffer for host-to-device uploads, one user at
+// a time: acquire() waits until the previous user's copy has completed,
+// release(stream) marks the end of this user's copies on its stream.
+class PinnedStage {
+ public:
+  void *acquire(size_t bytes) {
+    mu_.lock();
+    if (ev_) (void)hipEventSynchronize(ev_);
+    if (bytes > cap_) {
+      if (buf_) (void)hipHostFree(buf_);
+      buf_ = nullptr;
+      cap_ = 0;
+      const size_t want = std::max<size_t>(bytes, 1 << 20);
+      if (hipHostMalloc(&buf_, want) != hipSuccess) {
+        buf_ = nullptr;
+        mu_.unlock();
+        return nullptr;
+      }
+      cap_ = want;
+    }
+    return buf_;
+  }
+  void release(hipStream_t s) {
+    if (!ev_) (void)hipEventCreateWithFlags(&ev_, hipEventDisableTiming);
+    if (ev_) (void)hipEventRecord(ev_, s);
+    mu_.unlock();
+  }
+
+ private:
+  std::mutex mu_;
+  void *buf_ = nullptr;
+  size_t cap_ = 0;
+  hipEvent_t ev_ = nullptr;
+};
+inline PinnedStage &pinned_stage() {
+  static PinnedStage s;
+  return s;
+}
+
+// Sub-buffers of one allocation, each aligned to 256 bytes: first pass
+// records offsets, then base() turns them into pointers.
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    off = (size_t)round_up((int64_t)off, 256);
+    const size_t o = off;
+    off += std::max<size_t>(bytes, 1);
+    return o;
+  }
+};
 
 }  // namespace pogs
 
@@ -58,6 +168,9 @@ struct pogs_ctx {
   uint8_t *fh = nullptr, *gh = nullptr, *fh0 = nullptr, *gh0 = nullptr;
   void *fs = nullptr, *gs = nullptr;     // 5 arrays each, T
   double *f0 = nullptr, *g0 = nullptr;   // 5 arrays each, float64
+  // fh0 | gh0 | f0 | g0 form one block (fn_raw, fn_bytes) uploaded in one copy
+  void *fn_raw = nullptr;
+  size_t fn_bytes = 0, off_gh0 = 0, off_f0 = 0, off_g0 = 0;
   double *part = nullptr, *slots = nullptr;
   unsigned *counters = nullptr;
   Ctrl *ctrl = nullptr;
@@ -122,8 +235,12 @@ struct pogs_ctx {
   }
   ~pogs_ctx() {
     if (graph) (void)hipGraphExecDestroy(graph);
-    if (ctrl_host) (void)hipHostFree(ctrl_host);
-    if (obj_host) (void)hipHostFree(obj_host);
+    // device memory goes back to the pool on the context's stream, before
+    // that stream is destroyed
+    arena.free_all();
+    if (stream) (void)hipStreamSynchronize(stream);
+    pinned_slab().put(ctrl_host);
+    pinned_slab().put(obj_host);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };

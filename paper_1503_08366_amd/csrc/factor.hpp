@@ -25,9 +25,10 @@ struct CholLds {              // 66.6 KB
   double X[NB][NB + 1];
 };
 constexpr int kGramTB = 128;  // f32 Gram tile
+constexpr int kGramKC = 16;   // k depth of one f32 stage
 struct GramStage {            // 16.9 KB
-  float a[16][kGramTB + 4];
-  float b[16][kGramTB + 4];
+  float a[kGramKC][kGramTB + 4];
+  float b[kGramKC][kGramTB + 4];
 };
 
 // Tile pair t of a lower triangle (ti >= tj), row by row.
@@ -44,11 +45,14 @@ typedef float GramAcc __attribute__((ext_vector_type(4)));
 // Gram tile (ti, tj) over k in [k0, k1): TALL: sum_k A[k][i] A[k][j] (A^T A),
 // else sum_k A[i][k] A[j][k] (A A^T).  Each wave owns a 64 x 64 quarter as
 // 4 x 4 f32 MFMA 16x16x4 blocks; out(row, col, value) visits the tile's
-// elements (tile-local indices).  Reads beyond m / n are zero.
+// elements (tile-local indices).  Reads beyond m / n are zero.  k0 is a
+// multiple of kGramKC.  Stages of kGramKC k; the next stage is loaded into
+// registers while the MFMAs of the current one run.  Ends with a barrier.
 template <bool TALL, class Out>
 __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld, int ti, int tj, int k0, int k1,
                               GramStage &st, Out out) {
-  constexpr int TB = kGramTB, KC = 16;
+  constexpr int TB = kGramTB, KC = kGramKC;
+  constexpr int NL = KC * TB / 4 / 256;  // float4 loads per thread per panel
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = w >> 1, wj = w & 1;
   const bool diag = ti == tj;
@@ -58,38 +62,56 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = GramAcc{0.f, 0.f, 0.f, 0.f};
-
-  for (int kk0 = k0; kk0 < k1; kk0 += KC) {
+  f4 ra[NL], rb[NL];
+  auto load = [&](int kk0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int f = t + h * 256;  // float4 index in the 16 x 128 stage
+    for (int h = 0; h < NL; ++h) {
+      const int f = t + h * 256;
+      ra[h] = f4{0.f, 0.f, 0.f, 0.f};
+      rb[h] = f4{0.f, 0.f, 0.f, 0.f};
       if (TALL) {
         const int k = f >> 5, c = (f & 31) * 4;
         const int row = kk0 + k;
-        f4 va = f4{0.f, 0.f, 0.f, 0.f}, vb = f4{0.f, 0.f, 0.f, 0.f};
         if (row < k1) {
           const int ca = ti * TB + c, cb = tj * TB + c;
-          if (ca < n) va = *reinterpret_cast<const f4 *>(A + (size_t)row * ld + ca);
-          if (!diag && cb < n) vb = *reinterpret_cast<const f4 *>(A + (size_t)row * ld + cb);
+          if (ca < n) ra[h] = *reinterpret_cast<const f4 *>(A + (size_t)row * ld + ca);
+          if (!diag && cb < n) rb[h] = *reinterpret_cast<const f4 *>(A + (size_t)row * ld + cb);
         }
-        *reinterpret_cast<f4 *>(&st.a[k][c]) = va;
-        if (!diag) *reinterpret_cast<f4 *>(&st.b[k][c]) = vb;
       } else {
         const int r = f & 127, kq = (f >> 7) * 4;
         const int kc = kk0 + kq;  // kc + 3 < ld (kk0 % 16 == 0, ld % 64 == 0, kk0 < n <= ld)
-        const int ra = ti * TB + r, rb = tj * TB + r;
-        f4 va = f4{0.f, 0.f, 0.f, 0.f}, vb = f4{0.f, 0.f, 0.f, 0.f};
-        if (ra < m) va = *reinterpret_cast<const f4 *>(A + (size_t)ra * ld + kc);
-        if (!diag && rb < m) vb = *reinterpret_cast<const f4 *>(A + (size_t)rb * ld + kc);
+        const int rra = ti * TB + r, rrb = tj * TB + r;
+        if (rra < m) ra[h] = *reinterpret_cast<const f4 *>(A + (size_t)rra * ld + kc);
+        if (!diag && rrb < m) rb[h] = *reinterpret_cast<const f4 *>(A + (size_t)rrb * ld + kc);
+      }
+    }
+  };
+  auto store = [&](int kk0) {
+#pragma unroll
+    for (int h = 0; h < NL; ++h) {
+      const int f = t + h * 256;
+      if (TALL) {
+        const int k = f >> 5, c = (f & 31) * 4;
+        *reinterpret_cast<f4 *>(&st.a[k][c]) = ra[h];
+        if (!diag) *reinterpret_cast<f4 *>(&st.b[k][c]) = rb[h];
+      } else {
+        const int r = f & 127, kq = (f >> 7) * 4;
+        const int kc = kk0 + kq;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const bool ok = kc + u < k1;
-          st.a[kq + u][r] = ok ? va[u] : 0.f;
-          if (!diag) st.b[kq + u][r] = ok ? vb[u] : 0.f;
+          st.a[kq + u][r] = ok ? ra[h][u] : 0.f;
+          if (!diag) st.b[kq + u][r] = ok ? rb[h][u] : 0.f;
         }
       }
     }
+  };
+  load(k0);
+  for (int kk0 = k0; kk0 < k1; kk0 += KC) {
+    if (kk0 != k0) __syncthreads();
+    store(kk0);
     __syncthreads();
+    if (kk0 + KC < k1) load(kk0 + KC);
     const float(*pb)[TB + 4] = diag ? st.a : st.b;
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
@@ -105,8 +127,8 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
+  __syncthreads();
   // f32 16x16x4 result layout: lane l, element r -> row 4 (l / 16) + r, column l % 16
 #pragma unroll
   for (int i = 0; i < 4; ++i)

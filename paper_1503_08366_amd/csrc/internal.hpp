@@ -113,5 +113,7 @@ template <typename T> void launch_prox_eval(const uint8_t *h, const T *a, const 
 int gemv_t_tile(int elem_size);
 void gemv_t_geometry(int m, int ncols, int elem_size, int *splits, int *rows_per_split, int *ncolp);
 int gemv_n_blocks(int m, int ncols, int elem_size, int nrhs_rows_hint);
+// Workgroups of `kernel` resident on the whole device at once.
+int resident_workgroups(const void *kernel, int block);
 
 }  // namespace pogs

@@ -82,7 +82,7 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
   p.A = (const float *)ctx->A;
   p.Kinv = (const float *)ctx->Kinv;
 
-  DevArena tmp;
+  DevArena tmp(s);
   const size_t tf = (size_t)m * Rp, tg = (size_t)n * Rp;
   double *f0, *g0;
   uint8_t *fh0, *gh0, *fh, *gh;

@@ -70,7 +70,7 @@ template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, 
                                     pogs_mem mem) {
   const int m = (int)c->m, n = (int)c->n;
   hipStream_t s = c->stream;
-  DevArena tmp;
+  DevArena tmp(s);
   int rc;
   // -- layout -------------------------------------------------------------
   if ((rc = c->arena.alloc(&c->A, (size_t)m * c->ld * sizeof(T)))) return rc;
@@ -130,35 +130,58 @@ template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, 
 }
 
 template <typename T> int alloc_iteration(pogs_ctx *c) {
+  static_assert(sizeof(Ctrl) <= PinnedSlab::kChunk, "control block larger than a pinned slab chunk");
   const int m = (int)c->m, n = (int)c->n;
-  int rc;
-  if ((rc = c->arena.alloc(&c->vec, c->vec_elems() * sizeof(T)))) return rc;
-  POGS_HIP_TRY(hipMemsetAsync(c->vec, 0, c->vec_elems() * sizeof(T), c->stream));
-  if ((rc = c->arena.alloc((void **)&c->fh, m))) return rc;
-  if ((rc = c->arena.alloc((void **)&c->gh, n))) return rc;
-  if ((rc = c->arena.alloc((void **)&c->fh0, m))) return rc;
-  if ((rc = c->arena.alloc((void **)&c->gh0, n))) return rc;
-  if ((rc = c->arena.alloc(&c->fs, (size_t)5 * m * sizeof(T)))) return rc;
-  if ((rc = c->arena.alloc(&c->gs, (size_t)5 * n * sizeof(T)))) return rc;
-  if ((rc = c->arena.alloc((void **)&c->f0, (size_t)5 * m * 8))) return rc;
-  if ((rc = c->arena.alloc((void **)&c->g0, (size_t)5 * n * 8))) return rc;
   // gemv_t geometry over the n columns (same for both orientations)
   gemv_t_geometry(m, n, sizeof(T), &c->splits, &c->rps, &c->ncolp);
-  if ((rc = c->arena.alloc((void **)&c->part, (size_t)c->splits * 2 * c->ncolp * 8))) return rc;
   c->nbx = (int)cdiv(n, kBlock);
   c->nby = (int)cdiv(m, kBlock);
   c->n_pri = gemv_n_blocks(m, n, sizeof(T), 0);
   c->n_dual = (int)cdiv(n, kFinishCols);
   // prox sums (two parities), residual sums, then the unscale kernel's sums
   const int nslots = 2 * (c->nbx + c->nby) + c->n_pri + c->n_dual + c->nbx + c->nby;
-  if ((rc = c->arena.alloc((void **)&c->slots, (size_t)nslots * 8))) return rc;
   const int ntiles = (int)cdiv(n, gemv_t_tile(sizeof(T)));
-  if ((rc = c->arena.alloc((void **)&c->counters, (size_t)(ntiles + 64) * sizeof(unsigned)))) return rc;
+  // raw functions: fh0 | gh0 | f0 | g0, uploaded in one copy
+  Carve raw;
+  raw.take(m);
+  c->off_gh0 = raw.take(n);
+  c->off_f0 = raw.take((size_t)5 * m * 8);
+  c->off_g0 = raw.take((size_t)5 * n * 8);
+  c->fn_bytes = raw.off;
+  // every per-context iteration buffer in one allocation
+  Carve cv;
+  const size_t o_vec = cv.take(c->vec_elems() * sizeof(T));
+  const size_t o_fh = cv.take(m), o_gh = cv.take(n);
+  const size_t o_fs = cv.take((size_t)5 * m * sizeof(T)), o_gs = cv.take((size_t)5 * n * sizeof(T));
+  const size_t o_raw = cv.take(c->fn_bytes);
+  const size_t o_part = cv.take((size_t)c->splits * 2 * c->ncolp * 8);
+  const size_t o_slots = cv.take((size_t)nslots * 8);
+  const size_t o_cnt = cv.take((size_t)(ntiles + 64) * sizeof(unsigned));
+  const size_t o_ctrl = cv.take(sizeof(Ctrl));
+  const size_t o_obj = cv.take(64);
+  char *base;
+  int rc;
+  if ((rc = c->arena.alloc((void **)&base, cv.off))) return rc;
+  c->vec = base + o_vec;
+  c->fh = (uint8_t *)(base + o_fh);
+  c->gh = (uint8_t *)(base + o_gh);
+  c->fs = base + o_fs;
+  c->gs = base + o_gs;
+  c->fn_raw = base + o_raw;
+  c->fh0 = (uint8_t *)c->fn_raw;
+  c->gh0 = (uint8_t *)c->fn_raw + c->off_gh0;
+  c->f0 = (double *)((char *)c->fn_raw + c->off_f0);
+  c->g0 = (double *)((char *)c->fn_raw + c->off_g0);
+  c->part = (double *)(base + o_part);
+  c->slots = (double *)(base + o_slots);
+  c->counters = (unsigned *)(base + o_cnt);
+  c->ctrl = (Ctrl *)(base + o_ctrl);
+  c->obj_dev = (double *)(base + o_obj);
+  POGS_HIP_TRY(hipMemsetAsync(c->vec, 0, c->vec_elems() * sizeof(T), c->stream));
   POGS_HIP_TRY(hipMemsetAsync(c->counters, 0, (size_t)(ntiles + 64) * sizeof(unsigned), c->stream));
-  if ((rc = c->arena.alloc((void **)&c->ctrl, sizeof(Ctrl)))) return rc;
-  if ((rc = c->arena.alloc((void **)&c->obj_dev, 64))) return rc;
-  if (hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl)) != hipSuccess) return POGS_ENOMEM;
-  if (hipHostMalloc((void **)&c->obj_host, 64) != hipSuccess) return POGS_ENOMEM;
+  c->ctrl_host = (Ctrl *)pinned_slab().get();
+  c->obj_host = (double *)pinned_slab().get();
+  if (!c->ctrl_host || !c->obj_host) return POGS_ENOMEM;
   return POGS_OK;
 }
 
@@ -199,6 +222,7 @@ extern "C" int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, po
     }
     c->own_stream = true;
   }
+  c->arena.stream = c->stream;
   int rc = dt == POGS_F32 ? init_impl<float>(c, A, dt, ord, lda, mem) : init_impl<double>(c, A, dt, ord, lda, mem);
   if (!rc) rc = dt == POGS_F32 ? alloc_iteration<float>(c) : alloc_iteration<double>(c);
   if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = POGS_EDEVICE;
@@ -216,26 +240,28 @@ namespace {
 template <typename T> int upload_fns(pogs_ctx *c, const HostFn &f, const HostFn &g) {
   const int m = (int)c->m, n = (int)c->n;
   hipStream_t s = c->stream;
+  // one pinned staging copy of fh0 | gh0 | f0 | g0
+  char *st = (char *)pinned_stage().acquire(c->fn_bytes);
+  if (!st) return POGS_ENOMEM;
+  std::memcpy(st, f.h.data(), (size_t)m);
+  std::memcpy(st + c->off_gh0, g.h.data(), (size_t)n);
   const HostFn *fs[2] = {&f, &g};
-  double *dst[2] = {c->f0, c->g0};
-  uint8_t *hd[2] = {c->fh0, c->gh0};
+  const size_t off[2] = {c->off_f0, c->off_g0};
   const int len[2] = {m, n};
   for (int k = 0; k < 2; ++k) {
-    const HostFn &F = *fs[k];
-    const int L = len[k];
-    POGS_HIP_TRY(hipMemcpyAsync(hd[k], F.h.data(), L, hipMemcpyHostToDevice, s));
-    const std::vector<double> *arr[5] = {&F.a, &F.b, &F.c, &F.d, &F.e};
+    const std::vector<double> *arr[5] = {&fs[k]->a, &fs[k]->b, &fs[k]->c, &fs[k]->d, &fs[k]->e};
     for (int j = 0; j < 5; ++j)
-      POGS_HIP_TRY(hipMemcpyAsync(dst[k] + (size_t)j * L, arr[j]->data(), (size_t)L * 8, hipMemcpyHostToDevice, s));
+      std::memcpy(st + off[k] + (size_t)j * len[k] * 8, arr[j]->data(), (size_t)len[k] * 8);
   }
+  const hipError_t e = hipMemcpyAsync(c->fn_raw, st, c->fn_bytes, hipMemcpyHostToDevice, s);
+  pinned_stage().release(s);
+  if (e != hipSuccess) return POGS_EDEVICE;
   T *fsp = (T *)c->fs, *gsp = (T *)c->gs;
   // f^(y) = f(y / D), g^(x) = g(E x)  (Section 4.1)
   launch_scale_fn<T>(c->fh0, c->f0, c->f0 + m, c->f0 + 2 * m, c->f0 + 3 * m, c->f0 + 4 * m, c->D, true, m, c->fh, fsp,
                      fsp + m, fsp + 2 * m, fsp + 3 * m, fsp + 4 * m, s);
   launch_scale_fn<T>(c->gh0, c->g0, c->g0 + n, c->g0 + 2 * n, c->g0 + 3 * n, c->g0 + 4 * n, c->E, false, n, c->gh, gsp,
                      gsp + n, gsp + 2 * n, gsp + 3 * n, gsp + 4 * n, s);
-  // The host vectors must outlive the asynchronous copies.
-  POGS_HIP_TRY(hipStreamSynchronize(s));
   return POGS_OK;
 }
 
@@ -246,21 +272,31 @@ int even_chunk(int requested) {
   return c + (c & 1);
 }
 
+// One chunk of iterations (chunk even: iteration parity is i % 2), then the
+// stop test of its last iteration so the state after the chunk is in st[0].
+template <typename T> void launch_chunk(pogs_ctx *c, int chunk, hipStream_t s) {
+  IterArgs<T> p = c->iter_args<T>();
+  for (int i = 0; i < chunk; ++i) {
+    p.par = i & 1;
+    launch_iteration<T>(p, c->splits, c->rps, c->ncolp, s);
+  }
+  launch_control_preview<T>(p, 1, s);
+}
+
 template <typename T> int ensure_graph(pogs_ctx *c, int chunk) {
   if (c->graph && c->graph_chunk == chunk) return POGS_OK;
   if (c->graph) {
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
   }
-  IterArgs<T> p = c->iter_args<T>();
+  // captured on a stream of this thread that never runs work, so the
+  // context's stream can be executing the first chunk meanwhile
+  static thread_local hipStream_t cap = nullptr;
+  if (!cap) POGS_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipGraph_t g;
-  POGS_HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  for (int i = 0; i < chunk; ++i) {  // chunk is even: iteration parity is i % 2
-    p.par = i & 1;
-    launch_iteration<T>(p, c->splits, c->rps, c->ncolp, c->stream);
-  }
-  launch_control_preview<T>(p, 1, c->stream);  // state after the chunk lands in st[0]
-  POGS_HIP_TRY(hipStreamEndCapture(c->stream, &g));
+  POGS_HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  launch_chunk<T>(c, chunk, cap);
+  POGS_HIP_TRY(hipStreamEndCapture(cap, &g));
   hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return POGS_EDEVICE;
@@ -292,10 +328,17 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   *c->ctrl_host = h;
   POGS_HIP_TRY(hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   const int chunk = even_chunk(p.chunk_iters);
-  if ((rc = ensure_graph<T>(c, chunk))) return rc;
+  // Without a graph for this chunk size yet, the first chunk is launched
+  // directly and the graph is captured while the GPU runs it.
+  bool eager = !(c->graph && c->graph_chunk == chunk);
   for (;;) {
-    POGS_HIP_TRY(hipGraphLaunch(c->graph, s));
+    if (eager) launch_chunk<T>(c, chunk, s);
+    else POGS_HIP_TRY(hipGraphLaunch(c->graph, s));
     POGS_HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    if (eager) {
+      if ((rc = ensure_graph<T>(c, chunk))) return rc;
+      eager = false;
+    }
     POGS_HIP_TRY(hipStreamSynchronize(s));
     const CtrlState &cs = c->ctrl_host->st[0];
     if (p.verbose)
@@ -446,7 +489,7 @@ template <typename T> int project_impl(pogs_ctx *c, const void *cv, const void *
 template <typename T> int prox_impl(const HostFn &F, double rho, const void *v, void *out, pogs_mem mem,
                                     hipStream_t s) {
   const int L = (int)F.h.size();
-  DevArena tmp;
+  DevArena tmp(s);
   int rc;
   uint8_t *h;
   T *prm, *vd, *od;

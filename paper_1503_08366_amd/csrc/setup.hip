@@ -9,6 +9,8 @@
 //   factor      : blocked Cholesky K = L L^T in float64 (64 x 64 blocks, f64
 //                 MFMA for the block products), L^{-1} by blocked substitution,
 //                 K^{-1} = L^{-T} L^{-1}, stored in T for the iterations.
+#include <atomic>
+
 #include "gemv.hpp"
 #include "internal.hpp"
 #include "factor.hpp"
@@ -102,6 +104,86 @@ struct EpiEqCol {
   __device__ void tile_done(int tile, double v) const { a.slots[tile] = v; }
 };
 
+// One Sinkhorn-Knopp sweep (Algorithm 2, p = 2) in a single pass over a
+// float32 A with n <= 1024 U: workgroup b owns rows [b rps, (b + 1) rps) and
+// thread t the columns 4 t + 1024 u.  For each group of R rows the row sums
+// sum_j A_ij^2 e_j are reduced across the workgroup (fixed order: lane tree,
+// then waves in order), every thread forms d_i = n / (sum + gamma/m) and adds
+// A_ij^2 d_i to its column sums while the row is still in registers.  The
+// column sums of each workgroup go to part[b * ncolp + j]; a finish kernel
+// adds them in workgroup order and forms e.  Same arithmetic as the two-pass
+// sweep, half the reads of A.
+template <int U, int R>
+__global__ __launch_bounds__(kBlock) void equil_sweep_kernel(const float *__restrict__ A, int m, int n, int ld,
+                                                             int rps, const double *__restrict__ e,
+                                                             double *__restrict__ d, double *__restrict__ part,
+                                                             int ncolp, double nf, double gamma_m) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  __shared__ double red[2][R][kBlock / kWave];
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t >> 6;
+  const int r0 = blockIdx.x * rps, r1 = min(m, r0 + rps);
+  double ev[U][4], col[U][4];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = 4 * t + 1024 * u + k;
+      ev[u][k] = c < n ? e[c] : 0.0;
+      col[u][k] = 0.0;
+    }
+  int g = 0;
+  for (int i0 = r0; i0 < r1; i0 += R, ++g) {
+    f4 a[R][U];
+#pragma unroll
+    for (int ri = 0; ri < R; ++ri) {
+      const int row = min(i0 + ri, r1 - 1);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = 4 * t + 1024 * u;
+        a[ri][u] = c < ld ? *reinterpret_cast<const f4 *>(A + (size_t)row * ld + c) : f4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+    double p[R];
+#pragma unroll
+    for (int ri = 0; ri < R; ++ri) {
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double x = (double)a[ri][u][k];
+          acc = fma(x * x, ev[u][k], acc);
+        }
+      p[ri] = wave_sum(acc);
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int ri = 0; ri < R; ++ri) red[g & 1][ri][w] = p[ri];
+    __syncthreads();
+#pragma unroll
+    for (int ri = 0; ri < R; ++ri) {
+      const double rs = ((red[g & 1][ri][0] + red[g & 1][ri][1]) + red[g & 1][ri][2]) + red[g & 1][ri][3];
+      const bool live = i0 + ri < r1;
+      const double di = live ? nf / (rs + gamma_m) : 0.0;
+      if (t == 0 && live) d[i0 + ri] = di;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double x = (double)a[ri][u][k];
+          col[u][k] = fma(x * x, di, col[u][k]);
+        }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = 4 * t + 1024 * u + k;
+      if (c < ncolp) part[(size_t)blockIdx.x * ncolp + c] = col[u][k];
+    }
+}
+
 __global__ void fill_kernel(double *p, double v, int len) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) p[i] = v;
@@ -127,12 +209,24 @@ __global__ void scale_matrix_kernel(T *A, int m, int n, int ld, const double *D,
   for (int r = blockIdx.y; r < m; r += gridDim.y) A[(size_t)r * ld + c] = (T)(D[r] * (double)A[(size_t)r * ld + c] * E[c]);
 }
 
+// Workgroups of `kernel` (block threads per workgroup, static LDS only)
+// resident on the whole device at once.
+int resident_workgroups(const void *kernel, int block) {
+  int nb = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess) nb = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  return std::max(1, nb) * std::max(1, cus);
+}
+
 size_t equil_workspace_bytes(int m, int n) {
   int splits, rps, ncolp;
   gemv_t_geometry(m, n, 4, &splits, &rps, &ncolp);
   int s2, r2, nc2;
   gemv_t_geometry(m, n, 8, &s2, &r2, &nc2);
-  const size_t part = (size_t)std::max(splits * ncolp, s2 * nc2);
+  // the fused float32 sweep writes up to 1024 workgroups of column sums
+  const size_t part = std::max<size_t>((size_t)std::max(splits * ncolp, s2 * nc2), (size_t)1024 * ncolp);
   // d, e, colsum, slots, fro2, partials
   return ((size_t)m + 2 * (size_t)n + (size_t)ncolp + 8 + part) * sizeof(double);
 }
@@ -163,7 +257,45 @@ int run_equilibrate(T *A, int m, int n, int ld, int iters, double eps_cmp, doubl
   hipLaunchKernelGGL(fill_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, a.e, 1.0, n);
   const int tiles = (int)cdiv(n, gemv_t_tile(sizeof(T)));
   (void)counters;
-  for (int it = 0; it < iters; ++it) {
+  if (sizeof(T) == 4 && n <= 4096) {
+    // fused sweeps: one pass over A per sweep, as many workgroups as are
+    // resident at once (no tail round)
+    constexpr int R = 4;
+    const int U = (int)cdiv(n, 1024);
+    const void *kern = U == 1   ? (const void *)equil_sweep_kernel<1, R>
+                       : U == 2 ? (const void *)equil_sweep_kernel<2, R>
+                       : U == 3 ? (const void *)equil_sweep_kernel<3, R>
+                                : (const void *)equil_sweep_kernel<4, R>;
+    const int nwg = (int)std::min<int64_t>(std::min(1024, resident_workgroups(kern, kBlock)), cdiv(m, R));
+    const int rps = (int)round_up(cdiv(m, nwg), R);
+    const int nsplit = (int)cdiv(m, rps);
+    if ((size_t)((part + (size_t)nsplit * ncolp) - ws) * sizeof(double) > ws_bytes) return POGS_ENOMEM;
+    for (int it = 0; it < iters; ++it) {
+      const float *Af = (const float *)A;
+      switch (U) {
+        case 1:
+          hipLaunchKernelGGL((equil_sweep_kernel<1, R>), dim3(nsplit), dim3(kBlock), 0, s, Af, m, n, ld, rps, a.e,
+                             a.d, part, ncolp, a.nf, a.gamma_m);
+          break;
+        case 2:
+          hipLaunchKernelGGL((equil_sweep_kernel<2, R>), dim3(nsplit), dim3(kBlock), 0, s, Af, m, n, ld, rps, a.e,
+                             a.d, part, ncolp, a.nf, a.gamma_m);
+          break;
+        case 3:
+          hipLaunchKernelGGL((equil_sweep_kernel<3, R>), dim3(nsplit), dim3(kBlock), 0, s, Af, m, n, ld, rps, a.e,
+                             a.d, part, ncolp, a.nf, a.gamma_m);
+          break;
+        default:
+          hipLaunchKernelGGL((equil_sweep_kernel<4, R>), dim3(nsplit), dim3(kBlock), 0, s, Af, m, n, ld, rps, a.e,
+                             a.d, part, ncolp, a.nf, a.gamma_m);
+          break;
+      }
+      EpiEqCol ec{a};
+      hipLaunchKernelGGL((gemv_t_finish_kernel<1, EpiEqCol>), dim3(cdiv(n, kFinishCols)), dim3(kBlock), 0, s, n,
+                         nsplit, (const double *)part, ncolp, ec);
+    }
+  }
+  for (int it = 0; it < iters && !(sizeof(T) == 4 && n <= 4096); ++it) {
     // rows: d = n / (|A|^2 e + gamma/m)
     {
       EpiEqRow er{a};
@@ -284,8 +416,18 @@ static void gram_geometry(int m, int n, int elem_size, int *TB, int *ntp, int *s
   *TB = elem_size == 4 ? 128 : 64;
   const int nt = (int)cdiv(qdim, *TB);
   *ntp = nt * (nt + 1) / 2;
-  int s = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(512, *ntp), cdiv(kdim, 256)));
-  *kchunk = (int)round_up(cdiv(kdim, s), 16);
+  // as many (tile, split) workgroups as are resident at once, one round,
+  // each split at least 256 deep
+  const void *kern = elem_size == 4 ? (tall ? (const void *)gram_f32_kernel<true> : (const void *)gram_f32_kernel<false>)
+                                    : (tall ? (const void *)gram_f64_kernel<true> : (const void *)gram_f64_kernel<false>);
+  static std::atomic<int> resident[2][2];  // per (element size, orientation); 0 = not yet queried
+  int res = resident[elem_size == 4][tall].load(std::memory_order_relaxed);
+  if (!res) {
+    res = resident_workgroups(kern, 256);
+    resident[elem_size == 4][tall].store(res, std::memory_order_relaxed);
+  }
+  int s = (int)std::max<int64_t>(1, std::min<int64_t>(res / *ntp, cdiv(kdim, 256)));
+  *kchunk = (int)round_up(cdiv(kdim, s), kGramKC);
   *splits = (int)cdiv(kdim, *kchunk);
 }
 
