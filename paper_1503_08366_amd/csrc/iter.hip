@@ -346,10 +346,36 @@ static void gemv_t(const T *A, int m, int n, int ld, const TV *v0, const TV *v1,
                      (const double *)part, ncolp, epi);
 }
 
-// Pick lanes-per-row and rows-per-thread from the row length and row count.
+// float32 rows of at most 2048 elements: whole rows per wave, the grid one
+// round of resident workgroups (four per CU up to 1024 columns, three above;
+// the kernel's register budget guarantees that residency on 256 CUs).
+constexpr int kRowsMaxLd = 2048;
+static int rows_grid(int m, int ld) {
+  return (int)std::min<int64_t>(cdiv(m, kBlock / kWave), (ld > 1024 ? 3 : 4) * 256);
+}
+
+template <int NRHS, int NC, class Epi>
+static void launch_rows(const float *A, int m, int n, int ld, const float *v0, const float *v1, const Epi &epi,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((gemv_n_rows_kernel<NRHS, NC, Epi>), dim3(rows_grid(m, ld)), dim3(kBlock), 0, s, A, m, n, ld,
+                     v0, v1, epi);
+}
+
+// Pick the kernel and its shape from the row length and row count.
 template <typename T, typename TV, int NRHS, class Epi>
 static void gemv_n(const T *A, int m, int n, int ld, const TV *v0, const TV *v1, const Epi &epi, hipStream_t s,
                    int *nblocks_out = nullptr) {
+  if constexpr (sizeof(T) == 4 && sizeof(TV) == 4) {
+    if (ld <= kRowsMaxLd) {
+      const float *Af = (const float *)A, *x0 = (const float *)v0, *x1 = (const float *)v1;
+      if (ld <= 256) launch_rows<NRHS, 1>(Af, m, n, ld, x0, x1, epi, s);
+      else if (ld <= 512) launch_rows<NRHS, 2>(Af, m, n, ld, x0, x1, epi, s);
+      else if (ld <= 1024) launch_rows<NRHS, 4>(Af, m, n, ld, x0, x1, epi, s);
+      else launch_rows<NRHS, 8>(Af, m, n, ld, x0, x1, epi, s);
+      if (nblocks_out) *nblocks_out = rows_grid(m, ld);
+      return;
+    }
+  }
   constexpr int VN = Vec16<T>::N;
   const int vpr = (int)cdiv(n, VN);
   const bool wide_rows = vpr >= 128;
@@ -381,6 +407,7 @@ static void gemv_n(const T *A, int m, int n, int ld, const TV *v0, const TV *v1,
 }
 
 int gemv_n_blocks(int m, int ncols, int elem_size, int) {
+  if (elem_size == 4 && round_up(ncols, 64) <= kRowsMaxLd) return rows_grid(m, (int)round_up(ncols, 64));
   const int VN = 16 / elem_size;
   const int vpr = (int)cdiv(ncols, VN);
   if (vpr >= 128) {
