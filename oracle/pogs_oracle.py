@@ -406,7 +406,8 @@ class Result:
 
 
 def solve(A, f, g, params: Params = Params(), record: bool = False,
-          D: Optional[np.ndarray] = None, E: Optional[np.ndarray] = None) -> Result:
+          D: Optional[np.ndarray] = None, E: Optional[np.ndarray] = None,
+          x0: Optional[np.ndarray] = None, nu0: Optional[np.ndarray] = None) -> Result:
     """Graph projection splitting (Algorithm 1) on the pre-conditioned problem.
 
     Per iteration k = 0, 1, ... (all in the scaled variables of Section 4.1,
@@ -428,6 +429,13 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
 
     The returned tuple is the last half-step tuple (Section 5) mapped back to
     the original variables: x = E x_h, y = D^-1 y_h, mu = E^-1 mu_h, nu = D nu_h.
+
+    Warm start (Section 5 lets the caller supply x0 and nu0; the state they
+    define is not spelled out).  Reading: x = E^-1 x0 and y = A^ x (a point of
+    the graph); y~ = -(D^-1 nu0) / rho0, since nu_h = -rho y~ whenever the
+    prox step leaves y unchanged; x~ = -A^T y~, the relation every projection
+    restores.  From an optimal pair this state is a fixed point of the
+    iteration; x0 = 0, nu0 = 0 is the cold start.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
@@ -445,6 +453,12 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
     y = np.zeros(m)
     xt = np.zeros(n)
     yt = np.zeros(m)
+    if x0 is not None:
+        x = np.asarray(x0, dtype=np.float64) / E
+        y = Ah @ x
+    if nu0 is not None:
+        yt = -(np.asarray(nu0, dtype=np.float64) / D) / params.rho0
+        xt = -(Ah.T @ yt)
     rho = params.rho0
     l = u = 0
     hist = {"r_pri": [], "r_dual": [], "eps_pri": [], "eps_dual": [], "rho": [],

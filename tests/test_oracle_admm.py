@@ -278,3 +278,49 @@ def test_two_iterations_by_hand():
     np.testing.assert_allclose([r.x[0], r.y[0], r.mu[0], r.nu[0]], [1.2, 1.0, 0.5, -1.0], atol=1e-15)
     np.testing.assert_allclose([r.r_pri, r.r_dual], [0.2, 0.5], atol=1e-15)
     assert not r.converged and r.iters == 2
+
+
+# --------------------------------------------------------------------------
+# Warm start (Section 5: the caller may supply x0 and nu0)
+# --------------------------------------------------------------------------
+def test_warm_start_from_zero_is_the_cold_start():
+    p = W.lasso(60, 25, seed=11, dtype=np.float64)
+    prm = O.Params(eps_cmp=2.0 ** -52)
+    cold = O.solve(p.A, p.f, p.g, prm)
+    warm = O.solve(p.A, p.f, p.g, prm, x0=np.zeros(25), nu0=np.zeros(60))
+    assert warm.iters == cold.iters
+    assert np.array_equal(warm.x, cold.x) and np.array_equal(warm.nu, cold.nu)
+
+
+@pytest.mark.parametrize("kind", ["lasso", "nnls", "logistic", "wide_lasso"])
+def test_warm_start_from_an_optimum_is_a_fixed_point(kind):
+    """From an optimal pair, prox_g(x* + mu*/rho) = x* because mu* is in
+    dg(x*), and likewise for y: the warm-start state does not move and the
+    stop test passes at the first iteration."""
+    if kind == "lasso":
+        p = W.lasso(80, 30, seed=12, dtype=np.float64)
+    elif kind == "nnls":
+        p = W.nnls_from(W.lasso(80, 30, seed=13, dtype=np.float64))
+    elif kind == "logistic":
+        p = W.logistic(90, 20, seed=14, dtype=np.float64)
+    else:
+        p = W.lasso(30, 70, seed=15, dtype=np.float64)
+    ref = O.solve(p.A, p.f, p.g, TIGHT)
+    assert ref.converged
+    r = O.solve(p.A, p.f, p.g, O.Params(eps_cmp=2.0 ** -52), x0=ref.x, nu0=ref.nu)
+    assert r.converged and r.iters == 1
+    scale = max(1.0, float(np.max(np.abs(ref.x))))
+    assert np.max(np.abs(r.x - ref.x)) <= 1e-6 * scale
+
+
+def test_warm_start_along_a_lambda_path_saves_iterations():
+    """Continuation: the solution at one lambda is a good start for the next."""
+    probs = W.lambda_path(m=300, n=80, R=6, seed=16)
+    prm = O.Params(eps_cmp=float(np.finfo(np.float32).eps))
+    A = probs[0].A.astype(np.float64)
+    prev = O.solve(A, probs[2].f, probs[2].g, prm)
+    cold = O.solve(A, probs[3].f, probs[3].g, prm)
+    warm = O.solve(A, probs[3].f, probs[3].g, prm, x0=prev.x, nu0=prev.nu)
+    assert warm.converged and cold.converged
+    assert warm.iters < cold.iters
+    assert abs(warm.optval - cold.optval) <= 1e-3 * max(1.0, abs(cold.optval))
