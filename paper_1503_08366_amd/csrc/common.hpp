@@ -27,6 +27,15 @@ template <> struct Vec16<double> {
   static constexpr int N = 2;
 };
 
+// Coordinates of a workgroup's share of a launch: the hardware block index
+// for a launch over one problem, or the fields of a work item when one
+// launch covers the tiles of many problems.
+struct Blk {
+  int x, y;    // block index
+  int nx, ny;  // blocks of this problem along x and y
+};
+__device__ inline Blk hw_block() { return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y}; }
+
 // Sum over the 64 lanes of a wave (every lane receives the total).
 __device__ inline double wave_sum(double v) {
 #pragma unroll

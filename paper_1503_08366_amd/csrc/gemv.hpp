@@ -34,9 +34,9 @@ template <bool SQUARE> __device__ inline double elem_op(double a) {
 //                                                returns a value summed per tile
 //   void tile_done(int tile, double sum)       -> thread 0 of the tile's workgroup
 template <typename TA, typename TV, int NRHS, bool SQUARE, class Epi>
-__global__ __launch_bounds__(kBlock) void gemv_t_kernel(
-    const TA *__restrict__ A, int m, int n, int ld, const TV *__restrict__ v0,
-    const TV *__restrict__ v1, int rows_per_split, double *__restrict__ part, int ncolp, Epi epi) {
+__device__ __forceinline__ void gemv_t_body(
+    const Blk &b, const TA *__restrict__ A, int m, int n, int ld, const TV *__restrict__ v0,
+    const TV *__restrict__ v1, int rows_per_split, double *__restrict__ part, int ncolp, const Epi &epi) {
   using V = typename Vec16<TA>::type;
   constexpr int VN = Vec16<TA>::N;
   constexpr int TILE = kWave * VN;
@@ -45,8 +45,8 @@ __global__ __launch_bounds__(kBlock) void gemv_t_kernel(
 
   const int lane = threadIdx.x & (kWave - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int tile = blockIdx.x;
-  const int split = blockIdx.y;
+  const int tile = b.x;
+  const int split = b.y;
   const int col = tile * TILE + lane * VN;
   const int r0 = split * rows_per_split;
   const int r1 = min(m, r0 + rows_per_split);
@@ -107,21 +107,29 @@ __global__ __launch_bounds__(kBlock) void gemv_t_kernel(
   }
 }
 
-// Sum the split partials of kFinishCols columns (block blockIdx.x): the
-// threads form kBlock / kFinishCols split groups, group g sums the splits
-// g, g + groups, ...; the group sums are then added in group order (a fixed
+template <typename TA, typename TV, int NRHS, bool SQUARE, class Epi>
+__global__ __launch_bounds__(kBlock) void gemv_t_kernel(const TA *__restrict__ A, int m, int n, int ld,
+                                                        const TV *__restrict__ v0, const TV *__restrict__ v1,
+                                                        int rows_per_split, double *__restrict__ part, int ncolp,
+                                                        Epi epi) {
+  gemv_t_body<TA, TV, NRHS, SQUARE, Epi>(hw_block(), A, m, n, ld, v0, v1, rows_per_split, part, ncolp, epi);
+}
+
+// Sum the split partials of kFinishCols columns (block b.x): the threads
+// form kBlock / kFinishCols split groups, group g sums the splits g,
+// g + groups, ...; the group sums are then added in group order (a fixed
 // order, so results are deterministic); each column is finished by the
-// epilogue and the block's sum goes to tile_done(blockIdx.x, .).
+// epilogue and the block's sum goes to tile_done(b.x, .).
 template <int NRHS, class Epi>
-__global__ __launch_bounds__(kBlock) void gemv_t_finish_kernel(int n, int splits, const double *__restrict__ part,
-                                                                int ncolp, Epi epi) {
+__device__ __forceinline__ void gemv_t_finish_body(const Blk &b, int n, int splits, const double *__restrict__ part,
+                                                   int ncolp, const Epi &epi) {
   constexpr int G = kBlock / kFinishCols;
   __shared__ double red[G][2][kFinishCols];
   __shared__ double bs[kBlock / kWave];
   if (epi.skip()) return;
   const int c = threadIdx.x % kFinishCols;
   const int g = threadIdx.x / kFinishCols;
-  const int cg = blockIdx.x * kFinishCols + c;
+  const int cg = b.x * kFinishCols + c;
   double s[2] = {0.0, 0.0};
   if (cg < ncolp) {
 #pragma unroll 4
@@ -143,7 +151,13 @@ __global__ __launch_bounds__(kBlock) void gemv_t_finish_kernel(int n, int splits
     contrib = epi.column(cg, t0, t1);
   }
   const double tsum = block_sum(contrib, bs);
-  if (threadIdx.x == 0) epi.tile_done(blockIdx.x, tsum);
+  if (threadIdx.x == 0) epi.tile_done(b.x, tsum);
+}
+
+template <int NRHS, class Epi>
+__global__ __launch_bounds__(kBlock) void gemv_t_finish_kernel(int n, int splits, const double *__restrict__ part,
+                                                                int ncolp, Epi epi) {
+  gemv_t_finish_body<NRHS, Epi>(hw_block(), n, splits, part, ncolp, epi);
 }
 
 // ---------------------------------------------------------------------------
@@ -157,9 +171,9 @@ __global__ __launch_bounds__(kBlock) void gemv_t_finish_kernel(int n, int splits
 template <typename TV> struct GemvNChunk { static constexpr int value = 8192 / sizeof(TV) * 2; };
 
 template <typename TA, typename TV, int NRHS, bool SQUARE, int LPR, int RPT, class Epi>
-__global__ __launch_bounds__(kBlock) void gemv_n_kernel(
-    const TA *__restrict__ A, int m, int n, int ld, const TV *__restrict__ v0,
-    const TV *__restrict__ v1, Epi epi) {
+__device__ __forceinline__ void gemv_n_body(
+    const Blk &b, const TA *__restrict__ A, int m, int n, int ld, const TV *__restrict__ v0,
+    const TV *__restrict__ v1, const Epi &epi) {
   using V = typename Vec16<TA>::type;
   constexpr int VN = Vec16<TA>::N;
   constexpr int CH = GemvNChunk<TV>::value;  // vector elements staged per chunk
@@ -173,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void gemv_n_kernel(
   const int w = threadIdx.x >> 6;
   const int sub = lane % LPR;
   const int grp = lane / LPR;
-  const int row_base = blockIdx.x * ROWS + (w * GPW + grp) * RPT;
+  const int row_base = b.x * ROWS + (w * GPW + grp) * RPT;
 
   double acc[RPT][NRHS];
 #pragma unroll
@@ -247,7 +261,14 @@ __global__ __launch_bounds__(kBlock) void gemv_n_kernel(
     if (sub == 0 && i < m) contrib += epi.row(i, s0, s1);
   }
   const double bsum = block_sum(contrib, bs);
-  if (threadIdx.x == 0) epi.block_done(blockIdx.x, bsum);
+  if (threadIdx.x == 0) epi.block_done(b.x, bsum);
+}
+
+template <typename TA, typename TV, int NRHS, bool SQUARE, int LPR, int RPT, class Epi>
+__global__ __launch_bounds__(kBlock) void gemv_n_kernel(const TA *__restrict__ A, int m, int n, int ld,
+                                                        const TV *__restrict__ v0, const TV *__restrict__ v1,
+                                                        Epi epi) {
+  gemv_n_body<TA, TV, NRHS, SQUARE, LPR, RPT, Epi>(hw_block(), A, m, n, ld, v0, v1, epi);
 }
 
 // ---------------------------------------------------------------------------
@@ -262,15 +283,15 @@ __global__ __launch_bounds__(kBlock) void gemv_n_kernel(
 // current row is reduced.  No LDS staging, no barrier before the first load.
 // Register budget: four waves per SIMD up to 1024 columns, three above.
 template <int NRHS, int NC, class Epi>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NC >= 8 ? 3 : 4))) void gemv_n_rows_kernel(const float *__restrict__ A, int m, int n, int ld,
-                                                             const float *__restrict__ v0,
-                                                             const float *__restrict__ v1, Epi epi) {
+__device__ __forceinline__ void gemv_n_rows_body(const Blk &b, const float *__restrict__ A, int m, int n, int ld,
+                                                 const float *__restrict__ v0, const float *__restrict__ v1,
+                                                 const Epi &epi) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   __shared__ double bs[kBlock / kWave];
   if (epi.skip()) return;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
-  const int W = gridDim.x * (kBlock / kWave);
-  const int gw = blockIdx.x * (kBlock / kWave) + w;
+  const int W = b.nx * (kBlock / kWave);
+  const int gw = b.x * (kBlock / kWave) + w;
   f4 x0[NC], x1[NC];
 #pragma unroll
   for (int u = 0; u < NC; ++u) {
@@ -317,7 +338,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NC >= 8 
     row = next;
   }
   const double bsum = block_sum(contrib, bs);
-  if (threadIdx.x == 0) epi.block_done(blockIdx.x, bsum);
+  if (threadIdx.x == 0) epi.block_done(b.x, bsum);
+}
+
+template <int NRHS, int NC, class Epi>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NC >= 8 ? 3 : 4))) void gemv_n_rows_kernel(
+    const float *__restrict__ A, int m, int n, int ld, const float *__restrict__ v0, const float *__restrict__ v1,
+    Epi epi) {
+  gemv_n_rows_body<NRHS, NC, Epi>(hw_block(), A, m, n, ld, v0, v1, epi);
 }
 
 template <int LPR, int RPT> constexpr int gemv_n_rows_per_block() {
