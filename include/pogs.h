@@ -210,13 +210,20 @@ typedef struct {
   size_t hbm_budget_bytes;  /* device memory the engine may hold for resident
                                problems; 0 = 80% of free memory at creation */
   int32_t max_slots;        /* problems resident at once, 0 = 1024 */
-  int32_t chunk_iters;      /* iterations per scheduling round, 0 = 50 */
+  int32_t chunk_iters;      /* iterations per scheduling round, 0 = 20 */
   void *stream;             /* NULL = engine's own stream */
 } pogs_batch_cfg;
 
 typedef struct pogs_batch pogs_batch;
 
-/* Create a batch engine with its own scheduler thread.  cfg may be NULL. */
+/* Create a serving engine with its own scheduler thread (continuous
+ * batching): queued requests are admitted while the memory budget and the
+ * slot count allow, set up together, and advanced in chunks of chunk_iters
+ * iterations as one group; finished ones leave after each chunk and queued
+ * ones join.  Requests too large for the group (see pogs_solve_batch) or with
+ * m n > 16 Mi or min(m, n) > 2048 run on the whole-GPU path on a second
+ * thread and stream.  cfg may be NULL.  POGS_EAGAIN if the engine's own
+ * arrays do not fit the budget. */
 int pogs_batch_create(pogs_batch **out, const pogs_batch_cfg *cfg);
 
 /* Queue a problem; copies its data.  Returns a ticket in *ticket.
@@ -240,11 +247,16 @@ int pogs_batch_cancel(pogs_batch *b, uint64_t ticket);
 /* Stop the scheduler thread and free everything (pending tickets are dropped). */
 int pogs_batch_destroy(pogs_batch *b);
 
-/* Solve nprob independent problems (host data) in one call: setup for all of
- * them runs as batched kernels over a flattened work list, then one persistent
- * launch runs every problem's ADMM iterations to its own stop, one workgroup
- * per problem pulled from a device work queue (largest first).  out[i]
- * receives problem i's result (host buffers).  Errors as pogs_init/pogs_solve. */
+/* Solve nprob independent problems (host data) in one call.  Problems with
+ * n <= 4096 and min(m, n) <= 4096 run as one group: each launch runs one
+ * phase (a setup step, or one step of an ADMM iteration) for every problem of
+ * the group through a work list of (problem, tile) items, largest problems
+ * first; each problem stops at its own stopping test and leaves the group at
+ * the next chunk boundary.  Larger problems run one at a time on the
+ * whole-GPU path.  A problem gives the same bits alone and in any group.
+ * out[i] receives problem i's result (host or device buffers, out[i].mem).
+ * Errors as pogs_init/pogs_solve; POGS_EINVAL also for non-finite entries of
+ * a grouped matrix (found on the device during the setup). */
 int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_result *out, void *stream);
 
 const char *pogs_strerror(int code);

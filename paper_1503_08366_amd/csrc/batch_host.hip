@@ -1,14 +1,15 @@
-// Host side of the batched solver: packing problems into device memory, the
-// one-call batch entry point, and the serving engine (continuous batching).
+// Host side of the batched solver and the serving engine, on top of the
+// grouped launches (group_engine.hpp): every launch runs one phase for all
+// problems of a group, so each pass over a matrix has the whole GPU behind it.
 //
-// Serving: a scheduler thread admits queued requests while the resident set
-// fits the memory budget and the slot count, uploads them, and runs rounds of
-// the persistent batch kernel (each round: setup of new problems, then at most
-// chunk_iters iterations of every resident problem).  Finished problems are
-// copied out and their memory released after each round, so requests that
-// arrive while others are on the GPU join at the next round.  Problems too
-// large for one workgroup (min(m, n) > kBatchMaxQ or n > kBatchMaxN) run on
-// the whole-GPU path on a second thread and stream, overlapping the rounds.
+// Serving (continuous batching): a scheduler thread admits queued requests
+// while the resident set fits the memory budget and the slot count, runs the
+// setup of the newly admitted ones as one group, then one chunk of
+// chunk_iters iterations of every resident problem.  Finished problems are
+// returned and their memory released after each chunk, so requests that
+// arrive while others are on the GPU join at the next chunk.  Problems too
+// large for the grouped path, or large enough to slow every chunk, run on the
+// whole-GPU path on a second thread and stream, overlapping the chunks.
 #include <algorithm>
 #include <cfloat>
 #include <chrono>
@@ -22,7 +23,7 @@
 #include <thread>
 #include <vector>
 
-#include "batch.hpp"
+#include "group_engine.hpp"
 #include "hostutil.hpp"
 
 using namespace pogs;
@@ -41,14 +42,23 @@ struct HostProblem {
   pogs_params params{};
 };
 
-int make_host_problem(const pogs_problem *p, HostProblem *hp) {
+// Validate a problem (not its matrix entries).
+int check_problem(const pogs_problem *p) {
   if (!p || p->m <= 0 || p->n <= 0 || !p->A) return POGS_EINVAL;
   if (p->m > (1LL << 31) - 1 || p->n > (1LL << 31) - 1) return POGS_EINVAL;
   if (p->dt != POGS_F32) return POGS_EUNSUPPORTED;
   if (p->ord != POGS_ROW_MAJOR && p->ord != POGS_COL_MAJOR) return POGS_EINVAL;
   if (p->lda < (p->ord == POGS_ROW_MAJOR ? p->n : p->m)) return POGS_EINVAL;
   if (check_params(p->params)) return POGS_EINVAL;
+  return POGS_OK;
+}
+
+// A self-contained copy (serving: the caller may free its buffers on return);
+// the matrix is copied row-major and checked for non-finite entries in the
+// same pass.
+int make_host_problem(const pogs_problem *p, HostProblem *hp) {
   int rc;
+  if ((rc = check_problem(p))) return rc;
   if ((rc = expand_fn(&p->f, p->m, &hp->f))) return rc;
   if ((rc = expand_fn(&p->g, p->n, &hp->g))) return rc;
   hp->m = (int)p->m;
@@ -56,124 +66,36 @@ int make_host_problem(const pogs_problem *p, HostProblem *hp) {
   hp->params = p->params;
   hp->A.resize((size_t)p->m * p->n);
   const float *src = (const float *)p->A;
-  if (p->ord == POGS_ROW_MAJOR) {
-    for (int64_t i = 0; i < p->m; ++i) memcpy(&hp->A[(size_t)i * p->n], src + i * p->lda, (size_t)p->n * 4);
-  } else {
-    for (int64_t i = 0; i < p->m; ++i)
-      for (int64_t j = 0; j < p->n; ++j) hp->A[(size_t)i * p->n + j] = src[j * p->lda + i];
+  bool bad = false;
+  for (int64_t i = 0; i < p->m; ++i) {
+    float *dst = &hp->A[(size_t)i * p->n];
+    for (int64_t j = 0; j < p->n; ++j) {
+      const float v = p->ord == POGS_ROW_MAJOR ? src[i * p->lda + j] : src[j * p->lda + i];
+      bad |= !std::isfinite(v);
+      dst[j] = v;
+    }
   }
-  for (float v : hp->A)
-    if (!std::isfinite(v)) return POGS_EINVAL;
-  return POGS_OK;
+  return bad ? POGS_EINVAL : POGS_OK;
 }
 
-bool fits_workgroup(int m, int n) { return std::min(m, n) <= kBatchMaxQ && n <= kBatchMaxN; }
-
-// Device footprint of one problem on the workgroup path (bytes, 256-aligned pieces).
-struct Layout {
-  size_t A, Kinv, D, E, f0, g0, fh, gh, fs, gs, vec, out, total;
-};
-
-size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
-
-Layout layout_of(int m, int n) {
-  Layout L{};
-  const size_t ld = round_up(n, 64), q = std::min(m, n), ldk = round_up(q, 64);
-  const size_t ldn = round_up(n, 64), ldm = round_up(m, 64);
-  size_t o = 0;
-  L.A = o; o += al((size_t)m * ld * 4);
-  L.Kinv = o; o += al(q * ldk * 4);
-  L.D = o; o += al((size_t)m * 8);
-  L.E = o; o += al((size_t)n * 8);
-  L.f0 = o; o += al((size_t)5 * m * 8);
-  L.g0 = o; o += al((size_t)5 * n * 8);
-  L.fh = o; o += al((size_t)m);
-  L.gh = o; o += al((size_t)n);
-  L.fs = o; o += al((size_t)5 * m * 4);
-  L.gs = o; o += al((size_t)5 * n * 4);
-  L.vec = o; o += al((5 * ldn + 5 * ldm + ldk) * 4);
-  L.out = o; o += al((size_t)(2 * m + 2 * n) * 4);
-  L.total = o;
-  return L;
+// Problems the serving engine runs on the whole-GPU path: those the grouped
+// path does not take, and those large enough to slow every chunk of the group.
+bool serve_solo(int m, int n) {
+  return !GroupEngine::fits(m, n) || (double)m * n > 16.0 * (1 << 20) || std::min(m, n) > 2048;
 }
 
-// Upload one problem into `base` (device, L.total bytes, zeroed) and fill its descriptor.
-int stage_problem(const HostProblem &hp, char *base, BProb *bp, hipStream_t s, std::vector<double> &tmp) {
-  const int m = hp.m, n = hp.n;
-  const Layout L = layout_of(m, n);
-  const int ld = (int)round_up(n, 64), q = std::min(m, n);
-  POGS_HIP_TRY(hipMemcpy2DAsync(base + L.A, (size_t)ld * 4, hp.A.data(), (size_t)n * 4, (size_t)n * 4, m,
-                                hipMemcpyHostToDevice, s));
-  tmp.resize((size_t)5 * (m + n));
-  const std::vector<double> *fa[5] = {&hp.f.a, &hp.f.b, &hp.f.c, &hp.f.d, &hp.f.e};
-  const std::vector<double> *ga[5] = {&hp.g.a, &hp.g.b, &hp.g.c, &hp.g.d, &hp.g.e};
-  for (int k = 0; k < 5; ++k) memcpy(&tmp[(size_t)k * m], fa[k]->data(), (size_t)m * 8);
-  for (int k = 0; k < 5; ++k) memcpy(&tmp[(size_t)5 * m + (size_t)k * n], ga[k]->data(), (size_t)n * 8);
-  POGS_HIP_TRY(hipMemcpyAsync(base + L.f0, tmp.data(), (size_t)5 * m * 8, hipMemcpyHostToDevice, s));
-  POGS_HIP_TRY(hipMemcpyAsync(base + L.g0, tmp.data() + (size_t)5 * m, (size_t)5 * n * 8, hipMemcpyHostToDevice, s));
-  POGS_HIP_TRY(hipMemcpyAsync(base + L.fh, hp.f.h.data(), m, hipMemcpyHostToDevice, s));
-  POGS_HIP_TRY(hipMemcpyAsync(base + L.gh, hp.g.h.data(), n, hipMemcpyHostToDevice, s));
-  // the host staging must outlive the copies
-  POGS_HIP_TRY(hipStreamSynchronize(s));
-  BProb &b = *bp;
-  memset(&b, 0, sizeof(b));
-  b.m = m;
-  b.n = n;
-  b.ld = ld;
-  b.q = q;
-  b.ldk = (int)round_up(q, 64);
-  b.Q = (int)round_up(q, 64);
-  b.A = (float *)(base + L.A);
-  b.Kinv = (float *)(base + L.Kinv);
-  b.D = (double *)(base + L.D);
-  b.E = (double *)(base + L.E);
-  b.fh = (const uint8_t *)(base + L.fh);
-  b.gh = (const uint8_t *)(base + L.gh);
-  b.f0 = (const double *)(base + L.f0);
-  b.g0 = (const double *)(base + L.g0);
-  b.fs = (float *)(base + L.fs);
-  b.gs = (float *)(base + L.gs);
-  b.vec = (float *)(base + L.vec);
-  b.out = (float *)(base + L.out);
-  b.ldn = (int)round_up(n, 64);
-  b.ldm = (int)round_up(m, 64);
-  const pogs_params &p = hp.params;
-  b.eps_abs = p.eps_abs;
-  b.eps_rel = p.eps_rel;
-  b.rho0 = p.rho0;
-  b.alpha = p.alpha;
-  b.delta = p.delta;
-  b.tau = p.tau;
-  const double eps = p.eps_cmp > 0.0 ? p.eps_cmp : (double)FLT_EPSILON;
-  b.gamma = (double)(m + n) * std::sqrt(eps);
-  b.max_iter = p.max_iter;
-  b.adaptive = p.adaptive_rho ? 1 : 0;
-  b.equil_iters = p.equil_iters;
-  b.status = -1;
-  return POGS_OK;
-}
-
-void fill_result(const BProb &b, pogs_result *out, double ms_solve) {
-  out->optval = b.optval;
-  out->r_pri = b.r_pri;
-  out->r_dual = b.r_dual;
-  out->eps_pri = b.eps_pri;
-  out->eps_dual = b.eps_dual;
-  out->rho = b.rho;
-  out->iters = b.k;
-  out->status = b.bad ? POGS_NUMERICAL : b.status;
+void fill_result(const GStatus &st, pogs_result *out, double ms_solve) {
+  const CtrlState &c = st.st;
+  out->optval = st.obj;
+  out->r_pri = c.r_pri;
+  out->r_dual = c.r_dual;
+  out->eps_pri = c.eps_pri;
+  out->eps_dual = c.eps_dual;
+  out->rho = c.rho;
+  out->iters = c.k;
+  out->status = st.flags[1] ? POGS_NUMERICAL : (c.done ? c.done - 1 : POGS_MAXITER);
   out->ms_setup = 0.0;
   out->ms_solve = ms_solve;
-}
-
-int copy_outputs(const char *dev_out, int m, int n, pogs_result *out, hipStream_t s) {
-  const float *o = (const float *)dev_out;
-  const hipMemcpyKind k = out->mem == POGS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  if (out->x) POGS_HIP_TRY(hipMemcpyAsync(out->x, o, (size_t)n * 4, k, s));
-  if (out->y) POGS_HIP_TRY(hipMemcpyAsync(out->y, o + n, (size_t)m * 4, k, s));
-  if (out->mu) POGS_HIP_TRY(hipMemcpyAsync(out->mu, o + n + m, (size_t)n * 4, k, s));
-  if (out->nu) POGS_HIP_TRY(hipMemcpyAsync(out->nu, o + 2 * n + m, (size_t)m * 4, k, s));
-  return POGS_OK;
 }
 
 // Whole-GPU path for one problem (used for problems too large for a workgroup).
@@ -189,22 +111,6 @@ int solve_large(const HostProblem &hp, pogs_result *out, hipStream_t s) {
   return rc;
 }
 
-struct DevBuf {
-  void *p = nullptr;
-  ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-  }
-  int alloc(size_t b) {
-    if (hipMalloc(&p, std::max<size_t>(b, 256)) != hipSuccess) {
-      p = nullptr;
-      return POGS_ENOMEM;
-    }
-    return POGS_OK;
-  }
-};
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -213,9 +119,11 @@ struct DevBuf {
 extern "C" int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_result *out, void *stream) {
   if (nprob <= 0 || !probs || !out) return POGS_EINVAL;
   const double t0 = now_ms();
-  std::vector<HostProblem> hp(nprob);
+  std::vector<HostFn> fs(nprob), gs(nprob);
   for (int i = 0; i < nprob; ++i) {
-    int rc = make_host_problem(&probs[i], &hp[i]);
+    int rc = check_problem(&probs[i]);
+    if (!rc) rc = expand_fn(&probs[i].f, probs[i].m, &fs[i]);
+    if (!rc) rc = expand_fn(&probs[i].g, probs[i].n, &gs[i]);
     if (rc) return rc;
     if (out[i].mem != POGS_HOST && out[i].mem != POGS_DEVICE) return POGS_EINVAL;
   }
@@ -232,61 +140,57 @@ extern "C" int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_r
       if (own) (void)hipStreamDestroy(s);
     }
   } guard{s, own};
-  std::vector<int> small, large;
-  for (int i = 0; i < nprob; ++i) (fits_workgroup(hp[i].m, hp[i].n) ? small : large).push_back(i);
+  std::vector<int> grouped, large;
+  for (int i = 0; i < nprob; ++i)
+    (GroupEngine::fits((int)probs[i].m, (int)probs[i].n) ? grouped : large).push_back(i);
   int rc;
-  if (!small.empty()) {
-    std::vector<size_t> off(small.size());
-    size_t total = 0;
-    int Qmax = 0, nmax = 0;
-    for (size_t k = 0; k < small.size(); ++k) {
-      const HostProblem &p = hp[small[k]];
-      off[k] = total;
-      total += layout_of(p.m, p.n).total;
-      Qmax = std::max(Qmax, (int)round_up(std::min(p.m, p.n), 64));
-      nmax = std::max(nmax, std::max(p.n, std::min(p.m, p.n)));
+  if (!grouped.empty()) {
+    GroupEngine eng(s, (int)grouped.size());
+    if ((rc = eng.init())) return rc;
+    std::vector<int> handle(nprob, -1), active;
+    int chunk = 0;
+    for (int i : grouped) {
+      const pogs_problem &p = probs[i];
+      GroupEngine::Input in;
+      in.m = (int)p.m;
+      in.n = (int)p.n;
+      in.A = (const float *)p.A;
+      in.colmajor = p.ord == POGS_COL_MAJOR;
+      in.lda = p.lda;
+      in.f = &fs[i];
+      in.g = &gs[i];
+      in.params = p.params;
+      if ((rc = eng.add(in, &handle[i]))) return rc;
+      active.push_back(handle[i]);
+      chunk = std::max(chunk, p.params.chunk_iters > 0 ? p.params.chunk_iters : 20);
     }
-    const int count = (int)small.size();
-    const int slots = std::min(count, 512);
-    const size_t slot_doubles = batch_slot_doubles(Qmax);
-    DevBuf arena, descs, scratch;
-    if ((rc = arena.alloc(total))) return rc;
-    if ((rc = descs.alloc(count * sizeof(BProb) + count * sizeof(int) + 256))) return rc;
-    if ((rc = scratch.alloc(slots * slot_doubles * sizeof(double)))) return rc;
-    POGS_HIP_TRY(hipMemsetAsync(arena.p, 0, total, s));
-    std::vector<BProb> hb(count);
-    std::vector<double> tmp;
-    for (int k = 0; k < count; ++k)
-      if ((rc = stage_problem(hp[small[k]], (char *)arena.p + off[k], &hb[k], s, tmp))) return rc;
-    // largest estimated work first (setup ~ m q^2, iterations ~ m n)
-    std::vector<int> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    auto cost = [&](int k) {
-      const double m = hb[k].m, n = hb[k].n, q = hb[k].q;
-      return m * n * 200.0 + m * q * q / 16.0;
-    };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    BProb *dprobs = (BProb *)descs.p;
-    int *dorder = (int *)((char *)descs.p + count * sizeof(BProb));
-    unsigned *dnext = (unsigned *)((char *)dorder + count * sizeof(int));
-    POGS_HIP_TRY(hipMemcpyAsync(dprobs, hb.data(), count * sizeof(BProb), hipMemcpyHostToDevice, s));
-    POGS_HIP_TRY(hipMemcpyAsync(dorder, order.data(), count * sizeof(int), hipMemcpyHostToDevice, s));
-    POGS_HIP_TRY(hipMemsetAsync(dnext, 0, sizeof(unsigned), s));
-    launch_batch(dprobs, dorder, count, dnext, (double *)scratch.p, slot_doubles, slots, nmax, 0x7fffffff, s);
-    POGS_HIP_TRY(hipGetLastError());
-    POGS_HIP_TRY(hipMemcpyAsync(hb.data(), dprobs, count * sizeof(BProb), hipMemcpyDeviceToHost, s));
-    POGS_HIP_TRY(hipStreamSynchronize(s));
-    const double ms = now_ms() - t0;
-    for (int k = 0; k < count; ++k) {
-      const int i = small[k];
-      fill_result(hb[k], &out[i], ms);
-      const Layout L = layout_of(hp[i].m, hp[i].n);
-      if ((rc = copy_outputs((const char *)arena.p + off[k] + L.out, hp[i].m, hp[i].n, &out[i], s))) return rc;
+    if ((rc = eng.setup(active))) return rc;
+    for (int h : active)
+      if (eng.status(h).flags[0]) return POGS_EINVAL;  // non-finite entries in A
+    std::vector<int> index_of(grouped.size());
+    for (int i : grouped) index_of[handle[i]] = i;
+    while (!active.empty()) {
+      if ((rc = eng.run_chunk(active, chunk))) return rc;
+      std::vector<int> done, still;
+      for (int h : active) (eng.status(h).st.done || eng.status(h).flags[1] ? done : still).push_back(h);
+      if (!done.empty()) {
+        if ((rc = eng.finish(done))) return rc;
+        for (int h : done) {
+          const int i = index_of[h];
+          fill_result(eng.status(h), &out[i], now_ms() - t0);
+          if ((rc = eng.copy_out(h, out[i].x, out[i].y, out[i].mu, out[i].nu, out[i].mem))) return rc;
+          eng.remove(h);
+        }
+      }
+      active.swap(still);
     }
     POGS_HIP_TRY(hipStreamSynchronize(s));
   }
-  for (int i : large)
-    if ((rc = solve_large(hp[i], &out[i], s))) return rc;
+  for (int i : large) {
+    HostProblem hp;
+    if ((rc = make_host_problem(&probs[i], &hp))) return rc;
+    if ((rc = solve_large(hp, &out[i], s))) return rc;
+  }
   return POGS_OK;
 }
 
@@ -302,8 +206,7 @@ struct Request {
   bool cancel = false;
   bool large = false;
   size_t bytes = 0;
-  DevBuf mem;
-  int slot = -1;
+  int handle = -1;  // grouped engine handle while resident
   pogs_result res{};
   std::vector<float> xo, yo, muo, nuo;
   double t_submit = 0.0;
@@ -324,10 +227,7 @@ struct pogs_batch {
   std::vector<std::shared_ptr<Request>> resident;
   size_t budget = 0, used = 0, fixed = 0;
   int pending = 0;
-  // device resources of the rounds
-  DevBuf descs, scratch;
-  int slots = 0;
-  size_t slot_doubles = 0;
+  std::unique_ptr<GroupEngine> eng;
   std::thread worker, solo;
   int error = 0;
 
@@ -341,21 +241,13 @@ void pogs_batch::finish(const std::shared_ptr<Request> &r, int status_override) 
   if (status_override >= 0) r->res.status = status_override;
   r->state = 2;
   if (r->bytes) used -= r->bytes;
-  r->mem.release();
   --pending;
   cv_done.notify_all();
   cv.notify_all();
 }
 
 void pogs_batch::run() {
-  std::vector<BProb> hb;
-  std::vector<double> tmp;
-  std::vector<int> order;
-  BProb *dprobs = (BProb *)descs.p;
-  int *dorder = (int *)((char *)descs.p + cfg.max_slots * sizeof(BProb));
-  unsigned *dnext = (unsigned *)((char *)dorder + cfg.max_slots * sizeof(int));
-  std::vector<int> free_slots(cfg.max_slots);
-  std::iota(free_slots.rbegin(), free_slots.rend(), 0);
+  int free_slots = cfg.max_slots;
   for (;;) {
     std::vector<std::shared_ptr<Request>> admitted;
     {
@@ -363,7 +255,7 @@ void pogs_batch::run() {
       cv.wait(lk, [&] { return stop || !queue.empty() || !resident.empty(); });
       if (stop) return;
       // admit while memory and slots allow (first come, first served)
-      while (!queue.empty() && !free_slots.empty()) {
+      while (!queue.empty() && free_slots > 0) {
         auto r = queue.front();
         if (r->cancel) {
           queue.pop_front();
@@ -376,28 +268,47 @@ void pogs_batch::run() {
         if (used + r->bytes > budget) break;
         queue.pop_front();
         used += r->bytes;
-        r->slot = free_slots.back();
-        free_slots.pop_back();
+        --free_slots;
         r->state = 1;
         admitted.push_back(r);
       }
     }
+    // upload and set up the newly admitted requests as one group
+    std::vector<int> fresh;
+    std::vector<std::shared_ptr<Request>> fresh_req;
     for (auto &r : admitted) {
-      BProb b;
-      int rc = r->mem.alloc(r->bytes);
-      if (!rc) rc = hipMemsetAsync(r->mem.p, 0, r->bytes, stream) == hipSuccess ? 0 : POGS_EDEVICE;
-      if (!rc) rc = stage_problem(r->hp, (char *)r->mem.p, &b, stream, tmp);
-      if (!rc) rc = hipMemcpyAsync(dprobs + r->slot, &b, sizeof(BProb), hipMemcpyHostToDevice, stream) == hipSuccess
-                        ? 0 : POGS_EDEVICE;
-      if (!rc) rc = hipStreamSynchronize(stream) == hipSuccess ? 0 : POGS_EDEVICE;
+      GroupEngine::Input in;
+      in.m = r->hp.m;
+      in.n = r->hp.n;
+      in.A = r->hp.A.data();
+      in.lda = r->hp.n;
+      in.f = &r->hp.f;
+      in.g = &r->hp.g;
+      in.params = r->hp.params;
+      const int rc = eng->add(in, &r->handle);
       if (rc) {
-        free_slots.push_back(r->slot);
-        r->res.status = POGS_NUMERICAL;
+        ++free_slots;
+        r->handle = -1;
+        finish(r, POGS_NUMERICAL);
+        continue;
+      }
+      fresh.push_back(r->handle);
+      fresh_req.push_back(r);
+    }
+    int rc = eng->setup(fresh);
+    for (auto &r : fresh_req) {
+      if (rc || eng->status(r->handle).flags[0]) {
+        eng->remove(r->handle);
+        ++free_slots;
         finish(r, POGS_NUMERICAL);
         continue;
       }
       std::lock_guard<std::mutex> g(mu);
       resident.push_back(r);
+    }
+    if (rc) {
+      std::lock_guard<std::mutex> g(mu);
+      error = rc;
     }
     std::vector<std::shared_ptr<Request>> live;
     {
@@ -405,62 +316,40 @@ void pogs_batch::run() {
       live = resident;
     }
     if (live.empty()) continue;
-    // one round: every resident problem advances by at most chunk_iters iterations
-    order.clear();
-    int nmax = 1, Qmax = 64;
+    // one chunk: every resident problem advances by chunk_iters iterations
+    std::vector<int> hs;
+    for (auto &r : live) hs.push_back(r->handle);
+    rc = eng->run_chunk(hs, cfg.chunk_iters);
+    std::vector<std::shared_ptr<Request>> done;
+    std::vector<int> done_h;
     for (auto &r : live) {
-      order.push_back(r->slot);
-      nmax = std::max(nmax, std::max(r->hp.n, std::min(r->hp.m, r->hp.n)));
-      Qmax = std::max(Qmax, (int)round_up(std::min(r->hp.m, r->hp.n), 64));
+      const GStatus &st = eng->status(r->handle);
+      if (rc || st.st.done || st.flags[1] || r->cancel) {
+        done.push_back(r);
+        if (!r->cancel && !rc) done_h.push_back(r->handle);
+      }
     }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-      auto ra = std::find_if(live.begin(), live.end(), [&](auto &r) { return r->slot == a; });
-      auto rb = std::find_if(live.begin(), live.end(), [&](auto &r) { return r->slot == b; });
-      return (double)(*ra)->hp.m * (*ra)->hp.n > (double)(*rb)->hp.m * (*rb)->hp.n;
-    });
-    const int count = (int)order.size();
-    int rc = hipMemcpyAsync(dorder, order.data(), count * sizeof(int), hipMemcpyHostToDevice, stream) == hipSuccess
-                 ? 0 : POGS_EDEVICE;
-    if (!rc) rc = hipMemsetAsync(dnext, 0, sizeof(unsigned), stream) == hipSuccess ? 0 : POGS_EDEVICE;
-    if (!rc) {
-      launch_batch(dprobs, dorder, count, dnext, (double *)scratch.p, slot_doubles, std::min(count, slots), nmax,
-                   cfg.chunk_iters, stream);
-      rc = hipGetLastError() == hipSuccess ? 0 : POGS_EDEVICE;
-    }
-    hb.resize(cfg.max_slots);
-    if (!rc) rc = hipMemcpyAsync(hb.data(), dprobs, cfg.max_slots * sizeof(BProb), hipMemcpyDeviceToHost, stream) ==
-                          hipSuccess ? 0 : POGS_EDEVICE;
-    if (!rc) rc = hipStreamSynchronize(stream) == hipSuccess ? 0 : POGS_EDEVICE;
+    if (!rc && !done_h.empty()) rc = eng->finish(done_h);
     if (rc) {
       std::lock_guard<std::mutex> g(mu);
       error = rc;
     }
-    for (auto &r : live) {
-      const BProb &b = hb[r->slot];
-      const bool done = rc || b.bad || (b.setup_done && b.status >= 0) || r->cancel;
-      if (!done) continue;
-      fill_result(b, &r->res, now_ms() - r->t_submit);
+    for (auto &r : done) {
       const int m = r->hp.m, n = r->hp.n;
-      r->xo.resize(n);
-      r->yo.resize(m);
-      r->muo.resize(n);
-      r->nuo.resize(m);
-      pogs_result tmpres{};
-      tmpres.mem = POGS_HOST;
-      tmpres.x = r->xo.data();
-      tmpres.y = r->yo.data();
-      tmpres.mu = r->muo.data();
-      tmpres.nu = r->nuo.data();
+      fill_result(eng->status(r->handle), &r->res, now_ms() - r->t_submit);
       if (!rc && !r->cancel) {
-        const Layout L = layout_of(m, n);
-        copy_outputs((const char *)r->mem.p + L.out, m, n, &tmpres, stream);
-        (void)hipStreamSynchronize(stream);
+        r->xo.resize(n);
+        r->yo.resize(m);
+        r->muo.resize(n);
+        r->nuo.resize(m);
+        (void)eng->copy_out(r->handle, r->xo.data(), r->yo.data(), r->muo.data(), r->nuo.data(), POGS_HOST);
       }
+      eng->remove(r->handle);
+      ++free_slots;
       {
         std::lock_guard<std::mutex> g(mu);
         resident.erase(std::find(resident.begin(), resident.end(), r));
       }
-      free_slots.push_back(r->slot);
       finish(r, rc ? POGS_NUMERICAL : (r->cancel ? POGS_CANCELLED : -1));
     }
   }
@@ -507,7 +396,7 @@ extern "C" int pogs_batch_create(pogs_batch **out, const pogs_batch_cfg *cfg) {
   if (!b) return POGS_ENOMEM;
   if (cfg) b->cfg = *cfg;
   if (b->cfg.max_slots <= 0) b->cfg.max_slots = 1024;
-  if (b->cfg.chunk_iters <= 0) b->cfg.chunk_iters = 50;
+  if (b->cfg.chunk_iters <= 0) b->cfg.chunk_iters = 20;
   if (b->cfg.stream) {
     b->stream = (hipStream_t)b->cfg.stream;
   } else {
@@ -518,16 +407,14 @@ extern "C" int pogs_batch_create(pogs_batch **out, const pogs_batch_cfg *cfg) {
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return POGS_EDEVICE;
   b->budget = b->cfg.hbm_budget_bytes ? b->cfg.hbm_budget_bytes : (size_t)(0.8 * (double)fr);
-  b->slots = 256;
-  b->slot_doubles = batch_slot_doubles(kBatchMaxQ);
-  const size_t sbytes = (size_t)b->slots * b->slot_doubles * sizeof(double);
-  const size_t dbytes = (size_t)b->cfg.max_slots * (sizeof(BProb) + sizeof(int)) + 256;
-  if (sbytes + dbytes >= b->budget) return POGS_EAGAIN;
-  int rc;
-  if ((rc = b->scratch.alloc(sbytes))) return rc;
-  if ((rc = b->descs.alloc(dbytes))) return rc;
-  b->fixed = sbytes + dbytes;
+  // the engine's own arrays: descriptors, status, work lists
+  b->fixed = (size_t)b->cfg.max_slots * (sizeof(GProb) + sizeof(GStatus) + 64 * sizeof(GItem)) + (1 << 20);
+  if (b->fixed >= b->budget) return POGS_EAGAIN;
   b->budget -= b->fixed;
+  b->eng.reset(new (std::nothrow) GroupEngine(b->stream, b->cfg.max_slots));
+  if (!b->eng) return POGS_ENOMEM;
+  int rc;
+  if ((rc = b->eng->init())) return rc;
   b->worker = std::thread([p = b.get()] { p->run(); });
   b->solo = std::thread([p = b.get()] { p->run_solo(); });
   *out = b.release();
@@ -539,9 +426,9 @@ extern "C" int pogs_batch_submit(pogs_batch *b, const pogs_problem *p, uint64_t 
   auto r = std::make_shared<Request>();
   int rc = make_host_problem(p, &r->hp);
   if (rc) return rc;
-  r->large = !fits_workgroup(r->hp.m, r->hp.n);
+  r->large = serve_solo(r->hp.m, r->hp.n);
   if (!r->large) {
-    r->bytes = layout_of(r->hp.m, r->hp.n).total;
+    r->bytes = GroupEngine::bytes_for(r->hp.m, r->hp.n);
     if (r->bytes > b->budget) return POGS_EAGAIN;
   } else {
     const size_t q = std::min(r->hp.m, r->hp.n);
@@ -625,7 +512,7 @@ extern "C" int pogs_batch_destroy(pogs_batch *b) {
     (void)hipStreamSynchronize(b->solo_stream);
     (void)hipStreamDestroy(b->solo_stream);
   }
-  for (auto &r : b->resident) r->mem.release();
+  b->eng.reset();
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return POGS_OK;

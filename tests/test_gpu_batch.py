@@ -1,5 +1,5 @@
-"""GPU tests of the batched solver (one persistent launch, one workgroup per
-problem) and the serving engine (continuous batching).
+"""GPU tests of the batched solver (grouped launches: one launch per phase for
+all problems of a group) and the serving engine (continuous batching).
 
 Tolerances: objectives |p - p_oracle| <= 1e-3 max(|p_oracle|, 1) against the
 FP64 oracle; a problem solved alone, in a mix, in one launch or over many
@@ -68,7 +68,7 @@ def test_batch_agrees_with_whole_gpu_path():
 
 
 def test_batch_routes_large_problem_to_whole_gpu_path():
-    big = W.lasso(2600, 2200, 21)  # min(m, n) above the one-workgroup limit
+    big = W.lasso(600, 4500, 21)  # n above the grouped path's limit
     small = W.lasso(300, 100, 22)
     res = P.pogs_solve_batch([small, big])
     for p, r in zip([small, big], res):
@@ -117,16 +117,20 @@ def test_serving_cancel_and_unknown_ticket():
 
 
 def test_serving_budget_refusal():
-    # the engine's own per-slot factor scratch does not fit 1 GiB: refused
+    # the engine's own descriptor and work-list arrays do not fit 1 MiB: refused
     with pytest.raises(P.PogsError) as ei:
-        P.BatchEngine(hbm_budget_bytes=1 << 30)
+        P.BatchEngine(hbm_budget_bytes=1 << 20)
     assert ei.value.code == P.POGS_EAGAIN
     # a request larger than the whole budget is refused at submit
-    eng = P.BatchEngine(hbm_budget_bytes=int(16.25 * 2 ** 30) + (32 << 20))
+    eng = P.BatchEngine(hbm_budget_bytes=64 << 20)
     try:
         with pytest.raises(P.PogsError) as ei:
             eng.submit(W.lasso(8000, 2000, 51))
         assert ei.value.code == P.POGS_EAGAIN
+        # and a small one is accepted and solved
+        t = eng.submit(W.lasso(200, 50, 52))
+        eng.wait_all()
+        assert eng.poll(t).converged
     finally:
         eng.close()
 
