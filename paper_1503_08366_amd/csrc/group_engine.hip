@@ -122,6 +122,7 @@ GroupEngine::~GroupEngine() {
   if (status_dev_) (void)hipFreeAsync(status_dev_, s_);
   if (items_dev_) (void)hipFreeAsync(items_dev_, s_);
   (void)hipStreamSynchronize(s_);
+  if (items_copied_) (void)hipEventDestroy(items_copied_);
   if (status_host_) (void)hipHostFree(status_host_);
   if (items_host_) (void)hipHostFree(items_host_);
   if (fn_stage_) (void)hipHostFree(fn_stage_);
@@ -298,6 +299,9 @@ void GroupEngine::remove(int h) {
 // Concatenate the lists into the pinned staging buffer and one device
 // buffer; ptrs[i] is the device address of list i.
 int GroupEngine::upload_items(const std::vector<std::vector<GItem>> &lists, std::vector<const GItem *> *ptrs) {
+  // the previous copy out of the pinned staging must have completed before
+  // the staging is overwritten (the copy is asynchronous)
+  if (items_copied_) POGS_HIP_TRY(hipEventSynchronize(items_copied_));
   size_t total = 0;
   for (const auto &l : lists) total += l.size();
   total = std::max<size_t>(total, 1);
@@ -322,7 +326,11 @@ int GroupEngine::upload_items(const std::vector<std::vector<GItem>> &lists, std:
     ptrs->push_back(items_dev_ + off);
     off += l.size();
   }
-  if (off) POGS_HIP_TRY(hipMemcpyAsync(items_dev_, items_host_, off * sizeof(GItem), hipMemcpyHostToDevice, s_));
+  if (off) {
+    POGS_HIP_TRY(hipMemcpyAsync(items_dev_, items_host_, off * sizeof(GItem), hipMemcpyHostToDevice, s_));
+    if (!items_copied_) POGS_HIP_TRY(hipEventCreateWithFlags(&items_copied_, hipEventDisableTiming));
+    POGS_HIP_TRY(hipEventRecord(items_copied_, s_));
+  }
   return POGS_OK;
 }
 

@@ -72,6 +72,7 @@ class GroupEngine {
   size_t items_cap_ = 0;
   GItem *items_host_ = nullptr;     // pinned staging of the work lists
   size_t items_host_cap_ = 0;
+  hipEvent_t items_copied_ = nullptr;  // the last copy out of items_host_
   char *fn_stage_ = nullptr;        // pinned staging of function parameters
   size_t fn_stage_cap_ = 0;
   float *out_stage_ = nullptr;      // pinned staging of returned vectors
