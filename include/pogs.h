@@ -142,10 +142,17 @@ int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, pogs_dtype dt
               void *stream);
 
 /* Solve with functions f (len m) and g (len n) on the context's matrix.
- * params may be NULL (the context's).  x0 and nu0 are reserved for warm
- * starts and must be NULL (POGS_EUNSUPPORTED otherwise).
+ * params may be NULL (the context's).
+ * Warm start (Section 5: the caller may supply x0 and nu0): x0 (len n) and
+ * nu0 (len m), in the context's dtype and in the memory space out->mem says,
+ * are a primal point and a dual estimate in the original variables; either
+ * may be NULL (that part starts from zero, as Algorithm 1 does).  The state
+ * they define: x = E^-1 x0 and y = A^ x on the graph, y~ = -(D^-1 nu0)/rho0
+ * (the scaled dual the prox step returns when it leaves y unchanged) and
+ * x~ = -A^T y~ (the relation every projection restores); from an optimal
+ * pair this state is a fixed point and the solve stops after one iteration.
  * Errors: EINVAL (NULL ctx/f/g/out, wrong lengths, c < 0, e < 0, a == 0 with
- * c > 0, unknown h, non-finite parameters), EUNSUPPORTED, EDEVICE. */
+ * c > 0, unknown h, non-finite parameters), EDEVICE. */
 int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, const pogs_params *params,
                const void *x0, const void *nu0, pogs_result *out);
 

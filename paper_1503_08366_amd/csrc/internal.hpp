@@ -109,6 +109,12 @@ template <typename T> void launch_prox_eval(const uint8_t *h, const T *a, const 
                                             const T *d, const T *e, double rho, const T *v, T *out,
                                             int len, hipStream_t s);
 
+// Warm start of the iteration state from (x0, nu0) (device, original
+// variables; either may be NULL): x, y = A^ x, y~, x~ = -A^T y~.
+template <typename T>
+void launch_warm_start(const IterArgs<T> &p, int splits, int rps, int ncolp, const double *D, const double *E,
+                       double rho0, const T *x0, const T *nu0, hipStream_t s);
+
 // Iteration geometry helpers.
 int gemv_t_tile(int elem_size);
 void gemv_t_geometry(int m, int ncols, int elem_size, int *splits, int *rows_per_split, int *ncolp);

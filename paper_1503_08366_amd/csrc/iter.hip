@@ -255,6 +255,48 @@ void launch_project(const IterArgs<T> &p, int splits, int rps, int ncolp, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Warm start from (x0, nu0) in the original variables: x = E^-1 x0 and
+// y = A^ x (a point of the graph); y~ = -(D^-1 nu0) / rho0 (the scaled dual
+// the prox step returns when it leaves y unchanged); x~ = -A^T y~ (the
+// relation every projection restores).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void warm_scale_kernel(const T *v0, const double *S, bool divide, double f,
+                                                            int len, T *out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < len) out[i] = (T)(f * (divide ? (double)v0[i] / S[i] : (double)v0[i] * S[i]));
+}
+template <typename T> struct EpiWarmY : EpiNoSkip<T> {  // y = A x
+  T *y;
+  __device__ double row(int i, double v, double) const { y[i] = (T)v; return 0.0; }
+  __device__ void block_done(int, double) const {}
+};
+template <typename T> struct EpiWarmXt : EpiNoSkip<T> {  // x~ = -A^T y~
+  T *xt;
+  __device__ double column(int j, double v, double) const { xt[j] = (T)(-v); return 0.0; }
+  __device__ void tile_done(int, double) const {}
+};
+
+template <typename T>
+void launch_warm_start(const IterArgs<T> &p, int splits, int rps, int ncolp, const double *D, const double *E,
+                       double rho0, const T *x0, const T *nu0, hipStream_t s) {
+  if (x0) {
+    hipLaunchKernelGGL(warm_scale_kernel<T>, dim3(cdiv(p.n, kBlock)), dim3(kBlock), 0, s, x0, E, true, 1.0, p.n,
+                       p.x);
+    EpiWarmY<T> e;
+    e.y = p.y;
+    gemv_n<T, T, 1>(p.A, p.m, p.n, p.ld, (const T *)p.x, (const T *)p.x, e, s);
+  }
+  if (nu0) {
+    hipLaunchKernelGGL(warm_scale_kernel<T>, dim3(cdiv(p.m, kBlock)), dim3(kBlock), 0, s, nu0, D, true,
+                       -1.0 / rho0, p.m, p.yt);
+    EpiWarmXt<T> e;
+    e.xt = p.xt;
+    gemv_t<T, T, 1>(p.A, p.m, p.n, p.ld, (const T *)p.yt, (const T *)p.yt, splits, rps, p.part, ncolp, e, s);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void scale_fn_kernel(const uint8_t *h, const double *a, const double *b,
                                                           const double *c, const double *d, const double *e,
@@ -314,6 +356,8 @@ void launch_prox_eval(const uint8_t *h, const T *a, const T *b, const T *c, cons
   template void launch_control_preview<T>(const IterArgs<T> &, int, hipStream_t);                      \
   template void launch_project<T>(const IterArgs<T> &, int, int, int, const T *, const T *, T *, T *,  \
                                   hipStream_t);                                                        \
+  template void launch_warm_start<T>(const IterArgs<T> &, int, int, int, const double *, const double *, \
+                                     double, const T *, const T *, hipStream_t);                         \
   template void launch_scale_fn<T>(const uint8_t *, const double *, const double *, const double *,    \
                                    const double *, const double *, const double *, bool, int,          \
                                    uint8_t *, T *, T *, T *, T *, T *, hipStream_t);                   \

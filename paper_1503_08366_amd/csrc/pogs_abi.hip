@@ -305,14 +305,29 @@ template <typename T> int ensure_graph(pogs_ctx *c, int chunk) {
 }
 
 template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn &g, const pogs_params &p,
-                                     pogs_result *out) {
+                                     const void *x0, const void *nu0, pogs_result *out) {
   const double t0 = now_ms();
   const int m = (int)c->m, n = (int)c->n;
   hipStream_t s = c->stream;
   int rc;
   if ((rc = upload_fns<T>(c, f, g))) return rc;
-  // zero state (Algorithm 1 starts from x = y = x~ = y~ = 0)
+  // zero state (Algorithm 1 starts from x = y = x~ = y~ = 0), or the warm start
   POGS_HIP_TRY(hipMemsetAsync(c->vec, 0, c->vec_elems() * sizeof(T), s));
+  if (x0 || nu0) {
+    const T *dx0 = (const T *)x0, *dnu0 = (const T *)nu0;
+    if (out->mem == POGS_HOST) {  // staged in the output vectors (written again at the end)
+      if (x0) {
+        POGS_HIP_TRY(hipMemcpyAsync(c->vecp<T>(11), x0, (size_t)n * sizeof(T), hipMemcpyHostToDevice, s));
+        dx0 = c->vecp<T>(11);
+      }
+      if (nu0) {
+        POGS_HIP_TRY(hipMemcpyAsync(c->vecp<T>(14), nu0, (size_t)m * sizeof(T), hipMemcpyHostToDevice, s));
+        dnu0 = c->vecp<T>(14);
+      }
+    }
+    launch_warm_start<T>(c->iter_args<T>(), c->splits, c->rps, c->ncolp, c->D, c->E, p.rho0, dx0, dnu0, s);
+    if (out->mem == POGS_HOST) POGS_HIP_TRY(hipStreamSynchronize(s));  // host x0, nu0 may be pageable
+  }
   Ctrl h{};
   h.eps_abs = p.eps_abs;
   h.eps_rel = p.eps_rel;
@@ -435,7 +450,7 @@ template <typename T> int profile_impl(pogs_ctx *c, int reps, double *ms) {
 extern "C" int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, const pogs_params *params,
                           const void *x0, const void *nu0, pogs_result *out) {
   if (!ctx || !f || !g || !out) return POGS_EINVAL;
-  if (x0 || nu0) return POGS_EUNSUPPORTED;
+
   if (out->mem != POGS_HOST && out->mem != POGS_DEVICE) return POGS_EINVAL;
   pogs_params p = params ? *params : ctx->params;
   if (check_params(p)) return POGS_EINVAL;
@@ -443,7 +458,8 @@ extern "C" int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, con
   int rc;
   if ((rc = expand_fn(f, ctx->m, &hf))) return rc;
   if ((rc = expand_fn(g, ctx->n, &hg))) return rc;
-  return ctx->dt == POGS_F32 ? solve_impl<float>(ctx, hf, hg, p, out) : solve_impl<double>(ctx, hf, hg, p, out);
+  return ctx->dt == POGS_F32 ? solve_impl<float>(ctx, hf, hg, p, x0, nu0, out)
+                             : solve_impl<double>(ctx, hf, hg, p, x0, nu0, out);
 }
 
 extern "C" int pogs_profile_iteration(pogs_ctx *ctx, int32_t reps, double *ms) {

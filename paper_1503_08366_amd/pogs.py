@@ -312,10 +312,31 @@ class Context:
     def __exit__(self, *exc):
         self.free()
 
-    def solve(self, f, g, params: Optional[pogs_params] = None, device_out: bool = False) -> Result:
+    def solve(self, f, g, params: Optional[pogs_params] = None, device_out: bool = False,
+              x0=None, nu0=None) -> Result:
+        """Solve; x0 (n) and nu0 (m) warm-start the iteration (original
+        variables; NumPy arrays, or torch device tensors with device_out)."""
         fh, gh = _FnHolder(f, self.m), _FnHolder(g, self.n)
         r = pogs_result()
         npdt = _np_dtype(self.dtype)
+        keep = []
+
+        def _warm(v, k):
+            if v is None:
+                return None
+            if device_out:
+                import torch
+                tdt = torch.float32 if self.dtype == POGS_F32 else torch.float64
+                t = torch.as_tensor(v).to(device="cuda", dtype=tdt).contiguous()
+                if t.numel() != k:
+                    raise ValueError("warm-start vector has the wrong length")
+                keep.append(t)
+                return C.c_void_p(t.data_ptr())
+            a = np.ascontiguousarray(v, dtype=npdt)
+            if a.size != k:
+                raise ValueError("warm-start vector has the wrong length")
+            keep.append(a)
+            return a.ctypes.data_as(C.c_void_p)
         if device_out:
             import torch
             tdt = torch.float32 if self.dtype == POGS_F32 else torch.float64
@@ -326,8 +347,9 @@ class Context:
             outs = [np.empty(k, dtype=npdt) for k in (self.n, self.m, self.n, self.m)]
             r.x, r.y, r.mu, r.nu = (o.ctypes.data for o in outs)
             r.mem = POGS_HOST
+        wx, wnu = _warm(x0, self.n), _warm(nu0, self.m)
         rc = _lib().pogs_solve(self._h(), C.byref(fh.s), C.byref(gh.s),
-                               C.byref(params) if params is not None else None, None, None, C.byref(r))
+                               C.byref(params) if params is not None else None, wx, wnu, C.byref(r))
         _check(rc, "pogs_solve")
         return Result(r, *outs)
 
@@ -348,6 +370,18 @@ class Context:
         rc = _lib().pogs_solve_path(self._h(), R, farr, garr, C.byref(params) if params is not None else None, res)
         _check(rc, "pogs_solve_path")
         return [Result(res[r], *outs[r]) for r in range(R)]
+
+    def solve_continuation(self, fs: Sequence, gs: Sequence, params: Optional[pogs_params] = None) -> List[Result]:
+        """Solve a sequence of problems on this matrix (e.g. a lambda path),
+        each warm-started from the previous one's (x, nu)."""
+        out = []
+        prev = None
+        for f, g in zip(fs, gs):
+            r = self.solve(f, g, params, x0=None if prev is None else prev.x,
+                           nu0=None if prev is None else prev.nu)
+            out.append(r)
+            prev = r
+        return out
 
     def profile_iteration(self, reps: int = 50):
         """Average ms of a full iteration and of each iteration kernel (HIP events)."""
