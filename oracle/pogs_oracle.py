@@ -34,7 +34,8 @@ import numpy as np
 # ---------------------------------------------------------------------------
 
 H_NAMES = ("zero", "identity", "abs", "square", "huber", "hinge", "logistic",
-           "ind_ge0", "ind_le0", "ind_eq0", "ind_box01")
+           "ind_ge0", "ind_le0", "ind_eq0", "ind_box01",
+           "exp", "neg_entr", "neg_log", "recipr", "max_neg0")
 
 
 def h_eval(h: str, u, tol: float = 0.0):
@@ -67,6 +68,20 @@ def h_eval(h: str, u, tol: float = 0.0):
         return np.where(np.abs(u) <= tol, 0.0, np.inf)
     if h == "ind_box01":
         return np.where((u >= -tol) & (u <= 1.0 + tol), 0.0, np.inf)
+    if h == "exp":
+        return np.exp(u)
+    if h == "neg_entr":  # u log u on u >= 0 (0 at 0)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            v = np.where(u > 0.0, u * np.log(np.where(u > 0.0, u, 1.0)), 0.0)
+        return np.where(u >= -tol, v, np.inf)
+    if h == "neg_log":  # -log u on u > 0
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(u > 0.0, -np.log(np.where(u > 0.0, u, 1.0)), np.inf)
+    if h == "recipr":  # 1 / u on u > 0
+        with np.errstate(divide="ignore"):
+            return np.where(u > 0.0, 1.0 / np.where(u > 0.0, u, 1.0), np.inf)
+    if h == "max_neg0":
+        return np.maximum(-u, 0.0)
     raise ValueError(h)
 
 
@@ -117,7 +132,62 @@ def h_conj(h: str, s, tol: float = 0.0):
         return np.zeros_like(s)
     if h == "ind_box01":
         return np.maximum(s, 0.0)
+    if h == "exp":  # s log s - s on s >= 0
+        with np.errstate(divide="ignore", invalid="ignore"):
+            v = np.where(s > 0.0, s * np.log(np.where(s > 0.0, s, 1.0)) - s, 0.0)
+        return np.where(s >= -tol, v, inf)
+    if h == "neg_entr":
+        return np.exp(s - 1.0)
+    if h == "neg_log":  # -1 - log(-s) on s < 0
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(s < 0.0, -1.0 - np.log(np.where(s < 0.0, -s, 1.0)), inf)
+    if h == "recipr":  # -2 sqrt(-s) on s <= 0
+        return np.where(s <= tol, -2.0 * np.sqrt(np.maximum(-s, 0.0)), inf)
+    if h == "max_neg0":
+        ok, _ = box(-1.0, 0.0)
+        return np.where(ok, 0.0, inf)
     raise ValueError(h)
+
+
+def _bisect_increasing(phi, lo, hi, iters=300):
+    """Root of an increasing function phi on [lo, hi] with phi(lo) <= 0 <= phi(hi)."""
+    lo = np.array(lo, dtype=np.float64)
+    hi = np.array(hi, dtype=np.float64)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        pos = phi(mid) > 0.0
+        hi = np.where(pos, mid, hi)
+        lo = np.where(pos, lo, mid)
+        if np.all(hi - lo <= 4 * np.finfo(float).eps * np.maximum(1.0, np.abs(hi))):
+            break
+    return 0.5 * (lo + hi)
+
+
+def _exp_prox(z, r):
+    """Root of e^u + r (u - z) = 0: increasing in u, positive at z, negative
+    at z - e^z / r."""
+    hi = z.copy()
+    lo = z - np.exp(np.minimum(z, 700.0)) / r
+    return _bisect_increasing(lambda u: np.exp(u) + r * (u - z), lo, hi)
+
+
+def _neg_entr_prox(z, r):
+    """argmin u log u + (r/2)(u - z)^2: with u = e^t the optimality condition
+    is t + r e^t - (r z - 1) = 0, increasing in t; it is non-negative at
+    t_hi = min(r z - 1, log max(z, 1/e)) and negative at r z - 1 - r e^t_hi."""
+    c = r * z - 1.0
+    thi = np.minimum(c, np.log(np.maximum(z, math.exp(-1.0))))
+    tlo = c - r * np.exp(thi)
+    t = _bisect_increasing(lambda t: t + r * np.exp(t) - c, tlo, thi)
+    return np.exp(t)
+
+
+def _recipr_prox(z, r):
+    """Root of r (u - z) - 1/u^2 = 0 on u > 0 (increasing in u): non-negative
+    at hi = max(z, 0) + r^(-1/3), negative at 1 / sqrt(r (hi - z))."""
+    hi = np.maximum(z, 0.0) + r ** (-1.0 / 3.0)
+    lo = np.minimum(1.0 / np.sqrt(r * (hi - z)), hi)
+    return _bisect_increasing(lambda u: r * (u - z) - 1.0 / (u * u), lo, hi)
 
 
 def _logistic_prox(z, r):
@@ -143,8 +213,9 @@ def prox_h(h: str, z, r):
     """prox_{h,r}(z) = argmin_u h(u) + (r/2)(u - z)^2 (elementwise; r > 0).
 
     Closed forms are the textbook ones (soft threshold for |u|, shrinkage
-    for u^2/2, clipping for indicators); logistic has none and is solved by
-    bisection.
+    for u^2/2, clipping for indicators, the positive root of a quadratic for
+    -log u); logistic, e^u, u log u and 1/u have none and are solved by
+    bisection on a bracket of their monotone optimality condition.
     """
     z = np.asarray(z, dtype=np.float64)
     r = np.broadcast_to(np.asarray(r, dtype=np.float64), z.shape)
@@ -170,6 +241,16 @@ def prox_h(h: str, z, r):
         return np.zeros_like(z)
     if h == "ind_box01":
         return np.clip(z, 0.0, 1.0)
+    if h == "exp":
+        return _exp_prox(z, r)
+    if h == "neg_entr":
+        return _neg_entr_prox(z, r)
+    if h == "neg_log":  # r u^2 - r z u - 1 = 0, positive root
+        return 0.5 * (z + np.sqrt(z * z + 4.0 / r))
+    if h == "recipr":
+        return _recipr_prox(z, r)
+    if h == "max_neg0":
+        return np.where(z < -1.0 / r, z + 1.0 / r, np.where(z > 0.0, z, 0.0))
     raise ValueError(h)
 
 

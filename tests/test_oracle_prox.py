@@ -189,3 +189,99 @@ def test_parametric_conjugate_fenchel_equality(h):
         lhs = O.fn_eval(Fi, y[i:i + 1], tol=1e-12) + O.fn_conj(Fi, nu[i:i + 1], tol=1e-12)
         assert math.isfinite(lhs), (h, i)
         assert abs(lhs - nu[i] * y[i]) <= 1e-8 * max(1.0, abs(nu[i] * y[i])), (h, i)
+
+
+# --------------------------------------------------------------------------
+# Base functions with restricted domains or no closed-form prox
+# (e^u, u log u, -log u, 1/u, max(0, -u))
+# --------------------------------------------------------------------------
+MORE_H = ["exp", "neg_entr", "neg_log", "recipr", "max_neg0"]
+
+
+@pytest.mark.parametrize("h", MORE_H)
+def test_more_prox_matches_brute_force(h):
+    rng = np.random.default_rng(21)
+    for _ in range(25):
+        z = float(rng.normal(0.0, 2.0))
+        r = float(10.0 ** rng.uniform(-1.0, 1.0))
+        got = float(O.prox_h(h, np.array([z]), r)[0])
+
+        def phi(u):
+            return _h_scalar(h, u) + 0.5 * r * (u - z) ** 2
+
+        lo = 1e-12 if h in ("neg_entr", "neg_log", "recipr") else min(z, 0.0) - 2.0 / r - 3.0
+        hi = max(z, 1.0) + 2.0 / r + 3.0
+        ref = brute.scalar_min(phi, lo, hi, grid=20001)
+        assert abs(got - ref) <= 1e-6 * max(1.0, abs(ref)), (h, z, r, got, ref)
+        assert phi(got) <= phi(ref) + 1e-10 * max(1.0, abs(phi(ref)))
+
+
+def test_more_prox_optimality_conditions():
+    """The stationarity conditions the minimisers satisfy (domains open)."""
+    rng = np.random.default_rng(22)
+    z = rng.normal(0, 4, 300)
+    r = 10.0 ** rng.uniform(-2, 2, 300)
+    u = O.prox_h("exp", z, r)
+    assert np.max(np.abs(np.exp(u) + r * (u - z)) / np.maximum(1.0, r * np.abs(z) + np.exp(u))) < 1e-12
+    u = O.prox_h("neg_entr", z, r)
+    pos = u > 1e-300  # exp(r z - 1) below the float64 range rounds to 0
+    assert np.all(u >= 0.0) and np.all(r[~pos] * z[~pos] - 1.0 < -600.0)
+    assert np.max(np.abs(np.log(u[pos]) + 1.0 + r[pos] * (u[pos] - z[pos])) / np.maximum(1.0, r[pos] * np.abs(z[pos]))) < 1e-10
+    u = O.prox_h("neg_log", z, r)
+    assert np.all(u > 0.0)
+    np.testing.assert_allclose(-1.0 / u + r * (u - z), 0.0, atol=1e-9 * np.max(r * (np.abs(z) + 1)))
+    u = O.prox_h("recipr", z, r)
+    assert np.all(u > 0.0)
+    assert np.max(np.abs(r * (u - z) - 1.0 / u ** 2) / np.maximum(1.0, 1.0 / u ** 2)) < 1e-10
+
+
+@pytest.mark.parametrize("h", MORE_H)
+def test_more_fenchel_young_equality_at_prox(h):
+    rng = np.random.default_rng(23)
+    z = rng.normal(0, 2, 300)
+    r = 10.0 ** rng.uniform(-1, 1, 300)
+    u = O.prox_h(h, z, r)
+    s = r * (z - u)
+    lhs = O.h_eval(h, u) + O.h_conj(h, s, tol=1e-12)
+    assert np.all(np.isfinite(lhs)), h
+    np.testing.assert_allclose(lhs, s * u, rtol=1e-8, atol=1e-8)
+
+
+@pytest.mark.parametrize("h", MORE_H)
+def test_more_conjugate_by_grid_sup(h):
+    us = np.linspace(-40, 40, 400001)
+    with np.errstate(over="ignore"):
+        hv = O.h_eval(h, us)
+    for s in [-2.0, -0.7, -0.2, 0.3, 1.0, 2.5]:
+        with np.errstate(invalid="ignore", over="ignore"):
+            ref = np.max(s * us - hv)
+        got = float(O.h_conj(h, np.array([s]))[0])
+        if np.isinf(got):
+            # unbounded: the supremum grows with the grid
+            half = np.abs(us) <= 20.0
+            with np.errstate(invalid="ignore", over="ignore"):
+                assert ref > np.max(s * us[half] - hv[half]) + 1.0, (h, s, ref)
+        else:
+            assert abs(got - ref) < 2e-3 * max(1.0, abs(ref)), (h, s, got, ref)
+
+
+@pytest.mark.parametrize("h", MORE_H)
+def test_more_parametric_prox_formula(h):
+    rng = np.random.default_rng(24)
+    N = 10
+    a = rng.choice([-1, 1], N) * 10.0 ** rng.uniform(-0.5, 0.5, N)
+    b = rng.normal(0, 1, N)
+    c = 10.0 ** rng.uniform(-1, 0.5, N)
+    d = rng.normal(0, 1, N)
+    e = np.where(rng.random(N) < 0.5, 0.0, 10.0 ** rng.uniform(-1, 1, N))
+    v = rng.normal(0, 2, N)
+    rho = 10.0 ** rng.uniform(-0.5, 1, N)
+    F = _F(h, a=a, b=b, c=c, d=d, e=e)
+    got = O.prox_param(F, v, rho)
+    for i in range(N):
+        def phi(y, i=i):
+            return (c[i] * _h_scalar(h, a[i] * y - b[i]) + d[i] * y + 0.5 * e[i] * y * y
+                    + 0.5 * rho[i] * (y - v[i]) ** 2)
+        span = 6.0 + abs(v[i]) + (abs(b[i]) + 3.0) / abs(a[i]) + abs(d[i]) / rho[i] + 3 * c[i] * abs(a[i]) / rho[i]
+        ref = brute.scalar_min(phi, -span, span, grid=40001)
+        assert abs(got[i] - ref) <= 1e-6 * max(1.0, abs(ref)), (h, i, got[i], ref)
