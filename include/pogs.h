@@ -72,7 +72,12 @@ typedef enum {
   POGS_H_IND_GE0 = 7,   /* indicator of u >= 0 */
   POGS_H_IND_LE0 = 8,   /* indicator of u <= 0 */
   POGS_H_IND_EQ0 = 9,   /* indicator of u == 0 */
-  POGS_H_IND_BOX01 = 10 /* indicator of 0 <= u <= 1 */
+  POGS_H_IND_BOX01 = 10, /* indicator of 0 <= u <= 1 */
+  POGS_H_EXP = 11,       /* e^u */
+  POGS_H_NEG_ENTR = 12,  /* u log u on u >= 0 (0 at 0), +inf for u < 0 */
+  POGS_H_NEG_LOG = 13,   /* -log u on u > 0, +inf otherwise */
+  POGS_H_RECIPR = 14,    /* 1/u on u > 0, +inf otherwise */
+  POGS_H_MAX_NEG0 = 15   /* max(0, -u) */
 } pogs_h;
 
 /* A separable function of length len, in host memory.  Each of h, a..e is

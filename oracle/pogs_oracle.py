@@ -9,8 +9,8 @@ imports the GPU package.
 Problem (Section 1): minimize f(y) + g(x) subject to y = A x, with f and g
 separable and each term written in the parametric form of Section 5,
     f_i(y) = c h(a y - b) + d y + (e/2) y^2,   c >= 0, e >= 0.
-A function is passed as an object with attributes ``h`` (base-function name),
-``size``, and a method ``field(name)`` returning the float64 array of a, b, c,
+A function is passed as an object with attributes ``h`` (one base-function
+name, or a sequence of ``size`` names, one per element), ``size``, and a method ``field(name)`` returning the float64 array of a, b, c,
 d or e (``Fn`` of the workload module has that shape; any duck type does).
 
 Everything here runs in float64.  Readings of passages the paper leaves open
@@ -258,11 +258,38 @@ def prox_h(h: str, z, r):
 # Parametric separable functions (Section 5)
 # ---------------------------------------------------------------------------
 
+def _h_groups(h, n: int):
+    """Split the elements by base function: yields (name, index array).  ``h``
+    is one name for all n elements or a sequence of n names."""
+    if isinstance(h, str):
+        yield h, np.arange(n)
+        return
+    names = np.asarray(h, dtype=object)
+    if names.shape != (n,):
+        raise ValueError(f"h has shape {names.shape}, expected ({n},)")
+    for name in sorted(set(names.tolist())):
+        yield name, np.flatnonzero(names == name)
+
+
+def _h_map(fun, h, u, *args):
+    """Apply fun(name, u_part, *args_part) group by group (per-element h);
+    scalar args are passed unchanged, arrays of u's shape are split."""
+    u = np.asarray(u, dtype=np.float64)
+    if isinstance(h, str):
+        return fun(h, u, *args)
+    out = np.empty_like(u)
+    for name, idx in _h_groups(h, u.shape[0]):
+        part = [a[idx] if isinstance(a, np.ndarray) and a.shape == u.shape else a for a in args]
+        out[idx] = fun(name, u[idx], *part)
+    return out
+
+
 @dataclasses.dataclass
 class Param:
-    """Plain parameter arrays of a separable parametric function."""
+    """Plain parameter arrays of a separable parametric function (``h`` is one
+    name or a per-element sequence of names)."""
 
-    h: str
+    h: object
     a: np.ndarray
     b: np.ndarray
     c: np.ndarray
@@ -279,7 +306,8 @@ class Param:
 
 def as_param(fn) -> Param:
     """Copy a duck-typed function description into float64 arrays."""
-    return Param(fn.h, *(np.array(fn.field(k), dtype=np.float64) for k in "abcde"))
+    h = fn.h if isinstance(fn.h, str) else tuple(fn.h)
+    return Param(h, *(np.array(fn.field(k), dtype=np.float64) for k in "abcde"))
 
 
 def fn_eval(fn, y, tol: float = 0.0) -> float:
@@ -287,7 +315,7 @@ def fn_eval(fn, y, tol: float = 0.0) -> float:
     offsets.  ``tol`` is passed to h_eval (indicator domains)."""
     p = as_param(fn)
     y = np.asarray(y, dtype=np.float64)
-    hv = h_eval(p.h, p.a * y - p.b, tol)
+    hv = _h_map(h_eval, p.h, p.a * y - p.b, tol)
     with np.errstate(invalid="ignore"):
         term = np.where(p.c == 0.0, 0.0, p.c * hv)
     return float(np.sum(term + p.d * y + 0.5 * p.e * y * y))
@@ -306,7 +334,8 @@ def fn_conj(fn, nu, tol: float = 0.0) -> float:
     zero_c = p.c == 0.0
     out[zero_c] = np.where(np.abs(s[zero_c]) <= tol, 0.0, np.inf)
     k = ~zero_c
-    out[k] = p.c[k] * h_conj(p.h, s[k] / (p.a[k] * p.c[k]), tol) + p.b[k] * s[k] / p.a[k]
+    hk = p.h if isinstance(p.h, str) else tuple(np.asarray(p.h, dtype=object)[k])
+    out[k] = p.c[k] * _h_map(h_conj, hk, s[k] / (p.a[k] * p.c[k]), tol) + p.b[k] * s[k] / p.a[k]
     return float(np.sum(out))
 
 
@@ -328,7 +357,8 @@ def prox_param(fn, v, rho):
     if np.any(k):
         a, b, c = p.a[k], p.b[k], p.c[k]
         r = (p.e[k] + rho[k]) / (c * a * a)
-        out[k] = (prox_h(p.h, a * vq[k] - b, r) + b) / a
+        hk = p.h if isinstance(p.h, str) else tuple(np.asarray(p.h, dtype=object)[k])
+        out[k] = (_h_map(prox_h, hk, a * vq[k] - b, r) + b) / a
     return out
 
 

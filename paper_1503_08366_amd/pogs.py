@@ -28,7 +28,8 @@ POGS_F32, POGS_F64 = 0, 1
 POGS_ROW_MAJOR, POGS_COL_MAJOR = 0, 1
 POGS_HOST, POGS_DEVICE = 0, 1
 H_CODES = {"zero": 0, "identity": 1, "abs": 2, "square": 3, "huber": 4, "hinge": 5,
-           "logistic": 6, "ind_ge0": 7, "ind_le0": 8, "ind_eq0": 9, "ind_box01": 10}
+           "logistic": 6, "ind_ge0": 7, "ind_le0": 8, "ind_eq0": 9, "ind_box01": 10,
+           "exp": 11, "neg_entr": 12, "neg_log": 13, "recipr": 14, "max_neg0": 15}
 STATUS_NAMES = {0: "converged", 1: "maxiter", 2: "numerical", 3: "cancelled"}
 
 
@@ -156,8 +157,10 @@ class _FnHolder:
     def __init__(self, fn, length: int):
         if fn.size != length:
             raise ValueError(f"function has length {fn.size}, expected {length}")
-        hname = fn.h
-        self.h = np.full(length, H_CODES[hname], dtype=np.uint8)
+        if isinstance(fn.h, str):
+            self.h = np.full(length, H_CODES[fn.h], dtype=np.uint8)
+        else:
+            self.h = np.array([H_CODES[n] for n in fn.h], dtype=np.uint8)
         self.arrs = [np.ascontiguousarray(fn.field(k), dtype=np.float64) for k in "abcde"]
         dp = C.POINTER(C.c_double)
         self.s = pogs_fn(length, 1, self.h.ctypes.data_as(C.POINTER(C.c_uint8)),

@@ -8,8 +8,10 @@ seeded NumPy generator.  It holds none of the solver's arithmetic: it is shared
 by the GPU path's tests and benchmark and by the CPU oracle's tests as the one
 source of inputs.
 
-Problem classes follow Appendix A (Lasso A.4, logistic regression A.5, linear
-program A.6, non-negative least squares A.7, support vector machine A.9); the
+Problem classes follow Appendix A (basis pursuit A.1, entropy maximization
+A.2, Huber fitting A.3, Lasso A.4, logistic regression A.5, linear program
+A.6, non-negative least squares A.7, portfolio optimization A.8, support vector
+machine A.9) and the radiation-treatment shape of Section 6.2; the
 sizes, noise levels and lambda rules of the named workloads are the ones the
 benchmark configurations fix (documented per generator).
 """
@@ -36,6 +38,11 @@ H_NAMES = (
     "ind_le0",    # h(u) = 0 if u <= 0 else +inf
     "ind_eq0",    # h(u) = 0 if u == 0 else +inf
     "ind_box01",  # h(u) = 0 if 0 <= u <= 1 else +inf
+    "exp",        # h(u) = e^u
+    "neg_entr",   # h(u) = u log u on u >= 0
+    "neg_log",    # h(u) = -log u on u > 0
+    "recipr",     # h(u) = 1/u on u > 0
+    "max_neg0",   # h(u) = max(0, -u)
 )
 
 
@@ -43,13 +50,14 @@ H_NAMES = (
 class Fn:
     """A separable function sum_i c_i h(a_i y_i - b_i) + d_i y_i + (e_i/2) y_i^2.
 
-    ``h`` is one base-function name for every element.  Each of a..e is a
+    ``h`` is one base-function name for every element or a sequence of
+    ``size`` names, one per element.  Each of a..e is a
     scalar (broadcast) or a length-``size`` array.  ``const`` is a constant
     the parametric form cannot carry; it is added back only when objectives
     are reported.
     """
 
-    h: str
+    h: Union[str, Sequence[str]]
     size: int
     a: ArrayLike = 1.0
     b: ArrayLike = 0.0
@@ -59,8 +67,12 @@ class Fn:
     const: float = 0.0
 
     def __post_init__(self):
-        if self.h not in H_NAMES:
-            raise ValueError(f"unknown base function {self.h!r}")
+        names = [self.h] if isinstance(self.h, str) else list(self.h)
+        if not isinstance(self.h, str) and len(names) != self.size:
+            raise ValueError(f"h has {len(names)} entries, expected {self.size}")
+        for h in set(names):
+            if h not in H_NAMES:
+                raise ValueError(f"unknown base function {h!r}")
 
     def field(self, name: str) -> np.ndarray:
         """Parameter ``name`` expanded to a float64 array of length ``size``."""
@@ -215,6 +227,93 @@ def lp(m: int, n: int, seed: int, dtype=np.float32, max_iter: int = 10000,
     g = Fn("ind_box01", n, d=cost)
     return Problem("lp", np.ascontiguousarray(A), f, g, max_iter=max_iter,
                    meta={"b": b, "cost": cost, "seed": seed})
+
+
+def basis_pursuit(m: int, n: int, seed: int, dtype=np.float32, max_iter: int = 10000,
+                  rng: Optional[np.random.Generator] = None) -> Problem:
+    """Basis pursuit (Appendix A.1): minimize ||x||_1 s.t. A x = b.
+
+    A_ij ~ N(0,1); v_j = 0 with probability 1/2, else N(0, 1/n); b = A v
+    (from the rounded A).  Graph form: f = indicator(y = b), g = ||x||_1.
+    The appendix draws m > n, where A v = b has the single solution v; any
+    shape is accepted.
+    """
+    rng = rng if rng is not None else np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)).astype(dtype)
+    v = np.where(rng.random(n) < 0.5, 0.0, rng.standard_normal(n) / math.sqrt(n))
+    b = A.astype(np.float64) @ v
+    f = Fn("ind_eq0", m, a=1.0, b=b)
+    g = Fn("abs", n)
+    return Problem("basis_pursuit", np.ascontiguousarray(A), f, g, max_iter=max_iter,
+                   meta={"b": b, "v": v, "seed": seed})
+
+
+def entropy_max(m: int, n: int, seed: int, dtype=np.float32, max_iter: int = 10000,
+                rng: Optional[np.random.Generator] = None) -> Problem:
+    """Entropy maximization (Appendix A.2): maximize -sum x log x s.t.
+    1^T x = 1, F x <= b.
+
+    F_ij ~ N(0, n) (variance n); v_j ~ U[0,1]; b = F v / (1^T v), so
+    x = v / (1^T v) is feasible.  Graph form on A = [F; 1^T] ((m+1) x n):
+    f_i = indicator(y_i <= b_i) for i < m, f_m = indicator(y_m = 1),
+    g_j = x_j log x_j.  The appendix draws m < n.
+    """
+    rng = rng if rng is not None else np.random.default_rng(seed)
+    F = rng.standard_normal((m, n)) * math.sqrt(n)
+    v = rng.random(n)
+    A = np.vstack([F, np.ones((1, n))]).astype(dtype)
+    b = A[:m].astype(np.float64) @ v / v.sum()
+    h = ["ind_le0"] * m + ["ind_eq0"]
+    f = Fn(h, m + 1, a=1.0, b=np.append(b, 1.0))
+    g = Fn("neg_entr", n)
+    return Problem("entropy_max", np.ascontiguousarray(A), f, g, max_iter=max_iter,
+                   meta={"b": b, "v": v, "seed": seed})
+
+
+def huber_fit(m: int, n: int, seed: int, dtype=np.float32, max_iter: int = 10000,
+              rng: Optional[np.random.Generator] = None) -> Problem:
+    """Huber fitting (Appendix A.3): minimize sum_i huber(b_i - a_i^T x).
+
+    A_ij ~ N(0, n) (variance n); v_j ~ N(0, 1/n); eps_i ~ N(0, 1/4) with
+    probability 0.95, else U[0, 10]; b = A v + eps (from the rounded A).
+    Graph form: f_i(y) = huber(b_i - y) (h = huber with a = -1, b = -b_i),
+    g = 0.  The appendix draws m > n.
+    """
+    rng = rng if rng is not None else np.random.default_rng(seed)
+    A = (rng.standard_normal((m, n)) * math.sqrt(n)).astype(dtype)
+    v = rng.standard_normal(n) / math.sqrt(n)
+    outlier = rng.random(m) >= 0.95
+    eps = np.where(outlier, rng.uniform(0.0, 10.0, m), 0.5 * rng.standard_normal(m))
+    b = A.astype(np.float64) @ v + eps
+    f = Fn("huber", m, a=-1.0, b=-b)
+    g = Fn("zero", n)
+    return Problem("huber_fit", np.ascontiguousarray(A), f, g, max_iter=max_iter,
+                   meta={"b": b, "v": v, "seed": seed})
+
+
+def portfolio(k: int, n: int, seed: int, dtype=np.float32, gamma: float = 1.0,
+              max_iter: int = 10000, rng: Optional[np.random.Generator] = None) -> Problem:
+    """Portfolio optimization with a k-factor risk model (Appendix A.8):
+    maximize mu^T x - gamma x^T (F F^T + D) x s.t. x >= 0, 1^T x = 1.
+
+    F_ij ~ N(0,1) (n x k); D_jj ~ U[0, sqrt(k)]; mu_j ~ N(0,1).  Graph form
+    on A = [F^T; 1^T] ((k+1) x n): f_i = gamma y_i^2 (square with c = 2 gamma)
+    for i < k, f_k = indicator(y_k = 1); g_j = -mu_j x_j + gamma D_jj x_j^2 +
+    indicator(x_j >= 0) (ind_ge0 with d = -mu_j, e = 2 gamma D_jj).  The
+    appendix draws n > k.
+    """
+    rng = rng if rng is not None else np.random.default_rng(seed)
+    F = rng.standard_normal((n, k))
+    Dg = rng.uniform(0.0, math.sqrt(k), n)
+    mu = rng.standard_normal(n)
+    A = np.vstack([F.T, np.ones((1, n))]).astype(dtype)
+    h = ["square"] * k + ["ind_eq0"]
+    c = np.append(np.full(k, 2.0 * gamma), 1.0)
+    f = Fn(h, k + 1, a=1.0, b=np.append(np.zeros(k), 1.0), c=c)
+    g = Fn("ind_ge0", n, d=-mu, e=2.0 * gamma * Dg)
+    return Problem("portfolio", np.ascontiguousarray(A), f, g, max_iter=max_iter,
+                   meta={"mu": mu, "D": Dg, "F": A[:k].astype(np.float64).T, "gamma": gamma,
+                         "seed": seed})
 
 
 # ---------------------------------------------------------------------------

@@ -179,6 +179,8 @@ def test_small_lasso_f64_matches_oracle_iteration_for_iteration():
 @pytest.mark.parametrize("kind,shape", [
     ("lasso", (300, 120)), ("lasso", (120, 300)), ("nnls", (400, 90)), ("logistic", (500, 60)),
     ("svm", (400, 30)), ("lp", (150, 40)), ("dose", (800, 50)), ("lasso", (257, 257)),
+    ("basis_pursuit", (300, 120)), ("basis_pursuit", (120, 300)), ("entropy_max", (40, 300)),
+    ("huber_fit", (500, 60)), ("portfolio", (10, 400)),
 ])
 def test_solve_classes(kind, shape, dt):
     m, n = shape
@@ -190,6 +192,10 @@ def test_solve_classes(kind, shape, dt):
         "svm": lambda: W.svm(m, n, seed, dtype=dt),
         "lp": lambda: W.lp(m, n, seed, dtype=dt),
         "dose": lambda: W.dose(m, n, seed, dtype=dt),
+        "basis_pursuit": lambda: W.basis_pursuit(m, n, seed, dtype=dt),
+        "entropy_max": lambda: W.entropy_max(m, n, seed, dtype=dt),
+        "huber_fit": lambda: W.huber_fit(m, n, seed, dtype=dt),
+        "portfolio": lambda: W.portfolio(m, n, seed, dtype=dt),
     }[kind]()
     _check_solve(prob, dt)
 

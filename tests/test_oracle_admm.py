@@ -70,14 +70,17 @@ def test_half_step_tuple_is_fenchel_feasible():
     """mu_h in dg(x_h) and nu_h in df(y_h) (Section 3.3): the Fenchel equalities
     hold termwise for the returned tuple, in the original variables."""
     for p in [W.lasso(50, 20, seed=1, dtype=np.float64), W.lp(12, 6, seed=2, dtype=np.float64),
-              W.svm(40, 10, seed=3, dtype=np.float64), W.logistic(50, 15, seed=4, dtype=np.float64)]:
+              W.svm(40, 10, seed=3, dtype=np.float64), W.logistic(50, 15, seed=4, dtype=np.float64),
+              W.basis_pursuit(30, 12, seed=5, dtype=np.float64), W.entropy_max(5, 25, seed=6, dtype=np.float64),
+              W.huber_fit(60, 10, seed=7, dtype=np.float64)]:
         r = O.solve(p.A, p.f, p.g, O.Params(max_iter=200))
         if p.f.field("e").any() or p.g.field("e").any():
             continue
         for fn, v, s in [(p.f, r.y, r.nu), (p.g, r.x, r.mu)]:
             P = O.as_param(fn)
             for i in range(fn.size):
-                Fi = O.Param(P.h, *(getattr(P, k)[i:i + 1] for k in "abcde"))
+                hi = P.h if isinstance(P.h, str) else P.h[i]
+                Fi = O.Param(hi, *(getattr(P, k)[i:i + 1] for k in "abcde"))
                 lhs = O.fn_eval(Fi, v[i:i + 1], 1e-9) + O.fn_conj(Fi, s[i:i + 1], 1e-9)
                 assert math.isfinite(lhs), (p.name, i)
                 assert abs(lhs - s[i] * v[i]) < 1e-7 * max(1.0, abs(s[i] * v[i])), (p.name, i)
