@@ -453,6 +453,46 @@ class Projector:
         return x, y
 
 
+def cgls_project(A, c, d, x0, thr: float, cap: int, trace: bool = False):
+    """Projection onto {(x, y) : y = A x} by CGLS (Section 3.5, indirect
+    methods): x minimises ||x - c||^2 + ||A x - d||^2, the least-squares
+    problem [A; I] x ~ [d; c], by conjugate gradients on its normal equations
+    (I + A^T A) x = c + A^T d, started from x0.
+
+    Residuals r1 = d - A x (rows), r2 = c - x (columns), normal residual
+    s = A^T r1 + r2; direction p, q = A p; step alpha = ||s||^2 / (||q||^2 +
+    ||p||^2); then x += alpha p, r1 -= alpha q, s recomputed from the residuals,
+    beta = ||s_new||^2 / ||s||^2, p = s_new + beta p.  Stops before a step when
+    ||s|| <= thr or after `cap` steps.
+
+    Returns (x, r1, steps) and, with trace, the list of iterates.  y = d - r1
+    equals A x up to rounding.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64)
+    r1 = d - A @ x
+    s = A.T @ r1 + (c - x)
+    p = s.copy()
+    gamma = float(s @ s)
+    steps = 0
+    xs = [x.copy()] if trace else None
+    while steps < cap and math.sqrt(gamma) > thr:
+        q = A @ p
+        alpha = gamma / (float(q @ q) + float(p @ p))
+        x = x + alpha * p
+        r1 = r1 - alpha * q
+        s = A.T @ r1 + (c - x)
+        gamma_new = float(s @ s)
+        p = s + (gamma_new / gamma) * p
+        gamma = gamma_new
+        steps += 1
+        if trace:
+            xs.append(x.copy())
+    if trace:
+        return x, r1, steps, xs
+    return x, r1, steps
+
+
 def _tri_solve(T, r, lower: bool):
     """Forward or back substitution with a triangular matrix (library primitive)."""
     from scipy.linalg import solve_triangular
@@ -495,6 +535,9 @@ class Params:
     equil_iters: int = 10    # reading: fixed sweep count for Algorithm 2
     equilibrate: bool = True
     eps_cmp: float = float(np.finfo(np.float32).eps)  # machine epsilon of the iteration type
+    projection: str = "direct"  # "direct" (cached factor) or "cgls" (Section 3.5, indirect)
+    cg_max_iter: int = 10       # reading: CGLS step cap per projection
+    cg_tol: float = 0.1         # reading: CGLS stops when rho ||s|| <= cg_tol * eps_dual
 
 
 @dataclasses.dataclass
@@ -514,6 +557,7 @@ class Result:
     D: np.ndarray
     E: np.ndarray
     history: Optional[dict] = None
+    cg_steps: int = 0       # CGLS steps over all projections (projection = "cgls")
 
 
 def solve(A, f, g, params: Params = Params(), record: bool = False,
@@ -528,6 +572,9 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
       3. x_r = alpha x_h + (1 - alpha) x, likewise y_r                (Sec. 3.2)
       4. (x, y) = Pi(x_r + x~, y_r + y~)                            (Alg. 1, Sec. 3.5)
       5. x~ += x_r - x, y~ += y_r - y                               (Alg. 1 + Sec. 3.2)
+         With projection = "cgls" steps 4-5 are: x = CGLS(c = x_r + x~,
+         d = y_r + y~) from x_h, then x~ = c - x, y~ = r1 = d - A^ x and
+         y = d - r1 (the same updates with the residual CGLS carries).
       6. r_pri = ||A^ x_h - y_h||, r_dual = ||A^T nu_h + mu_h||,
          eps_pri = eps_abs + eps_rel ||y_h||, eps_dual = eps_abs + eps_rel ||mu_h||
                                                                     (Sec. 3.4)
@@ -558,7 +605,11 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
     Ah = D[:, None] * A * E[None, :]
     fh = scale_fn(f, 1.0 / D)
     gh = scale_fn(g, E)
-    proj = Projector(Ah)
+    if params.projection not in ("direct", "cgls"):
+        raise ValueError(f"unknown projection {params.projection!r}")
+    cg = params.projection == "cgls"
+    proj = None if cg else Projector(Ah)
+    cg_steps = 0
 
     x = np.zeros(n)
     y = np.zeros(m)
@@ -573,7 +624,7 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
     rho = params.rho0
     l = u = 0
     hist = {"r_pri": [], "r_dual": [], "eps_pri": [], "eps_dual": [], "rho": [],
-            "inv_dual": [], "inv_primal": []} if record else None
+            "inv_dual": [], "inv_primal": [], "cg": []} if record else None
     converged = False
     k = 0
     for k in range(params.max_iter):
@@ -583,14 +634,29 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
         nu = -rho * (yh - y + yt)
         xr = params.alpha * xh + (1.0 - params.alpha) * x
         yr = params.alpha * yh + (1.0 - params.alpha) * y
-        x_new, y_new = proj(xr + xt, yr + yt)
-        xt = xt + xr - x_new
-        yt = yt + yr - y_new
+        eps_pri = params.eps_abs + params.eps_rel * float(np.linalg.norm(yh))
+        eps_dual = params.eps_abs + params.eps_rel * float(np.linalg.norm(mu))
+        if cg:
+            # CGLS from the half step (the projection's input converges to its
+            # output, Section 3.5); accurate to a fraction of the dual tolerance:
+            # the normal residual s is exactly x~ + A^T y~ after the update below,
+            # which enters the next dual residual multiplied by rho.
+            c_in, d_in = xr + xt, yr + yt
+            x_new, r1, steps = cgls_project(Ah, c_in, d_in, xh, params.cg_tol * eps_dual / rho,
+                                            params.cg_max_iter)
+            cg_steps += steps
+            y_new = d_in - r1
+            xt = c_in - x_new
+            yt = r1
+            if record:
+                hist["cg"].append(steps)
+        else:
+            x_new, y_new = proj(xr + xt, yr + yt)
+            xt = xt + xr - x_new
+            yt = yt + yr - y_new
         x, y = x_new, y_new
         r_pri = float(np.linalg.norm(Ah @ xh - yh))
         r_dual = float(np.linalg.norm(Ah.T @ nu + mu))
-        eps_pri = params.eps_abs + params.eps_rel * float(np.linalg.norm(yh))
-        eps_dual = params.eps_abs + params.eps_rel * float(np.linalg.norm(mu))
         if record:
             hist["r_pri"].append(r_pri)
             hist["r_dual"].append(r_dual)
@@ -616,7 +682,7 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
     # indicator domains checked to 1e-9 (prox outputs meet them up to rounding)
     optval = fn_eval(f, y_out, 1e-9) + fn_eval(g, x_out, 1e-9)
     return Result(x_out, y_out, mu_out, nu_out, k + 1, converged, rho, r_pri, r_dual,
-                  eps_pri, eps_dual, optval, D, E, hist)
+                  eps_pri, eps_dual, optval, D, E, hist, cg_steps)
 
 
 # ---------------------------------------------------------------------------
