@@ -91,6 +91,17 @@ typedef struct {
   const double *a, *b, *c, *d, *e;
 } pogs_fn;
 
+/* How the projection onto {(x, y) : y = A x} is computed (Section 3.5).
+ * DIRECT: the reduced update with the inverse of I + A^T A (m >= n) or
+ * I + A A^T (m < n), formed once at pogs_init from a float64 Cholesky factor.
+ * CGLS: conjugate gradients on the least-squares form of the projection,
+ * min ||x - c||^2 + ||A x - d||^2, started from the half step x_h and stopped
+ * when its normal residual s = A^T (d - A x) + c - x has
+ * rho ||s|| <= cg_tol * eps_dual (this iteration's dual tolerance) or after
+ * cg_max_iter steps; no Gram matrix or factor is formed, so any min(m, n)
+ * fits.  Each step reads A twice. */
+typedef enum { POGS_PROJ_DIRECT = 0, POGS_PROJ_CGLS = 1 } pogs_projection;
+
 /* Solver parameters; pogs_params_default fills the values of Section 5. */
 typedef struct {
   double eps_abs;        /* absolute tolerance (Section 3.4), default 1e-4 */
@@ -108,6 +119,9 @@ typedef struct {
   int32_t chunk_iters;   /* iterations per device launch sequence between
                             host checks of the stop flag, default 20 */
   int32_t verbose;       /* 0 silent, 1 per-chunk log on stderr */
+  int32_t projection;    /* POGS_PROJ_DIRECT (default) or POGS_PROJ_CGLS */
+  int32_t cg_max_iter;   /* CGLS steps per projection at most, 1..1000, default 10 */
+  double cg_tol;         /* CGLS stops when rho ||s|| <= cg_tol * eps_dual, default 0.1 */
 } pogs_params;
 
 /* Result of a solve: the half-step tuple (x, y, mu, nu) of the last iteration,
@@ -125,6 +139,8 @@ typedef struct {
   int32_t status;    /* POGS_CONVERGED / POGS_MAXITER / POGS_NUMERICAL / POGS_CANCELLED */
   double ms_setup;   /* setup time of the context this solve used (ms) */
   double ms_solve;   /* wall time of this solve (ms) */
+  int32_t cg_steps;  /* CGLS steps over all projections (0 for DIRECT) */
+  int32_t reserved;
 } pogs_result;
 
 typedef struct pogs_ctx pogs_ctx;
@@ -137,10 +153,13 @@ int pogs_params_default(pogs_params *p);
  * memory `mem`).  Copies A to the device, converts it to row-major storage of
  * dt with a 64-element-aligned leading dimension, runs Algorithm 2
  * (params->equil_iters sweeps, p = 2, gamma = (m + n) sqrt(eps_cmp)), the
- * Frobenius normalisation of Section 4.1.2, scales A in place to D A E, forms
- * the Gram matrix (Section 3.5) and factors I + G by Cholesky in float64, and
- * keeps everything for later solves.  params may be NULL (defaults).
- * Errors: EINVAL (m, n <= 0, NULL pointers, lda too small, non-finite A),
+ * Frobenius normalisation of Section 4.1.2, scales A in place to D A E, and,
+ * for params->projection == POGS_PROJ_DIRECT, forms the Gram matrix (Section
+ * 3.5), factors I + G by Cholesky in float64 and keeps the inverse for later
+ * solves (POGS_PROJ_CGLS skips the Gram matrix and the factor).  params may
+ * be NULL (defaults).
+ * Errors: EINVAL (m, n <= 0, NULL pointers, lda too small, non-finite A,
+ * invalid params), EUNSUPPORTED (direct projection with min(m, n) > 32768),
  * ENOMEM, EDEVICE.  On error *out is set to NULL. */
 int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, pogs_dtype dt,
               pogs_order ord, int64_t lda, pogs_mem mem, const pogs_params *params,
@@ -156,8 +175,11 @@ int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, pogs_dtype dt
  * (the scaled dual the prox step returns when it leaves y unchanged) and
  * x~ = -A^T y~ (the relation every projection restores); from an optimal
  * pair this state is a fixed point and the solve stops after one iteration.
+ * The projection is params->projection: a context set up for the direct
+ * projection also runs CGLS solves; a context set up for CGLS only runs CGLS.
  * Errors: EINVAL (NULL ctx/f/g/out, wrong lengths, c < 0, e < 0, a == 0 with
- * c > 0, unknown h, non-finite parameters), EDEVICE. */
+ * c > 0, unknown h, non-finite parameters), EUNSUPPORTED (direct projection
+ * on a context set up for CGLS), EDEVICE. */
 int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, const pogs_params *params,
                const void *x0, const void *nu0, pogs_result *out);
 
@@ -165,8 +187,10 @@ int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, const pogs_par
  * uses f[r], g[r] and writes out[r].  The R right-hand sides are stacked so the
  * two passes over A are matrix-matrix products (one read of A per pass for
  * all R problems); each problem keeps its own rho, stopping test and status,
- * exactly as if solved alone up to rounding.  1 <= R <= 256.
- * Errors as pogs_solve. */
+ * exactly as if solved alone up to rounding.  1 <= R <= 256.  Direct
+ * projection only.
+ * Errors as pogs_solve; EUNSUPPORTED for m < n, params->projection ==
+ * POGS_PROJ_CGLS or a context set up for CGLS. */
 int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const pogs_fn *g,
                     const pogs_params *params, pogs_result *out);
 
@@ -183,7 +207,8 @@ int pogs_get_scaling(pogs_ctx *ctx, double *D, double *E, pogs_mem mem);
 /* Orthogonal projection of (c, d) onto the graph {(x, y) : y = A^ x} of the
  * scaled matrix A^ = D A E (Section 3.1 projection, computed by the reduced
  * update of Section 3.5 with the cached factor).  c, x have n entries, d, y
- * have m entries, all of the context's dtype in memory `mem`. */
+ * have m entries, all of the context's dtype in memory `mem`.
+ * EUNSUPPORTED on a context set up for CGLS. */
 int pogs_project(pogs_ctx *ctx, const void *c, const void *d, void *x, void *y, pogs_mem mem);
 
 /* Evaluate prox_{f,rho}(v) elementwise (Section 5 formula) on the device for a
@@ -198,8 +223,12 @@ int pogs_prox(const pogs_fn *fn, pogs_dtype dt, double rho, const void *v, void 
  * disabled it runs `reps` full iterations as captured launch sequences, then
  * `reps` back-to-back launches of each iteration kernel alone, and writes
  *   ms[0] average ms per full iteration,
- *   ms[1] prox step, ms[2] first pass over A, ms[3] solve with the cached
- *   inverse, ms[4] second pass over A (average ms per launch).
+ *   direct projection: ms[1] prox step, ms[2] first pass over A, ms[3] solve
+ *   with the cached inverse, ms[4] second pass over A;
+ *   CGLS (context set up for it, every projection running cg_max_iter
+ *   steps): ms[1] prox step, ms[2] the two passes that start a projection,
+ *   ms[3] one CG step (two passes), ms[4] = 0
+ *   (average ms per launch sequence).
  * The solver state afterwards is meaningless; the next pogs_solve resets it.
  * Errors: EINVAL (NULL, reps < 1, no previous solve), EDEVICE. */
 int pogs_profile_iteration(pogs_ctx *ctx, int32_t reps, double *ms);
@@ -207,7 +236,8 @@ int pogs_profile_iteration(pogs_ctx *ctx, int32_t reps, double *ms);
 /* ---- batched and served solves ------------------------------------------ */
 
 /* One problem for the batch engine (all pointers host memory, copied on
- * submit). */
+ * submit).  params.projection must be POGS_PROJ_DIRECT (EUNSUPPORTED
+ * otherwise): the grouped path runs on cached factors. */
 typedef struct {
   int64_t m, n;
   const void *A;

@@ -50,6 +50,7 @@ int check_problem(const pogs_problem *p) {
   if (p->ord != POGS_ROW_MAJOR && p->ord != POGS_COL_MAJOR) return POGS_EINVAL;
   if (p->lda < (p->ord == POGS_ROW_MAJOR ? p->n : p->m)) return POGS_EINVAL;
   if (check_params(p->params)) return POGS_EINVAL;
+  if (p->params.projection != POGS_PROJ_DIRECT) return POGS_EUNSUPPORTED;  // grouped path: cached factors
   return POGS_OK;
 }
 

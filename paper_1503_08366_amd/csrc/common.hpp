@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <type_traits>
 
 namespace pogs {
 
@@ -35,6 +36,11 @@ struct Blk {
   int nx, ny;  // blocks of this problem along x and y
 };
 __device__ inline Blk hw_block() { return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y}; }
+
+// Two sums carried together through a reduction.
+struct Sum2 {
+  double a, b;
+};
 
 // Sum over the 64 lanes of a wave (every lane receives the total).
 __device__ inline double wave_sum(double v) {

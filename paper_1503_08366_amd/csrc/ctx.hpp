@@ -160,7 +160,8 @@ struct pogs_ctx {
   bool own_stream = false;
   DevArena arena;
   void *A = nullptr;     // scaled matrix, T
-  void *Kinv = nullptr;  // (I + G)^{-1}, T
+  void *Kinv = nullptr;  // (I + G)^{-1}, T (direct projection only)
+  int proj = POGS_PROJ_DIRECT;  // projection the context was set up for
   double *D = nullptr, *E = nullptr;
   // iteration state (T): x y xt yt xh yh mu nu cx dy rhs, outputs xo yo muo nuo
   void *vec = nullptr;
@@ -182,19 +183,21 @@ struct pogs_ctx {
   double ms_setup = 0.0;
   hipGraphExec_t graph = nullptr;
   int graph_chunk = 0;
+  int graph_cg_cap = 0;  // CGLS step cap of the captured graph (0: direct projection)
   bool solved = false;  // functions uploaded by a previous solve
 
   size_t esz() const { return dt == POGS_F32 ? 4 : 8; }
   template <typename T> T *vecp(int idx) const {
-    // vectors 0..3: x, y, xt, yt; 4..7: xh, yh, mu, nu; 8: cx, 9: dy, 10: rhs; 11..14: outputs
-    static const int kind[15] = {0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 2, 0, 1, 0, 1};  // 0: n, 1: m, 2: q
+    // vectors 0..3: x, y, xt, yt; 4..7: xh, yh, mu, nu; 8: cx, 9: dy, 10: rhs; 11..14: outputs;
+    // 15..17: CGLS p, q, s
+    static const int kind[18] = {0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 2, 0, 1, 0, 1, 0, 1, 0};  // 0: n, 1: m, 2: q
     size_t off = 0;
     const size_t L[3] = {(size_t)round_up(n, 64), (size_t)round_up(m, 64), (size_t)round_up(q, 64)};
     for (int i = 0; i < idx; ++i) off += L[kind[i]];
     return reinterpret_cast<T *>(vec) + off;
   }
-  size_t vec_elems() const {  // the 15 vectors of vecp: 7 of length n, 7 of m, 1 of q
-    return 7 * (size_t)round_up(n, 64) + 7 * (size_t)round_up(m, 64) + (size_t)round_up(q, 64);
+  size_t vec_elems() const {  // the 18 vectors of vecp: 9 of length n, 8 of m, 1 of q
+    return 9 * (size_t)round_up(n, 64) + 8 * (size_t)round_up(m, 64) + (size_t)round_up(q, 64);
   }
   template <typename T> IterArgs<T> iter_args() const {
     IterArgs<T> p{};
@@ -231,6 +234,12 @@ struct pogs_ctx {
     p.n_pri = n_pri;
     p.n_dual = n_dual;
     p.ctrl = ctrl;
+    p.pv = vecp<T>(15);
+    p.qv = vecp<T>(16);
+    p.sv = vecp<T>(17);
+    p.s_gam = p.s_dual + n_dual;     // 2 x n_dual
+    p.s_sig = p.s_gam + 2 * n_dual;  // 2 x n_dual
+    p.s_qq = p.s_sig + 2 * n_dual;   // n_pri
     return p;
   }
   ~pogs_ctx() {

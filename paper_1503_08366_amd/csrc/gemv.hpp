@@ -33,6 +33,8 @@ template <bool SQUARE> __device__ inline double elem_op(double a) {
 //   double column(int j, double s0, double s1) -> per-column finish, j < n;
 //                                                returns a value summed per tile
 //   void tile_done(int tile, double sum)       -> thread 0 of the tile's workgroup
+// The finish kernel also accepts column() returning Sum2 (two values summed
+// per tile) with tile_done(int tile, double sum_a, double sum_b).
 template <typename TA, typename TV, int NRHS, bool SQUARE, class Epi>
 __device__ __forceinline__ void gemv_t_body(
     const Blk &b, const TA *__restrict__ A, int m, int n, int ld, const TV *__restrict__ v0,
@@ -140,7 +142,8 @@ __device__ __forceinline__ void gemv_t_finish_body(const Blk &b, int n, int spli
   red[g][0][c] = s[0];
   red[g][1][c] = s[1];
   __syncthreads();
-  double contrib = 0.0;
+  using R = decltype(epi.column(0, 0.0, 0.0));
+  R contrib{};
   if (g == 0 && cg < n) {
     double t0 = 0.0, t1 = 0.0;
 #pragma unroll
@@ -150,8 +153,14 @@ __device__ __forceinline__ void gemv_t_finish_body(const Blk &b, int n, int spli
     }
     contrib = epi.column(cg, t0, t1);
   }
-  const double tsum = block_sum(contrib, bs);
-  if (threadIdx.x == 0) epi.tile_done(b.x, tsum);
+  if constexpr (std::is_same<R, Sum2>::value) {
+    const double ta = block_sum(contrib.a, bs);
+    const double tb = block_sum(contrib.b, bs);
+    if (threadIdx.x == 0) epi.tile_done(b.x, ta, tb);
+  } else {
+    const double tsum = block_sum(contrib, bs);
+    if (threadIdx.x == 0) epi.tile_done(b.x, tsum);
+  }
 }
 
 template <int NRHS, class Epi>

@@ -52,6 +52,10 @@ inline int check_params(const pogs_params &p) {
       !(p.alpha < 2.0) || !(p.delta >= 1.0) || !(p.tau > 0.0) || !(p.tau <= 1.0) || p.equil_iters < 0 ||
       p.chunk_iters < 0 || !finite(p.eps_abs) || !finite(p.eps_rel) || !finite(p.rho0) || !finite(p.delta))
     return POGS_EINVAL;
+  if (p.projection != POGS_PROJ_DIRECT && p.projection != POGS_PROJ_CGLS) return POGS_EINVAL;
+  if (p.projection == POGS_PROJ_CGLS && (p.cg_max_iter < 1 || p.cg_max_iter > 1000 || !(p.cg_tol > 0.0) ||
+                                         !finite(p.cg_tol)))
+    return POGS_EINVAL;
   return POGS_OK;
 }
 

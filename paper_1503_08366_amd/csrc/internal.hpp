@@ -18,6 +18,20 @@ struct CtrlState {
   int pad;
 };
 
+// State of the CGLS projection (Section 3.5, indirect) of the current
+// iteration; step j's scalars are stored by step parity where a kernel reads
+// the previous step's value while its workgroup 0 stores the new one.
+struct CgState {
+  double alpha;      // step length of the last CG step (its r1 update is pending)
+  double gamma[2];   // ||s_j||^2
+  double pnorm2[2];  // ||p_j||^2
+  double thr2;       // (cg_tol * eps_dual / rho)^2 of this projection
+  int stop;          // step at which this projection's CGLS stopped, -1 while running
+  int steps_total;   // CG steps over the solve
+  int cap_hits;      // projections that stopped at the step cap
+  int pad;
+};
+
 // Device control block of one solve.  The state is double-buffered by the
 // parity of the iteration: the prox step of iteration i reads st[1 - i % 2]
 // (the state after iteration i - 1's kernels), runs iteration i - 1's stop
@@ -29,6 +43,10 @@ struct Ctrl {
   int max_iter;
   int adaptive;
   CtrlState st[2];
+  double cg_tol;  // CGLS tolerance factor (projection = CGLS)
+  int cg_cap;     // CGLS step cap per projection
+  int pad;
+  CgState cg;
 };
 
 // Separable function as device arrays (per element).
@@ -55,6 +73,11 @@ template <typename T> struct IterArgs {
   int n_pri, n_dual;     // number of residual partial slots
   Ctrl *ctrl;
   int par;               // parity of this iteration (selects st[] and the prox slots)
+  // CGLS projection only: direction p (n), q = A^ p (m), normal residual s (n);
+  // per finish-block partials of ||s||^2 and s^T p_prev (2 x n_dual each, by
+  // step parity); per row-block partials of ||q||^2 (n_pri)
+  T *pv, *qv, *sv;
+  double *s_gam, *s_sig, *s_qq;
 };
 
 // ---- launchers (setup.hip) ------------------------------------------------
@@ -114,6 +137,29 @@ template <typename T> void launch_prox_eval(const uint8_t *h, const T *a, const 
 template <typename T>
 void launch_warm_start(const IterArgs<T> &p, int splits, int rps, int ncolp, const double *D, const double *E,
                        double rho0, const T *x0, const T *nu0, hipStream_t s);
+
+// CGLS projection (cgls.hip).  One iteration: prox, the first passes, cap
+// CG steps (each skipped once the projection's tolerance is met) and a final
+// check that applies the last residual update.
+template <typename T> void launch_iteration_cg(const IterArgs<T> &p, int splits, int rps, int ncolp, int cap,
+                                               hipStream_t s);
+// Parts of it for the profiler: 0 prox, 1 first passes, 2 one CG step.
+template <typename T> void launch_iteration_cg_part(const IterArgs<T> &p, int which, int splits, int rps,
+                                                    int ncolp, hipStream_t s);
+// State kept by the CGLS iteration from the direct state (x, y, x~, y~):
+// c = x + x~, d = y + y~ (then x~ = c - x, y = d - y~ as the prox step reads them).
+template <typename T> void launch_cg_from_state(const IterArgs<T> &p, hipStream_t s);
+
+// Row-dot pass shapes (iter.hip).
+enum GemvNVariant : int {
+  GEMV_N_ROWS1, GEMV_N_ROWS2, GEMV_N_ROWS4, GEMV_N_ROWS8,  // float32, whole rows per wave (NC)
+  GEMV_N_L64R1, GEMV_N_L64R4, GEMV_N_L16R1, GEMV_N_L16R4   // LDS-staged vectors (lanes per row, rows)
+};
+struct GemvNShape {
+  int variant;
+  int grid;
+};
+GemvNShape gemv_n_shape(int m, int n, int ld, int elem_size);
 
 // Iteration geometry helpers.
 int gemv_t_tile(int elem_size);

@@ -21,6 +21,7 @@
 // The wide-case x update is c + A^T (d - y), the sign the projection's
 // optimality conditions give.
 #include "iter.hpp"
+#include "gemv_launch.hpp"
 
 namespace pogs {
 
@@ -101,18 +102,6 @@ void gemv_t_geometry(int m, int ncols, int elem_size, int *splits, int *rows_per
   *ncolp = tiles * tile;
 }
 
-template <typename T, typename TV, int NRHS, class Epi>
-static void gemv_t(const T *A, int m, int n, int ld, const TV *v0, const TV *v1, int splits, int rps,
-                   double *part, int ncolp, const Epi &epi, hipStream_t s) {
-  const int tile = gemv_t_tile(sizeof(T));
-  const int tiles = (int)cdiv(n, tile);
-  dim3 grid(tiles, splits);
-  hipLaunchKernelGGL((gemv_t_kernel<T, TV, NRHS, false, Epi>), grid, dim3(kBlock), 0, s, A, m, n, ld, v0, v1, rps,
-                     part, ncolp, epi);
-  hipLaunchKernelGGL((gemv_t_finish_kernel<NRHS, Epi>), dim3(cdiv(n, kFinishCols)), dim3(kBlock), 0, s, n, splits,
-                     (const double *)part, ncolp, epi);
-}
-
 // float32 rows of at most 2048 elements: whole rows per wave, the grid one
 // round of resident workgroups (four per CU up to 1024 columns, three above;
 // the kernel's register budget guarantees that residency on 256 CUs).
@@ -121,68 +110,43 @@ static int rows_grid(int m, int ld) {
   return (int)std::min<int64_t>(cdiv(m, kBlock / kWave), (ld > 1024 ? 3 : 4) * 256);
 }
 
-template <int NRHS, int NC, class Epi>
-static void launch_rows(const float *A, int m, int n, int ld, const float *v0, const float *v1, const Epi &epi,
-                        hipStream_t s) {
-  hipLaunchKernelGGL((gemv_n_rows_kernel<NRHS, NC, Epi>), dim3(rows_grid(m, ld)), dim3(kBlock), 0, s, A, m, n, ld,
-                     v0, v1, epi);
-}
-
-// Pick the kernel and its shape from the row length and row count.
-template <typename T, typename TV, int NRHS, class Epi>
-static void gemv_n(const T *A, int m, int n, int ld, const TV *v0, const TV *v1, const Epi &epi, hipStream_t s,
-                   int *nblocks_out = nullptr) {
-  if constexpr (sizeof(T) == 4 && sizeof(TV) == 4) {
-    if (ld <= kRowsMaxLd) {
-      const float *Af = (const float *)A, *x0 = (const float *)v0, *x1 = (const float *)v1;
-      if (ld <= 256) launch_rows<NRHS, 1>(Af, m, n, ld, x0, x1, epi, s);
-      else if (ld <= 512) launch_rows<NRHS, 2>(Af, m, n, ld, x0, x1, epi, s);
-      else if (ld <= 1024) launch_rows<NRHS, 4>(Af, m, n, ld, x0, x1, epi, s);
-      else launch_rows<NRHS, 8>(Af, m, n, ld, x0, x1, epi, s);
-      if (nblocks_out) *nblocks_out = rows_grid(m, ld);
-      return;
-    }
+// Kernel variant and grid of a row-dot pass (A v) over an m x n matrix with
+// leading dimension ld: whole rows per wave for float32 rows up to 2048
+// elements (NC 16-byte loads per lane), else LDS-staged vectors with 64 or 16
+// lanes per row and 1 or 4 rows per lane group.
+GemvNShape gemv_n_shape(int m, int n, int ld, int elem_size) {
+  GemvNShape sh{};
+  if (elem_size == 4 && ld <= kRowsMaxLd) {
+    sh.variant = ld <= 256 ? GEMV_N_ROWS1 : ld <= 512 ? GEMV_N_ROWS2 : ld <= 1024 ? GEMV_N_ROWS4 : GEMV_N_ROWS8;
+    sh.grid = rows_grid(m, ld);
+    return sh;
   }
-  constexpr int VN = Vec16<T>::N;
+  const int VN = 16 / elem_size;
   const int vpr = (int)cdiv(n, VN);
-  const bool wide_rows = vpr >= 128;
-  int nb;
-  if (wide_rows) {
+  if (vpr >= 128) {
     const int rows1 = gemv_n_rows_per_block<64, 1>();
     if (cdiv(m, rows1) > 2048) {
-      nb = (int)cdiv(m, gemv_n_rows_per_block<64, 4>());
-      hipLaunchKernelGGL((gemv_n_kernel<T, TV, NRHS, false, 64, 4, Epi>), dim3(nb), dim3(kBlock), 0, s,
-                         A, m, n, ld, v0, v1, epi);
+      sh.variant = GEMV_N_L64R4;
+      sh.grid = (int)cdiv(m, gemv_n_rows_per_block<64, 4>());
     } else {
-      nb = (int)cdiv(m, rows1);
-      hipLaunchKernelGGL((gemv_n_kernel<T, TV, NRHS, false, 64, 1, Epi>), dim3(nb), dim3(kBlock), 0, s,
-                         A, m, n, ld, v0, v1, epi);
+      sh.variant = GEMV_N_L64R1;
+      sh.grid = (int)cdiv(m, rows1);
     }
   } else {
     const int rows1 = gemv_n_rows_per_block<16, 1>();
     if (cdiv(m, rows1) > 2048) {
-      nb = (int)cdiv(m, gemv_n_rows_per_block<16, 4>());
-      hipLaunchKernelGGL((gemv_n_kernel<T, TV, NRHS, false, 16, 4, Epi>), dim3(nb), dim3(kBlock), 0, s,
-                         A, m, n, ld, v0, v1, epi);
+      sh.variant = GEMV_N_L16R4;
+      sh.grid = (int)cdiv(m, gemv_n_rows_per_block<16, 4>());
     } else {
-      nb = (int)cdiv(m, rows1);
-      hipLaunchKernelGGL((gemv_n_kernel<T, TV, NRHS, false, 16, 1, Epi>), dim3(nb), dim3(kBlock), 0, s,
-                         A, m, n, ld, v0, v1, epi);
+      sh.variant = GEMV_N_L16R1;
+      sh.grid = (int)cdiv(m, rows1);
     }
   }
-  if (nblocks_out) *nblocks_out = nb;
+  return sh;
 }
 
 int gemv_n_blocks(int m, int ncols, int elem_size, int) {
-  if (elem_size == 4 && round_up(ncols, 64) <= kRowsMaxLd) return rows_grid(m, (int)round_up(ncols, 64));
-  const int VN = 16 / elem_size;
-  const int vpr = (int)cdiv(ncols, VN);
-  if (vpr >= 128) {
-    const int rows1 = gemv_n_rows_per_block<64, 1>();
-    return cdiv(m, rows1) > 2048 ? (int)cdiv(m, gemv_n_rows_per_block<64, 4>()) : (int)cdiv(m, rows1);
-  }
-  const int rows1 = gemv_n_rows_per_block<16, 1>();
-  return cdiv(m, rows1) > 2048 ? (int)cdiv(m, gemv_n_rows_per_block<16, 4>()) : (int)cdiv(m, rows1);
+  return gemv_n_shape(m, ncols, (int)round_up(ncols, 64), elem_size).grid;
 }
 
 // which: 0 prox (with the previous stop test), 1 first pass over A, 2 solve, 3 second pass over A.

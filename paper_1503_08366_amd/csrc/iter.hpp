@@ -116,7 +116,10 @@ __device__ __forceinline__ void control_preview_body(const IterArgs<T> &p, int p
 // ---------------------------------------------------------------------------
 // 1. prox step (runs the previous iteration's stop test first)
 // ---------------------------------------------------------------------------
-template <typename T>
+// With CG (the CGLS projection) the state is read as that projection leaves
+// it: x~ = c - x, y = d - r1, y~ = r1 (r1 kept in yt), and x is set to the
+// half step x_h, where the next projection starts.
+template <typename T, bool CG = false>
 __device__ __forceinline__ void prox_body(const Blk &b, const IterArgs<T> &p) {
   __shared__ double bs[4 * (kBlock / kWave)];
   __shared__ CtrlState st;
@@ -135,8 +138,18 @@ __device__ __forceinline__ void prox_body(const Blk &b, const IterArgs<T> &p) {
   T vi = T(0), vti = T(0), fa = T(0), fb = T(0), fc = T(0), fd = T(0), fe = T(0);
   int fh = 0;
   if (i < len) {
-    vi = v[i];
-    vti = vt[i];
+    if constexpr (CG) {
+      if (xs) {
+        vi = p.x[i];
+        vti = p.cx[i] - vi;
+      } else {
+        vti = p.yt[i];
+        vi = p.dy[i] - vti;
+      }
+    } else {
+      vi = v[i];
+      vti = vt[i];
+    }
     fh = F.h[i];
     fa = F.a[i];
     fb = F.b[i];
@@ -159,19 +172,29 @@ __device__ __forceinline__ void prox_body(const Blk &b, const IterArgs<T> &p) {
   if (i < len) {
     if (resc != T(1)) {
       vti *= resc;
-      vt[i] = vti;
+      if constexpr (!CG) vt[i] = vti;
     }
     const T arg = vi - vti;
     const T h = prox_param<T>(fh, fa, fb, fc, fd, fe, arg, rho);
     const T dual = -rho * (h - arg);
     const T rel = alpha * h + (T(1) - alpha) * vi;
-    (xs ? p.xh : p.yh)[i] = h;
-    (xs ? p.mu : p.nu)[i] = dual;
-    (xs ? p.cx : p.dy)[i] = rel + vti;
+    if (xs) {
+      p.xh[i] = h;
+      p.mu[i] = dual;
+      p.cx[i] = rel + vti;
+      if constexpr (CG) p.x[i] = h;
+    } else {
+      p.yh[i] = h;
+      p.nu[i] = dual;
+      p.dy[i] = rel + vti;
+    }
     contrib = xs ? (double)dual * (double)dual : (double)h * (double)h;
   }
   const double s = block_sum(contrib, bs);
-  if (threadIdx.x == 0) (xs ? p.s_mu + (size_t)par * p.nbx : p.s_yh + (size_t)par * p.nby)[blk] = s;
+  if (threadIdx.x == 0) {
+    if (xs) p.s_mu[(size_t)par * p.nbx + blk] = s;
+    else p.s_yh[(size_t)par * p.nby + blk] = s;
+  }
 }
 
 

@@ -43,6 +43,7 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
   if (ctx->dt != POGS_F32 || ctx->m < ctx->n) return POGS_EUNSUPPORTED;
   pogs_params prm = params ? *params : ctx->params;
   if (check_params(prm)) return POGS_EINVAL;
+  if (ctx->proj != POGS_PROJ_DIRECT || prm.projection != POGS_PROJ_DIRECT) return POGS_EUNSUPPORTED;
   const double t0 = now_ms();
   const int m = (int)ctx->m, n = (int)ctx->n;
   std::vector<HostFn> hf(R), hg(R);

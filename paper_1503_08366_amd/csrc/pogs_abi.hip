@@ -52,6 +52,9 @@ int pogs_params_default(pogs_params *p) {
   p->eps_cmp = 0.0;
   p->chunk_iters = 20;
   p->verbose = 0;
+  p->projection = POGS_PROJ_DIRECT;
+  p->cg_max_iter = 10;
+  p->cg_tol = 0.1;
   return POGS_OK;
 }
 
@@ -103,7 +106,14 @@ template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, 
     if ((rc = run_equilibrate<T>((T *)c->A, m, n, c->ld, c->params.equil_iters, eps, c->D, c->E, ws, wsb, cnt, s)))
       return rc;
   }
-  // -- Gram and factorisation ---------------------------------------------
+  // -- Gram and factorisation (direct projection) -------------------------
+  if (c->proj == POGS_PROJ_CGLS) {
+    unsigned bad = 0;
+    POGS_HIP_TRY(hipMemcpyAsync(&bad, flags, sizeof(bad), hipMemcpyDeviceToHost, s));
+    POGS_HIP_TRY(hipStreamSynchronize(s));
+    POGS_HIP_TRY(hipGetLastError());
+    return bad ? POGS_EINVAL : POGS_OK;
+  }
   const int Q = c->Q;
   double *K;
   if ((rc = tmp.alloc((void **)&K, (size_t)Q * Q * 8))) return rc;
@@ -138,8 +148,9 @@ template <typename T> int alloc_iteration(pogs_ctx *c) {
   c->nby = (int)cdiv(m, kBlock);
   c->n_pri = gemv_n_blocks(m, n, sizeof(T), 0);
   c->n_dual = (int)cdiv(n, kFinishCols);
-  // prox sums (two parities), residual sums, then the unscale kernel's sums
-  const int nslots = 2 * (c->nbx + c->nby) + c->n_pri + c->n_dual + c->nbx + c->nby;
+  // prox sums (two parities), residual sums, CGLS sums (||s||^2 and s^T p by
+  // step parity, ||q||^2), then the unscale kernel's sums
+  const int nslots = 2 * (c->nbx + c->nby) + c->n_pri + c->n_dual + 4 * c->n_dual + c->n_pri + c->nbx + c->nby;
   const int ntiles = (int)cdiv(n, gemv_t_tile(sizeof(T)));
   // raw functions: fh0 | gh0 | f0 | g0, uploaded in one copy
   Carve raw;
@@ -197,11 +208,12 @@ extern "C" int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, po
   if (mem != POGS_HOST && mem != POGS_DEVICE) return POGS_EINVAL;
   if (lda < (ord == POGS_ROW_MAJOR ? n : m)) return POGS_EINVAL;
   if ((size_t)round_up(m, 64) * (size_t)round_up(n, 64) > (size_t)(1ULL << 40)) return POGS_EINVAL;
-  if (std::min(m, n) > 32768) return POGS_EUNSUPPORTED;  // factor of I + G would exceed 8 GiB
   pogs_params p;
   pogs_params_default(&p);
   if (params) p = *params;
   if (check_params(p)) return POGS_EINVAL;
+  // the factor of I + G would exceed 8 GiB
+  if (p.projection == POGS_PROJ_DIRECT && std::min(m, n) > 32768) return POGS_EUNSUPPORTED;
   const double t0 = now_ms();
   pogs_ctx *c = new (std::nothrow) pogs_ctx();
   if (!c) return POGS_ENOMEM;
@@ -209,6 +221,7 @@ extern "C" int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, po
   c->n = n;
   c->dt = dt;
   c->params = p;
+  c->proj = p.projection;
   c->ld = (int)round_up(n, 64);
   c->q = (int)std::min(m, n);
   c->Q = (int)round_up(c->q, 64);
@@ -274,17 +287,19 @@ int even_chunk(int requested) {
 
 // One chunk of iterations (chunk even: iteration parity is i % 2), then the
 // stop test of its last iteration so the state after the chunk is in st[0].
-template <typename T> void launch_chunk(pogs_ctx *c, int chunk, hipStream_t s) {
+// cg_cap > 0 selects the CGLS projection with that step cap.
+template <typename T> void launch_chunk(pogs_ctx *c, int chunk, int cg_cap, hipStream_t s) {
   IterArgs<T> p = c->iter_args<T>();
   for (int i = 0; i < chunk; ++i) {
     p.par = i & 1;
-    launch_iteration<T>(p, c->splits, c->rps, c->ncolp, s);
+    if (cg_cap > 0) launch_iteration_cg<T>(p, c->splits, c->rps, c->ncolp, cg_cap, s);
+    else launch_iteration<T>(p, c->splits, c->rps, c->ncolp, s);
   }
   launch_control_preview<T>(p, 1, s);
 }
 
-template <typename T> int ensure_graph(pogs_ctx *c, int chunk) {
-  if (c->graph && c->graph_chunk == chunk) return POGS_OK;
+template <typename T> int ensure_graph(pogs_ctx *c, int chunk, int cg_cap) {
+  if (c->graph && c->graph_chunk == chunk && c->graph_cg_cap == cg_cap) return POGS_OK;
   if (c->graph) {
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
@@ -295,12 +310,13 @@ template <typename T> int ensure_graph(pogs_ctx *c, int chunk) {
   if (!cap) POGS_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipGraph_t g;
   POGS_HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  launch_chunk<T>(c, chunk, cap);
+  launch_chunk<T>(c, chunk, cg_cap, cap);
   POGS_HIP_TRY(hipStreamEndCapture(cap, &g));
   hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return POGS_EDEVICE;
   c->graph_chunk = chunk;
+  c->graph_cg_cap = cg_cap;
   return POGS_OK;
 }
 
@@ -309,6 +325,7 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   const double t0 = now_ms();
   const int m = (int)c->m, n = (int)c->n;
   hipStream_t s = c->stream;
+  const int cg_cap = p.projection == POGS_PROJ_CGLS ? p.cg_max_iter : 0;
   int rc;
   if ((rc = upload_fns<T>(c, f, g))) return rc;
   // zero state (Algorithm 1 starts from x = y = x~ = y~ = 0), or the warm start
@@ -326,6 +343,7 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
       }
     }
     launch_warm_start<T>(c->iter_args<T>(), c->splits, c->rps, c->ncolp, c->D, c->E, p.rho0, dx0, dnu0, s);
+    if (cg_cap > 0) launch_cg_from_state<T>(c->iter_args<T>(), s);
     if (out->mem == POGS_HOST) POGS_HIP_TRY(hipStreamSynchronize(s));  // host x0, nu0 may be pageable
   }
   Ctrl h{};
@@ -340,18 +358,21 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
     h.st[b].rho = p.rho0;
     h.st[b].rescale = 1.0;
   }
+  h.cg_tol = p.cg_tol;
+  h.cg_cap = cg_cap;
+  h.cg.stop = -1;
   *c->ctrl_host = h;
   POGS_HIP_TRY(hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   const int chunk = even_chunk(p.chunk_iters);
   // Without a graph for this chunk size yet, the first chunk is launched
   // directly and the graph is captured while the GPU runs it.
-  bool eager = !(c->graph && c->graph_chunk == chunk);
+  bool eager = !(c->graph && c->graph_chunk == chunk && c->graph_cg_cap == cg_cap);
   for (;;) {
-    if (eager) launch_chunk<T>(c, chunk, s);
+    if (eager) launch_chunk<T>(c, chunk, cg_cap, s);
     else POGS_HIP_TRY(hipGraphLaunch(c->graph, s));
     POGS_HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     if (eager) {
-      if ((rc = ensure_graph<T>(c, chunk))) return rc;
+      if ((rc = ensure_graph<T>(c, chunk, cg_cap))) return rc;
       eager = false;
     }
     POGS_HIP_TRY(hipStreamSynchronize(s));
@@ -372,7 +393,7 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   }
   double *fa = c->f0, *ga = c->g0;
   launch_unscale<T>(ia, c->D, c->E, c->fh0, fa, fa + m, fa + 2 * m, fa + 3 * m, fa + 4 * m, c->gh0, ga, ga + n,
-                    ga + 2 * n, ga + 3 * n, ga + 4 * n, xo, yo, muo, nuo, c->slots + 2 * (ia.nbx + ia.nby) + ia.n_pri + ia.n_dual,
+                    ga + 2 * n, ga + 3 * n, ga + 4 * n, xo, yo, muo, nuo, ia.s_qq + ia.n_pri,
                     c->obj_dev, c->counters + (int)cdiv(n, gemv_t_tile(sizeof(T))) + 8, s);
   POGS_HIP_TRY(hipMemcpyAsync(c->obj_host, c->obj_dev, sizeof(double), hipMemcpyDeviceToHost, s));
   if (out->mem == POGS_HOST) {
@@ -392,6 +413,7 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   out->rho = r.rho;
   out->iters = r.k;
   out->status = r.done - 1;
+  out->cg_steps = c->ctrl_host->cg.steps_total;
   out->ms_setup = c->ms_setup;
   out->ms_solve = now_ms() - t0;
   c->solved = true;
@@ -412,11 +434,15 @@ template <typename T> int profile_impl(pogs_ctx *c, int reps, double *ms) {
     h.st[b].rho = 1.0;
     h.st[b].rescale = 1.0;
   }
+  const int cg_cap = c->proj == POGS_PROJ_CGLS ? c->params.cg_max_iter : 0;
+  h.cg_tol = c->params.cg_tol;
+  h.cg_cap = cg_cap;
+  h.cg.stop = -1;
   *c->ctrl_host = h;
   POGS_HIP_TRY(hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   const int chunk = even_chunk(c->params.chunk_iters);
   int rc;
-  if ((rc = ensure_graph<T>(c, chunk))) return rc;
+  if ((rc = ensure_graph<T>(c, chunk, cg_cap))) return rc;
   hipEvent_t e0, e1;
   POGS_HIP_TRY(hipEventCreate(&e0));
   POGS_HIP_TRY(hipEventCreate(&e1));
@@ -430,10 +456,15 @@ template <typename T> int profile_impl(pogs_ctx *c, int reps, double *ms) {
   POGS_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
   ms[0] = (double)t / ((double)launches * chunk);
   const IterArgs<T> p = c->iter_args<T>();
-  for (int w = 0; w < 4; ++w) {
-    launch_iteration_part<T>(p, w, c->splits, c->rps, c->ncolp, s);  // warm
+  auto part = [&](int w) {
+    if (cg_cap > 0) launch_iteration_cg_part<T>(p, w, c->splits, c->rps, c->ncolp, s);
+    else launch_iteration_part<T>(p, w, c->splits, c->rps, c->ncolp, s);
+  };
+  ms[4] = 0.0;
+  for (int w = 0; w < (cg_cap > 0 ? 3 : 4); ++w) {
+    part(w);  // warm
     POGS_HIP_TRY(hipEventRecord(e0, s));
-    for (int i = 0; i < reps; ++i) launch_iteration_part<T>(p, w, c->splits, c->rps, c->ncolp, s);
+    for (int i = 0; i < reps; ++i) part(w);
     POGS_HIP_TRY(hipEventRecord(e1, s));
     POGS_HIP_TRY(hipEventSynchronize(e1));
     POGS_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
@@ -454,6 +485,8 @@ extern "C" int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, con
   if (out->mem != POGS_HOST && out->mem != POGS_DEVICE) return POGS_EINVAL;
   pogs_params p = params ? *params : ctx->params;
   if (check_params(p)) return POGS_EINVAL;
+  // a context set up for CGLS has no factor for the direct projection
+  if (p.projection == POGS_PROJ_DIRECT && ctx->proj != POGS_PROJ_DIRECT) return POGS_EUNSUPPORTED;
   HostFn hf, hg;
   int rc;
   if ((rc = expand_fn(f, ctx->m, &hf))) return rc;
@@ -478,6 +511,7 @@ extern "C" int pogs_get_scaling(pogs_ctx *ctx, double *D, double *E, pogs_mem me
 
 namespace {
 template <typename T> int project_impl(pogs_ctx *c, const void *cv, const void *dv, void *x, void *y, pogs_mem mem) {
+  if (c->proj != POGS_PROJ_DIRECT) return POGS_EUNSUPPORTED;
   const int m = (int)c->m, n = (int)c->n;
   hipStream_t s = c->stream;
   // inputs/outputs staged in the output vectors 11..14 when on the host

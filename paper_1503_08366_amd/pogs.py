@@ -50,7 +50,8 @@ class pogs_params(C.Structure):
     _fields_ = [("eps_abs", C.c_double), ("eps_rel", C.c_double), ("max_iter", C.c_int32),
                 ("rho0", C.c_double), ("alpha", C.c_double), ("delta", C.c_double),
                 ("tau", C.c_double), ("adaptive_rho", C.c_int32), ("equil_iters", C.c_int32),
-                ("eps_cmp", C.c_double), ("chunk_iters", C.c_int32), ("verbose", C.c_int32)]
+                ("eps_cmp", C.c_double), ("chunk_iters", C.c_int32), ("verbose", C.c_int32),
+                ("projection", C.c_int32), ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double)]
 
 
 class pogs_result(C.Structure):
@@ -58,7 +59,8 @@ class pogs_result(C.Structure):
                 ("mem", C.c_int), ("optval", C.c_double), ("r_pri", C.c_double),
                 ("r_dual", C.c_double), ("eps_pri", C.c_double), ("eps_dual", C.c_double),
                 ("rho", C.c_double), ("iters", C.c_int32), ("status", C.c_int32),
-                ("ms_setup", C.c_double), ("ms_solve", C.c_double)]
+                ("ms_setup", C.c_double), ("ms_solve", C.c_double), ("cg_steps", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class pogs_problem(C.Structure):
@@ -141,12 +143,19 @@ def _check(rc: int, what: str):
 
 # --- marshalling helpers -----------------------------------------------------
 
+PROJECTIONS = {"direct": 0, "cgls": 1}
+
+
 def default_params(**overrides) -> pogs_params:
+    """pogs_params_default with fields overridden by keyword; projection may be
+    given by name ("direct", "cgls")."""
     p = pogs_params()
     _check(_lib().pogs_params_default(C.byref(p)), "pogs_params_default")
     for k, v in overrides.items():
         if not hasattr(p, k):
             raise KeyError(k)
+        if k == "projection" and isinstance(v, str):
+            v = PROJECTIONS[v]
         setattr(p, k, v)
     return p
 
@@ -208,6 +217,7 @@ class Result:
         self.iters = r.iters
         self.status = r.status
         self.ms_setup, self.ms_solve = r.ms_setup, r.ms_solve
+        self.cg_steps = r.cg_steps
 
     @property
     def converged(self) -> bool:
