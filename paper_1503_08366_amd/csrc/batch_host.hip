@@ -150,6 +150,10 @@ extern "C" int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_r
     if ((rc = eng.init())) return rc;
     std::vector<int> handle(nprob, -1), active;
     int chunk = 0;
+    const bool verbose = probs[grouped[0]].params.verbose != 0;
+    double t_add = 0.0, t_setup = 0.0, t_chunks = 0.0, t_out = 0.0;
+    int nchunks = 0;
+    double tp = now_ms();
     for (int i : grouped) {
       const pogs_problem &p = probs[i];
       GroupEngine::Input in;
@@ -165,13 +169,22 @@ extern "C" int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_r
       active.push_back(handle[i]);
       chunk = std::max(chunk, p.params.chunk_iters > 0 ? p.params.chunk_iters : 20);
     }
+    t_add = now_ms() - tp;
+    tp = now_ms();
     if ((rc = eng.setup(active))) return rc;
+    t_setup = now_ms() - tp;
     for (int h : active)
       if (eng.status(h).flags[0]) return POGS_EINVAL;  // non-finite entries in A
     std::vector<int> index_of(grouped.size());
     for (int i : grouped) index_of[handle[i]] = i;
     while (!active.empty()) {
+      tp = now_ms();
       if ((rc = eng.run_chunk(active, chunk))) return rc;
+      t_chunks += now_ms() - tp;
+      ++nchunks;
+      if (verbose)
+        fprintf(stderr, "pogs batch: chunk %d, %zu problems, %.2f ms\n", nchunks, active.size(), now_ms() - tp);
+      tp = now_ms();
       std::vector<int> done, still;
       for (int h : active) (eng.status(h).st.done || eng.status(h).flags[1] ? done : still).push_back(h);
       if (!done.empty()) {
@@ -184,8 +197,12 @@ extern "C" int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_r
         }
       }
       active.swap(still);
+      t_out += now_ms() - tp;
     }
     POGS_HIP_TRY(hipStreamSynchronize(s));
+    if (verbose)
+      fprintf(stderr, "pogs batch: %zu grouped problems: add %.1f ms, setup %.1f ms, %d chunks %.1f ms, results %.1f ms\n",
+              grouped.size(), t_add, t_setup, nchunks, t_chunks, t_out);
   }
   for (int i : large) {
     HostProblem hp;
