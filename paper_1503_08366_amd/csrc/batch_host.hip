@@ -23,6 +23,7 @@
 #include <thread>
 #include <vector>
 
+#include "ctx.hpp"
 #include "group_engine.hpp"
 #include "hostutil.hpp"
 
@@ -97,6 +98,7 @@ void fill_result(const GStatus &st, pogs_result *out, double ms_solve) {
   out->status = st.flags[1] ? POGS_NUMERICAL : (c.done ? c.done - 1 : POGS_MAXITER);
   out->ms_setup = 0.0;
   out->ms_solve = ms_solve;
+  out->cg_steps = 0;
 }
 
 // Whole-GPU path for one problem (used for problems too large for a workgroup).
@@ -154,9 +156,30 @@ extern "C" int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_r
     double t_add = 0.0, t_setup = 0.0, t_chunks = 0.0, t_out = 0.0;
     int nchunks = 0;
     double tp = now_ms();
+    // one block for every problem's persistent arrays and one for the setup
+    // workspaces (released once the setup has run)
+    std::vector<size_t> off_a(grouped.size()), off_w(grouped.size());
+    size_t tot_a = 0, tot_w = 0;
+    for (size_t k = 0; k < grouped.size(); ++k) {
+      size_t a, w;
+      GroupEngine::split_bytes((int)probs[grouped[k]].m, (int)probs[grouped[k]].n, &a, &w);
+      off_a[k] = tot_a;
+      off_w[k] = tot_w;
+      tot_a += round_up(a, 256);
+      tot_w += round_up(w, 256);
+    }
+    DevArena blocks(s);
+    char *blk_a, *blk_w;
+    if ((rc = blocks.alloc((void **)&blk_a, tot_a))) return rc;
+    if ((rc = blocks.alloc((void **)&blk_w, tot_w))) return rc;
+    POGS_HIP_TRY(hipMemsetAsync(blk_a, 0, tot_a, s));
+    size_t k = 0;
     for (int i : grouped) {
       const pogs_problem &p = probs[i];
       GroupEngine::Input in;
+      in.arena = blk_a + off_a[k];
+      in.ws = blk_w + off_w[k];
+      ++k;
       in.m = (int)p.m;
       in.n = (int)p.n;
       in.A = (const float *)p.A;
@@ -172,6 +195,7 @@ extern "C" int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_r
     t_add = now_ms() - tp;
     tp = now_ms();
     if ((rc = eng.setup(active))) return rc;
+    blocks.release(blk_w);
     t_setup = now_ms() - tp;
     for (int h : active)
       if (eng.status(h).flags[0]) return POGS_EINVAL;  // non-finite entries in A
@@ -189,10 +213,11 @@ extern "C" int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_r
       for (int h : active) (eng.status(h).st.done || eng.status(h).flags[1] ? done : still).push_back(h);
       if (!done.empty()) {
         if ((rc = eng.finish(done))) return rc;
+        std::vector<pogs_result *> outs;
+        for (int h : done) outs.push_back(&out[index_of[h]]);
+        if ((rc = eng.copy_out_many(done, outs))) return rc;
         for (int h : done) {
-          const int i = index_of[h];
-          fill_result(eng.status(h), &out[i], now_ms() - t0);
-          if ((rc = eng.copy_out(h, out[i].x, out[i].y, out[i].mu, out[i].nu, out[i].mem))) return rc;
+          fill_result(eng.status(h), &out[index_of[h]], now_ms() - t0);
           eng.remove(h);
         }
       }

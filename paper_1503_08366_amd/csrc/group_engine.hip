@@ -113,6 +113,12 @@ size_t GroupEngine::bytes_for(int m, int n) {
   return g.arena + g.ws;
 }
 
+void GroupEngine::split_bytes(int m, int n, size_t *arena, size_t *ws) {
+  const Geo g = geo(m, n);
+  *arena = g.arena;
+  *ws = g.ws;
+}
+
 GroupEngine::GroupEngine(hipStream_t s, int capacity) : s_(s), cap_(std::max(1, capacity)) {}
 
 GroupEngine::~GroupEngine() {
@@ -123,6 +129,9 @@ GroupEngine::~GroupEngine() {
   if (items_dev_) (void)hipFreeAsync(items_dev_, s_);
   (void)hipStreamSynchronize(s_);
   if (items_copied_) (void)hipEventDestroy(items_copied_);
+  if (fn_stage_event_) (void)hipEventDestroy(fn_stage_event_);
+  if (desc_copied_) (void)hipEventDestroy(desc_copied_);
+  if (probs_host_) (void)hipHostFree(probs_host_);
   if (status_host_) (void)hipHostFree(status_host_);
   if (items_host_) (void)hipHostFree(items_host_);
   if (fn_stage_) (void)hipHostFree(fn_stage_);
@@ -134,6 +143,8 @@ int GroupEngine::init() {
   probs_.assign(cap_, GProb{});
   mem_.assign(cap_, Mem{});
   used_.assign(cap_, 0);
+  dirty_.assign(cap_, 0);
+  if (hipHostMalloc((void **)&probs_host_, (size_t)cap_ * sizeof(GProb)) != hipSuccess) return POGS_ENOMEM;
   if (hipMallocAsync((void **)&probs_dev_, (size_t)cap_ * sizeof(GProb), s_) != hipSuccess) return POGS_ENOMEM;
   if (hipMallocAsync((void **)&status_dev_, (size_t)cap_ * sizeof(GStatus), s_) != hipSuccess) return POGS_ENOMEM;
   if (hipHostMalloc((void **)&status_host_, (size_t)cap_ * sizeof(GStatus)) != hipSuccess) return POGS_ENOMEM;
@@ -153,46 +164,62 @@ int GroupEngine::add(const Input &in, int *handle) {
   const int m = in.m, n = in.n;
   const Geo g = geo(m, n);
   Mem &M = mem_[h];
-  if (hipMallocAsync(&M.arena, g.arena, s_) != hipSuccess) return POGS_ENOMEM;
-  if (hipMallocAsync(&M.ws, g.ws, s_) != hipSuccess) {
-    (void)hipFreeAsync(M.arena, s_);
-    M.arena = nullptr;
-    return POGS_ENOMEM;
-  }
-  used_[h] = 1;
-  POGS_HIP_TRY(hipMemsetAsync(M.arena, 0, g.arena, s_));
-  // input matrix, compacted (row-major: lda = n; column-major: lda = m)
-  float *raw = at<float>(M.ws, g.w_raw);
-  if (!in.colmajor)
-    POGS_HIP_TRY(hipMemcpy2DAsync(raw, (size_t)n * 4, in.A, (size_t)in.lda * 4, (size_t)n * 4, m,
-                                  hipMemcpyHostToDevice, s_));
-  else
-    POGS_HIP_TRY(hipMemcpy2DAsync(raw, (size_t)m * 4, in.A, (size_t)in.lda * 4, (size_t)m * 4, n,
-                                  hipMemcpyHostToDevice, s_));
-  // functions: codes and a..e, staged in pinned memory, one copy
-  if (g.fn_bytes > fn_stage_cap_) {
-    POGS_HIP_TRY(hipStreamSynchronize(s_));
-    if (fn_stage_) (void)hipHostFree(fn_stage_);
-    fn_stage_ = nullptr;
-    fn_stage_cap_ = std::max<size_t>(g.fn_bytes, 1 << 20);
-    if (hipHostMalloc((void **)&fn_stage_, fn_stage_cap_) != hipSuccess) {
-      fn_stage_cap_ = 0;
+  if (in.arena) {  // caller-provided, already zeroed
+    M.arena = in.arena;
+    M.ws = in.ws;
+    M.owned = false;
+  } else {
+    if (hipMallocAsync(&M.arena, g.arena, s_) != hipSuccess) return POGS_ENOMEM;
+    if (hipMallocAsync(&M.ws, g.ws, s_) != hipSuccess) {
+      (void)hipFreeAsync(M.arena, s_);
+      M.arena = nullptr;
       return POGS_ENOMEM;
     }
-  } else {
-    POGS_HIP_TRY(hipStreamSynchronize(s_));  // the previous upload from the stage has completed
+    M.owned = true;
+    POGS_HIP_TRY(hipMemsetAsync(M.arena, 0, g.arena, s_));
   }
-  memcpy(fn_stage_, in.f->h.data(), (size_t)m);
-  memcpy(fn_stage_ + g.off_gh0, in.g->h.data(), (size_t)n);
+  used_[h] = 1;
+  // input matrix, compacted (row-major: lda = n; column-major: lda = m): one
+  // copy when the rows (columns) are contiguous, a strided copy otherwise
+  float *raw = at<float>(M.ws, g.w_raw);
+  const int64_t inner = in.colmajor ? m : n, outer = in.colmajor ? n : m;
+  if (in.lda == inner)
+    POGS_HIP_TRY(hipMemcpyAsync(raw, in.A, (size_t)m * n * 4, hipMemcpyHostToDevice, s_));
+  else
+    POGS_HIP_TRY(hipMemcpy2DAsync(raw, (size_t)inner * 4, in.A, (size_t)in.lda * 4, (size_t)inner * 4, outer,
+                                  hipMemcpyHostToDevice, s_));
+  // functions: codes and a..e, packed into a pinned ring and copied in one
+  // transfer; the ring is reused from the start once the last copy out of it
+  // has completed
+  const size_t need = round_up(g.fn_bytes, 256);
+  if (fn_stage_pos_ + need > fn_stage_cap_) {
+    if (fn_stage_event_) POGS_HIP_TRY(hipEventSynchronize(fn_stage_event_));
+    fn_stage_pos_ = 0;
+    if (need > fn_stage_cap_) {
+      if (fn_stage_) (void)hipHostFree(fn_stage_);
+      fn_stage_ = nullptr;
+      fn_stage_cap_ = std::max<size_t>(need, 16 << 20);
+      if (hipHostMalloc((void **)&fn_stage_, fn_stage_cap_) != hipSuccess) {
+        fn_stage_cap_ = 0;
+        return POGS_ENOMEM;
+      }
+    }
+  }
+  char *st = fn_stage_ + fn_stage_pos_;
+  fn_stage_pos_ += need;
+  memcpy(st, in.f->h.data(), (size_t)m);
+  memcpy(st + g.off_gh0, in.g->h.data(), (size_t)n);
   const HostFn *fs[2] = {in.f, in.g};
   const size_t offs[2] = {g.off_f0, g.off_g0};
   const int lens[2] = {m, n};
   for (int k = 0; k < 2; ++k) {
     const std::vector<double> *arr[5] = {&fs[k]->a, &fs[k]->b, &fs[k]->c, &fs[k]->d, &fs[k]->e};
     for (int j = 0; j < 5; ++j)
-      memcpy(fn_stage_ + offs[k] + (size_t)j * lens[k] * 8, arr[j]->data(), (size_t)lens[k] * 8);
+      memcpy(st + offs[k] + (size_t)j * lens[k] * 8, arr[j]->data(), (size_t)lens[k] * 8);
   }
-  POGS_HIP_TRY(hipMemcpyAsync(at<char>(M.arena, g.o_raw), fn_stage_, g.fn_bytes, hipMemcpyHostToDevice, s_));
+  POGS_HIP_TRY(hipMemcpyAsync(at<char>(M.arena, g.o_raw), st, g.fn_bytes, hipMemcpyHostToDevice, s_));
+  if (!fn_stage_event_) POGS_HIP_TRY(hipEventCreateWithFlags(&fn_stage_event_, hipEventDisableTiming));
+  POGS_HIP_TRY(hipEventRecord(fn_stage_event_, s_));
   // descriptor
   GProb &P = probs_[h];
   P = GProb{};
@@ -283,15 +310,41 @@ int GroupEngine::add(const Input &in, int *handle) {
   P.rho0 = pp.rho0;
   P.max_iter = pp.max_iter;
   P.adaptive = pp.adaptive_rho ? 1 : 0;
-  POGS_HIP_TRY(hipMemcpyAsync(probs_dev_ + h, &P, sizeof(GProb), hipMemcpyHostToDevice, s_));
+  dirty_[h] = 1;  // uploaded with the other new descriptors before the next launch
   *handle = h;
+  return POGS_OK;
+}
+
+// Copy the descriptors added since the last upload to the device in one
+// transfer (through a pinned mirror of the descriptor array).
+int GroupEngine::flush_descriptors() {
+  int lo = cap_, hi = -1;
+  for (int h = 0; h < cap_; ++h)
+    if (dirty_[h]) {
+      lo = std::min(lo, h);
+      hi = h;
+    }
+  if (hi < 0) return POGS_OK;
+  if (desc_copied_) POGS_HIP_TRY(hipEventSynchronize(desc_copied_));
+  for (int h = lo; h <= hi; ++h)
+    if (dirty_[h]) {
+      probs_host_[h] = probs_[h];
+      dirty_[h] = 0;
+    }
+  POGS_HIP_TRY(hipMemcpyAsync(probs_dev_ + lo, probs_host_ + lo, (size_t)(hi - lo + 1) * sizeof(GProb),
+                              hipMemcpyHostToDevice, s_));
+  if (!desc_copied_) POGS_HIP_TRY(hipEventCreateWithFlags(&desc_copied_, hipEventDisableTiming));
+  POGS_HIP_TRY(hipEventRecord(desc_copied_, s_));
   return POGS_OK;
 }
 
 void GroupEngine::remove(int h) {
   if (h < 0 || h >= cap_ || !used_[h]) return;
-  if (mem_[h].arena) (void)hipFreeAsync(mem_[h].arena, s_);
-  if (mem_[h].ws) (void)hipFreeAsync(mem_[h].ws, s_);
+  dirty_[h] = 0;
+  if (mem_[h].owned) {
+    if (mem_[h].arena) (void)hipFreeAsync(mem_[h].arena, s_);
+    if (mem_[h].ws) (void)hipFreeAsync(mem_[h].ws, s_);
+  }
   mem_[h] = Mem{};
   used_[h] = 0;
 }
@@ -335,6 +388,7 @@ int GroupEngine::upload_items(const std::vector<std::vector<GItem>> &lists, std:
 }
 
 int GroupEngine::refresh_status(const std::vector<int> &handles) {
+  if (int rc0 = flush_descriptors()) return rc0;
   std::vector<std::vector<GItem>> lists(1);
   for (int h : handles) lists[0].push_back(GItem{h, 0, 0, 1, 1});
   std::vector<const GItem *> ptr;
@@ -368,6 +422,7 @@ void push_range(std::vector<GItem> &l, int h, int nx, int ny = 1) {
 
 int GroupEngine::setup(const std::vector<int> &handles) {
   if (handles.empty()) return POGS_OK;
+  if (int rc0 = flush_descriptors()) return rc0;
   const std::vector<int> hs = by_size(probs_, handles);
   enum { L_ROWS, L_TILES, L_NORM, L_SCALE, L_FN, L_GRAM, L_TRTRI, L_POTRF, L_KINV, L_INIT, L_FIXED };
   int max_eq = 0, max_nbt = 0;
@@ -440,7 +495,7 @@ int GroupEngine::setup(const std::vector<int> &handles) {
   POGS_HIP_TRY(hipGetLastError());
   // the setup workspace goes back to the pool once the kernels above are done
   for (int h : hs) {
-    if (mem_[h].ws) (void)hipFreeAsync(mem_[h].ws, s_);
+    if (mem_[h].ws && mem_[h].owned) (void)hipFreeAsync(mem_[h].ws, s_);
     mem_[h].ws = nullptr;
   }
   return refresh_status(handles);
@@ -448,6 +503,7 @@ int GroupEngine::setup(const std::vector<int> &handles) {
 
 int GroupEngine::run_chunk(const std::vector<int> &handles, int chunk) {
   if (handles.empty()) return POGS_OK;
+  if (int rc0 = flush_descriptors()) return rc0;
   chunk += chunk & 1;  // even: the state after the chunk is in st[0]
   const std::vector<int> hs = by_size(probs_, handles);
   enum { PROX, P1T, P1W64, P1W16, FIN1, SOL64, SOL16, P2T64, P2T16, P2W, FIN2, PREV, NLIST };
@@ -497,6 +553,7 @@ int GroupEngine::run_chunk(const std::vector<int> &handles, int chunk) {
 
 int GroupEngine::finish(const std::vector<int> &handles) {
   if (handles.empty()) return POGS_OK;
+  if (int rc0 = flush_descriptors()) return rc0;
   std::vector<std::vector<GItem>> lists(1);
   for (int h : handles) {
     const GProb &P = probs_[h];
@@ -508,6 +565,49 @@ int GroupEngine::finish(const std::vector<int> &handles) {
   launch_group(G_UNSCALE, probs_dev_, ptr[0], (int)lists[0].size(), 0, s_);
   POGS_HIP_TRY(hipGetLastError());
   return refresh_status(handles);
+}
+
+int GroupEngine::copy_out_many(const std::vector<int> &handles, const std::vector<pogs_result *> &outs) {
+  // device destinations: direct copies; host destinations: every block into
+  // one pinned buffer, one synchronisation, then to the callers' buffers
+  size_t total = 0;
+  for (size_t k = 0; k < handles.size(); ++k)
+    if (outs[k]->mem != POGS_DEVICE) total += (size_t)2 * (m(handles[k]) + n(handles[k]));
+  if (total * 4 > out_stage_cap_) {
+    if (out_stage_) (void)hipHostFree(out_stage_);
+    out_stage_ = nullptr;
+    out_stage_cap_ = 0;
+    const size_t want = std::max<size_t>(total * 4, 1 << 20);
+    if (hipHostMalloc((void **)&out_stage_, want) != hipSuccess) return POGS_ENOMEM;
+    out_stage_cap_ = want;
+  }
+  size_t off = 0;
+  for (size_t k = 0; k < handles.size(); ++k) {
+    const pogs_result &r = *outs[k];
+    if (r.mem == POGS_DEVICE) {
+      int rc = copy_out(handles[k], r.x, r.y, r.mu, r.nu, POGS_DEVICE);
+      if (rc) return rc;
+      continue;
+    }
+    const GProb &P = probs_[handles[k]];
+    const size_t len = (size_t)2 * (P.it.m + P.it.n);
+    POGS_HIP_TRY(hipMemcpyAsync(out_stage_ + off, P.out, len * 4, hipMemcpyDeviceToHost, s_));
+    off += len;
+  }
+  POGS_HIP_TRY(hipStreamSynchronize(s_));
+  off = 0;
+  for (size_t k = 0; k < handles.size(); ++k) {
+    const pogs_result &r = *outs[k];
+    if (r.mem == POGS_DEVICE) continue;
+    const int mm = m(handles[k]), nn = n(handles[k]);
+    const float *o = out_stage_ + off;
+    if (r.x) memcpy(r.x, o, (size_t)nn * 4);
+    if (r.y) memcpy(r.y, o + nn, (size_t)mm * 4);
+    if (r.mu) memcpy(r.mu, o + nn + mm, (size_t)nn * 4);
+    if (r.nu) memcpy(r.nu, o + 2 * nn + mm, (size_t)mm * 4);
+    off += (size_t)2 * (mm + nn);
+  }
+  return POGS_OK;
 }
 
 int GroupEngine::copy_out(int h, void *x, void *y, void *mu, void *nu, pogs_mem mem) {

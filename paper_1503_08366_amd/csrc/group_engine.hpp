@@ -21,12 +21,17 @@ class GroupEngine {
     long long lda = 0;
     const HostFn *f = nullptr, *g = nullptr;
     pogs_params params{};
+    // optional caller-owned device memory (split_bytes sizes; arena zeroed);
+    // NULL: the engine allocates and frees its own
+    void *arena = nullptr, *ws = nullptr;
   };
 
   // Largest problems the grouped path takes: n and min(m, n) up to 4096.
   static bool fits(int m, int n);
   // Device bytes a problem holds while resident (persistent + setup workspace).
   static size_t bytes_for(int m, int n);
+  // The same split into the persistent part and the setup workspace.
+  static void split_bytes(int m, int n, size_t *arena, size_t *ws);
 
   GroupEngine(hipStream_t s, int capacity);
   ~GroupEngine();
@@ -46,6 +51,9 @@ class GroupEngine {
   // Copy x (n), y (m), mu (n), nu (m) of a finished problem to host or device
   // buffers (NULL skips); mem says where the buffers are.
   int copy_out(int handle, void *x, void *y, void *mu, void *nu, pogs_mem mem);
+  // The same for several finished problems into outs[k]'s buffers (out->mem
+  // says where), with one synchronisation for all host destinations.
+  int copy_out_many(const std::vector<int> &handles, const std::vector<pogs_result *> &outs);
   void remove(int handle);
 
   const GStatus &status(int handle) const { return status_host_[handle]; }
@@ -56,8 +64,10 @@ class GroupEngine {
   struct Mem {
     void *arena = nullptr;  // persistent
     void *ws = nullptr;     // setup workspace
+    bool owned = false;     // allocated by the engine
   };
   int upload_items(const std::vector<std::vector<GItem>> &lists, std::vector<const GItem *> *ptrs);
+  int flush_descriptors();
   int refresh_status(const std::vector<int> &handles);
 
   hipStream_t s_;
@@ -65,6 +75,9 @@ class GroupEngine {
   std::vector<GProb> probs_;        // host copies of the descriptors
   std::vector<Mem> mem_;
   std::vector<char> used_;
+  std::vector<char> dirty_;         // descriptors not yet on the device
+  GProb *probs_host_ = nullptr;     // pinned mirror of the descriptors
+  hipEvent_t desc_copied_ = nullptr;  // the last copy out of probs_host_
   GProb *probs_dev_ = nullptr;
   GStatus *status_dev_ = nullptr;
   GStatus *status_host_ = nullptr;  // pinned
@@ -73,8 +86,10 @@ class GroupEngine {
   GItem *items_host_ = nullptr;     // pinned staging of the work lists
   size_t items_host_cap_ = 0;
   hipEvent_t items_copied_ = nullptr;  // the last copy out of items_host_
-  char *fn_stage_ = nullptr;        // pinned staging of function parameters
+  char *fn_stage_ = nullptr;        // pinned ring staging the function parameters
   size_t fn_stage_cap_ = 0;
+  size_t fn_stage_pos_ = 0;
+  hipEvent_t fn_stage_event_ = nullptr;  // the last copy out of the ring
   float *out_stage_ = nullptr;      // pinned staging of returned vectors
   size_t out_stage_cap_ = 0;
 };
