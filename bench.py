@@ -16,8 +16,10 @@ the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -28,11 +30,42 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
-WORKLOADS = {
-    "lasso": ("lasso_20000x2000", "Lasso 20000x2000 float32, lambda = 0.1 ||A^T b||_inf"),
-    "nnls": ("nnls_20000x2000", "NNLS 20000x2000 float32 (same A, b as the Lasso)"),
-    "dose": ("dose_100000x1000", "dose-shaped 100000x1000 float32, 30% |N(0,1)| dense, asym. L1, x >= 0"),
+WORKLOADS = {  # name: (generator, description, projection)
+    "lasso": ("lasso_20000x2000", "Lasso 20000x2000 float32, lambda = 0.1 ||A^T b||_inf", "direct"),
+    "nnls": ("nnls_20000x2000", "NNLS 20000x2000 float32 (same A, b as the Lasso)", "direct"),
+    "dose": ("dose_100000x1000", "dose-shaped 100000x1000 float32, 30% |N(0,1)| dense, asym. L1, x >= 0", "direct"),
+    "lasso-cgls": ("lasso_20000x2000", "Lasso 20000x2000 float32, CGLS projection (no Gram, no factor)", "cgls"),
 }
+
+# HBM traffic of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs summarised in profiles/ (record lines "traffic workload=... kernel=...
+# sources=<digest> bytes=<per launch>").  A record counts only while the
+# sources that define the kernel, its epilogue and its launch shape are the
+# ones it was taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lasso_20000x2000.md")
+KERNEL_SOURCES = [os.path.join("paper_1503_08366_amd", "csrc", f)
+                  for f in ("common.hpp", "gemv.hpp", "gemv_launch.hpp", "iter.hpp", "iter.hip")]
+
+
+def kernel_sources_digest() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload: str, kernel: str):
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    digest = kernel_sources_digest()
+    for rec in re.finditer(r"traffic workload=(\S+) kernel=(\S+) sources=([0-9a-f]+) bytes=(\d+)", text):
+        if rec.group(1) == workload and rec.group(2) == kernel and rec.group(3) == digest:
+            return int(rec.group(4))
+    return None
 
 
 def _cpu_threads() -> int:
@@ -47,12 +80,12 @@ def _cpu_threads() -> int:
     return os.cpu_count() or 1
 
 
-def cpu_baseline(prob, budget_s: float = 30.0):
+def cpu_baseline(prob, budget_s: float = 30.0, projection: str = "direct"):
     """The FP64 oracle (NumPy/SciPy) on the host: whole solves of the same
     problem, repeated while under the time budget (at least one)."""
     from oracle import pogs_oracle as O
     prm = O.Params(eps_abs=prob.eps_abs, eps_rel=prob.eps_rel, max_iter=prob.max_iter,
-                   eps_cmp=float(np.finfo(np.float32).eps))
+                   eps_cmp=float(np.finfo(np.float32).eps), projection=projection)
     A64 = prob.A.astype(np.float64)
     done = 0
     t0 = time.perf_counter()
@@ -198,13 +231,15 @@ def main():
     from paper_1503_08366_amd import pogs as P
     from paper_1503_08366_amd import workloads as W
 
-    gen_name, desc = WORKLOADS[args.workload]
+    gen_name, desc, projection = WORKLOADS[args.workload]
     prob = getattr(W, gen_name)()
     m, n = prob.m, prob.n
     torch.cuda.set_device(0)
     A = torch.from_numpy(prob.A).cuda()
     stream = torch.cuda.current_stream()
-    prm = P.default_params(eps_abs=prob.eps_abs, eps_rel=prob.eps_rel, max_iter=prob.max_iter)
+    prm = P.default_params(eps_abs=prob.eps_abs, eps_rel=prob.eps_rel, max_iter=prob.max_iter,
+                           projection=projection)
+    cgls = projection == "cgls"
 
     def step():
         t = time.perf_counter()
@@ -233,15 +268,24 @@ def main():
         ctx.solve(prob.f, prob.g, prm, device_out=True)
         prof = ctx.profile_iteration(args.profile_reps)
     tall = m >= n
-    vec_bytes = {  # float32 vectors read + written per launch
-        "pass1": (2 * m + 2 * n + n) * 4 if tall else (2 * n + 2 * m + m) * 4,
-        "pass2": (2 * n + 3 * m) * 4 if tall else (2 * m + 3 * n) * 4,
-    }
-    kern = max(("pass1", "pass2"), key=lambda k: prof[k])
-    alg_bytes = 4.0 * m * n + vec_bytes[kern]
-    achieved = alg_bytes / (prof[kern] * 1e-3) / 1e9
     q = min(m, n)
-    iter_bytes = 8.0 * m * n + 4.0 * q * q + 4.0 * 24 * (m + n)
+    if cgls:
+        # one CG step: A^ s (rows) and A^T [r1, q] (columns) plus the vectors
+        kern = "cg_step"
+        alg_bytes = 8.0 * m * n + 4.0 * (5 * m + 8 * n)
+        kern_desc = "CG step (A p, A^T [r1, q]: three launches)"
+        iter_bytes = None
+    else:
+        vec_bytes = {  # float32 vectors read + written per launch
+            "pass1": (2 * m + 2 * n + n) * 4 if tall else (2 * n + 2 * m + m) * 4,
+            "pass2": (2 * n + 3 * m) * 4 if tall else (2 * m + 3 * n) * 4,
+        }
+        kern = max(("pass1", "pass2"), key=lambda k: prof[k])
+        alg_bytes = 4.0 * m * n + vec_bytes[kern]
+        kern_desc = f"{kern} ({'A^T v' if (kern == 'pass1') == tall else 'A v'})"
+        iter_bytes = 8.0 * m * n + 4.0 * q * q + 4.0 * 24 * (m + n)
+    achieved = alg_bytes / (prof[kern] * 1e-3) / 1e9
+    traffic = None if cgls else recorded_traffic(args.workload, kern)
 
     line = {
         "metric": "solves/s at rel tol 1e-3 (plain, one problem per launch sequence); ADMM iter/s; p50/p99 latency",
@@ -265,14 +309,17 @@ def main():
         "solve_ms_mean": solve_ms / len(res),
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
         "kernel_ms": prof,
-        "iteration_GBps": iter_bytes / (prof["iteration"] * 1e-3) / 1e9,
-        "roofline": {"bound": "hbm", "kernel": f"{kern} ({'A^T v' if (kern == 'pass1') == tall else 'A v'})",
+        "roofline": {"bound": "hbm", "kernel": kern_desc,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    if iter_bytes is not None:
+        line["iteration_GBps"] = iter_bytes / (prof["iteration"] * 1e-3) / 1e9
+    if cgls:
+        line["cg_steps_per_iteration"] = sum(r.cg_steps for r in res) / max(iters, 1)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(prob)
+        line["cpu_baseline"] = cpu_baseline(prob, projection=projection)
     print(json.dumps(line), flush=True)
 
 

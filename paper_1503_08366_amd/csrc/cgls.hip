@@ -146,8 +146,7 @@ __device__ bool cg_rows_enter(const IterArgs<T> &p, int j, int cap, EpiCgRows<T>
 }
 
 template <int NC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NC >= 8 ? 3 : 4))) void cg_rows_f32_kernel(
-    IterArgs<float> p, int j, int cap) {
+__global__ __launch_bounds__(kBlock) void cg_rows_f32_kernel(IterArgs<float> p, int j, int cap) {
   EpiCgRows<float> e;
   if (!cg_rows_enter<float>(p, j, cap, &e)) return;
   gemv_n_rows_body<1, NC, EpiCgRows<float>>(hw_block(), p.A, p.m, p.n, p.ld, p.sv, p.sv, e);

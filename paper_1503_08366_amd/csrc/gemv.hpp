@@ -281,79 +281,77 @@ __global__ __launch_bounds__(kBlock) void gemv_n_kernel(const TA *__restrict__ A
 }
 
 // ---------------------------------------------------------------------------
-// gemv_n, whole rows per wave (float32 A, n <= 256 NC)
+// gemv_n, whole rows per wave (float32 A, rows of at most 256 NC elements)
 // ---------------------------------------------------------------------------
 // Each wave takes rows gw, gw + W, gw + 2W, ... (W = waves in the grid, gw
-// its global index), so the rows are spread over the waves to within one.
-// A wave loads a whole row at once (NC 16-byte loads per lane: lane l holds
-// columns 4 l + 256 u), multiplies it by the vectors it keeps in registers
-// (the same columns for every row, loaded once), reduces across the wave and
-// hands the row to the epilogue.  The next row's loads are issued before the
-// current row is reduced.  No LDS staging, no barrier before the first load.
-// Register budget: four waves per SIMD up to 1024 columns, three above.
+// its global index).  A wave loads a whole row with NC 16-byte loads per lane
+// (lane l holds columns 4 l + 256 u), multiplies it by the vectors, which the
+// workgroup staged once in LDS (float32, the same columns for every row),
+// reduces across the wave and hands the row to the epilogue.  Two rows are in
+// flight per wave: the loads of row r + W are issued before row r is reduced.
 template <int NRHS, int NC, class Epi>
 __device__ __forceinline__ void gemv_n_rows_body(const Blk &b, const float *__restrict__ A, int m, int n, int ld,
                                                  const float *__restrict__ v0, const float *__restrict__ v1,
                                                  const Epi &epi) {
   typedef float f4 __attribute__((ext_vector_type(4)));
+  __shared__ float xs[NRHS][256 * NC];
   __shared__ double bs[kBlock / kWave];
   if (epi.skip()) return;
+  for (int t = threadIdx.x; t < 256 * NC; t += kBlock) {
+    xs[0][t] = t < n ? v0[t] : 0.f;
+    if constexpr (NRHS > 1) xs[1][t] = t < n ? v1[t] : 0.f;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
   const int W = b.nx * (kBlock / kWave);
   const int gw = b.x * (kBlock / kWave) + w;
-  f4 x0[NC], x1[NC];
-#pragma unroll
-  for (int u = 0; u < NC; ++u) {
-    const int c = 4 * lane + 256 * u;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      x0[u][k] = c + k < n ? v0[c + k] : 0.f;
-      x1[u][k] = (NRHS > 1 && c + k < n) ? v1[c + k] : 0.f;
-    }
-  }
   double contrib = 0.0;
-  f4 a[NC];
-  int row = gw;
-  auto load = [&](int r) {
+  auto load = [&](f4 *dst, int r) {
 #pragma unroll
     for (int u = 0; u < NC; ++u) {
       const int c = 4 * lane + 256 * u;
-      a[u] = c < ld ? *reinterpret_cast<const f4 *>(A + (size_t)r * ld + c) : f4{0.f, 0.f, 0.f, 0.f};
+      dst[u] = c < ld ? *reinterpret_cast<const f4 *>(A + (size_t)r * ld + c) : f4{0.f, 0.f, 0.f, 0.f};
     }
   };
-  if (row < m) load(row);
-  while (row < m) {
-    // keep the vectors in float32 registers: without this the compiler hoists
-    // their float64 conversions out of the row loop and doubles their size
-#pragma unroll
-    for (int u = 0; u < NC; ++u) {
-      __asm__ volatile("" : "+v"(x0[u]));
-      if constexpr (NRHS > 1) __asm__ volatile("" : "+v"(x1[u]));
-    }
+  auto compute = [&](const f4 *a, int r) {
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int u = 0; u < NC; ++u)
+    for (int u = 0; u < NC; ++u) {
+      const f4 x0 = *reinterpret_cast<const f4 *>(&xs[0][4 * lane + 256 * u]);
+      f4 x1;
+      if constexpr (NRHS > 1) x1 = *reinterpret_cast<const f4 *>(&xs[1][4 * lane + 256 * u]);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const double e = (double)a[u][k];
-        s0 = fma(e, (double)x0[u][k], s0);
-        if constexpr (NRHS > 1) s1 = fma(e, (double)x1[u][k], s1);
+        s0 = fma(e, (double)x0[k], s0);
+        if constexpr (NRHS > 1) s1 = fma(e, (double)x1[k], s1);
       }
-    const int next = row + W;
-    if (next < m) load(next);
+    }
     s0 = wave_sum(s0);
     if constexpr (NRHS > 1) s1 = wave_sum(s1);
-    if (lane == 0) contrib += epi.row(row, s0, s1);
-    row = next;
+    if (lane == 0) contrib += epi.row(r, s0, s1);
+  };
+  f4 a0[NC], a1[NC];
+  int row = gw;
+  if (row < m) load(a0, row);
+  while (row < m) {
+    const int r1 = row + W;
+    if (r1 < m) load(a1, r1);
+    compute(a0, row);
+    if (r1 >= m) break;
+    const int r2 = r1 + W;
+    if (r2 < m) load(a0, r2);
+    compute(a1, r1);
+    row = r2;
   }
   const double bsum = block_sum(contrib, bs);
   if (threadIdx.x == 0) epi.block_done(b.x, bsum);
 }
 
 template <int NRHS, int NC, class Epi>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NC >= 8 ? 3 : 4))) void gemv_n_rows_kernel(
-    const float *__restrict__ A, int m, int n, int ld, const float *__restrict__ v0, const float *__restrict__ v1,
-    Epi epi) {
+__global__ __launch_bounds__(kBlock) void gemv_n_rows_kernel(const float *__restrict__ A, int m, int n, int ld,
+                                                             const float *__restrict__ v0,
+                                                             const float *__restrict__ v1, Epi epi) {
   gemv_n_rows_body<NRHS, NC, Epi>(hw_block(), A, m, n, ld, v0, v1, epi);
 }
 

@@ -102,12 +102,19 @@ void gemv_t_geometry(int m, int ncols, int elem_size, int *splits, int *rows_per
   *ncolp = tiles * tile;
 }
 
-// float32 rows of at most 2048 elements: whole rows per wave, the grid one
-// round of resident workgroups (four per CU up to 1024 columns, three above;
-// the kernel's register budget guarantees that residency on 256 CUs).
+// float32 rows of at most 2048 elements: whole rows per wave.  The grid
+// targets two workgroups per CU for rows longer than 1024 elements and three
+// otherwise (measured best on gfx950: 28 us for 20000 x 2000 at two, 34-36 us
+// at 2.5-3), then shrinks so every wave gets the same number of rows (the
+// last wave of the grid at most one fewer): a pass ends when its busiest wave
+// does.
 constexpr int kRowsMaxLd = 2048;
 static int rows_grid(int m, int ld) {
-  return (int)std::min<int64_t>(cdiv(m, kBlock / kWave), (ld > 1024 ? 3 : 4) * 256);
+  constexpr int kWavesPerBlock = kBlock / kWave;
+  const int64_t target = (int64_t)(ld > 1024 ? 2 : 3) * 256 * kWavesPerBlock;
+  const int64_t per_wave = cdiv((int64_t)m, target);
+  const int64_t waves = cdiv((int64_t)m, per_wave);
+  return (int)cdiv(waves, (int64_t)kWavesPerBlock);
 }
 
 // Kernel variant and grid of a row-dot pass (A v) over an m x n matrix with

@@ -297,6 +297,7 @@ class Context:
                 order, lda = POGS_ROW_MAJOR, n
             ptr, mem = A.ctypes.data, POGS_HOST
         self.stream = stream
+        self.projection = int(params.projection) if params is not None else 0
         handle = C.c_void_p()
         rc = lib.pogs_init(C.byref(handle), m, n, C.c_void_p(ptr), self.dtype, order, lda, mem,
                            C.byref(params) if params is not None else None, _stream_handle(stream))
@@ -397,9 +398,13 @@ class Context:
         return out
 
     def profile_iteration(self, reps: int = 50):
-        """Average ms of a full iteration and of each iteration kernel (HIP events)."""
+        """Average ms of a full iteration and of each part of it (HIP events):
+        prox, pass1, solve, pass2 (direct projection) or prox, first (the two
+        passes that start a projection), cg_step (a context set up for CGLS)."""
         ms = (C.c_double * 5)()
         _check(_lib().pogs_profile_iteration(self._h(), reps, ms), "pogs_profile_iteration")
+        if self.projection == PROJECTIONS["cgls"]:
+            return {"iteration": ms[0], "prox": ms[1], "first": ms[2], "cg_step": ms[3]}
         return {"iteration": ms[0], "prox": ms[1], "pass1": ms[2], "solve": ms[3], "pass2": ms[4]}
 
     def scaling(self):
