@@ -277,8 +277,8 @@ def main():
         iter_bytes = None
     else:
         vec_bytes = {  # float32 vectors read + written per launch
-            "pass1": (2 * m + 2 * n + n) * 4 if tall else (2 * n + 2 * m + m) * 4,
-            "pass2": (2 * n + 3 * m) * 4 if tall else (2 * m + 3 * n) * 4,
+            "pass1": (2 * m + 3 * n) * 4 if tall else (2 * n + 3 * m) * 4,
+            "pass2": (2 * n + 4 * m) * 4 if tall else (2 * m + 4 * n) * 4,
         }
         kern = max(("pass1", "pass2"), key=lambda k: prof[k])
         alg_bytes = 4.0 * m * n + vec_bytes[kern]
