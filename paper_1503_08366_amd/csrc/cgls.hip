@@ -48,12 +48,13 @@ __global__ __launch_bounds__(kBlock) void prox_cg_kernel(IterArgs<T> p) {
 
 // C0: t = A^ x_h -> r1 = d - t (kept in yt), (t - y_h)^2 per row
 template <typename T> struct EpiCgStart : EpiBase<T> {
-  __device__ double row(int i, double t, double) const {
-    const IterArgs<T> &p = this->p;
-    p.yt[i] = (T)((double)p.dy[i] - t);
-    const double r = t - (double)p.yh[i];
+  __device__ Pre2<T> pre(int i) const { return Pre2<T>{this->p.dy[i], this->p.yh[i]}; }
+  __device__ double row(int i, double t, double, const Pre2<T> &q) const {
+    this->p.yt[i] = (T)((double)q.a - t);
+    const double r = t - (double)q.b;
     return r * r;
   }
+  __device__ double row(int i, double t, double z) const { return row(i, t, z, pre(i)); }
   __device__ void block_done(int b, double v) const { this->p.s_pri[b] = v; }
 };
 
@@ -98,17 +99,19 @@ template <typename T> struct EpiCgRows {
   double alpha_prev, beta;
   int has_prev;
   __device__ bool skip() const { return false; }
-  __device__ double row(int i, double as, double) const {
+  __device__ Pre2<T> pre(int i) const { return has_prev ? Pre2<T>{p.qv[i], p.yt[i]} : Pre2<T>{T(0), T(0)}; }
+  __device__ double row(int i, double as, double, const Pre2<T> &q) const {
     double qn = as;
     if (has_prev) {
-      const double qo = (double)p.qv[i];
-      p.yt[i] = (T)((double)p.yt[i] - alpha_prev * qo);
+      const double qo = (double)q.a;
+      p.yt[i] = (T)((double)q.b - alpha_prev * qo);
       qn = as + beta * qo;
     }
     const T qt = (T)qn;
     p.qv[i] = qt;
     return (double)qt * (double)qt;
   }
+  __device__ double row(int i, double as, double z) const { return row(i, as, z, pre(i)); }
   __device__ void block_done(int b, double v) const { p.s_qq[b] = v; }
 };
 

@@ -16,6 +16,8 @@
 // per lane) and widened to float64 before accumulation.
 #pragma once
 
+#include <utility>
+
 #include "common.hpp"
 
 namespace pogs {
@@ -283,6 +285,19 @@ __global__ __launch_bounds__(kBlock) void gemv_n_kernel(const TA *__restrict__ A
 // ---------------------------------------------------------------------------
 // gemv_n, whole rows per wave (float32 A, rows of at most 256 NC elements)
 // ---------------------------------------------------------------------------
+// An epilogue may also provide `Pre pre(int i) const` and
+// `double row(int i, double s0, double s1, const Pre &) const`: pre() runs in
+// lane 0 when the row's loads are issued, so the per-row vector loads the
+// epilogue needs are in flight together with the row instead of after its
+// reduction.
+template <class E, class = void> struct EpiPre {
+  static constexpr bool value = false;
+  struct type {};
+};
+template <class E> struct EpiPre<E, std::void_t<decltype(std::declval<const E &>().pre(0))>> {
+  static constexpr bool value = true;
+  using type = decltype(std::declval<const E &>().pre(0));
+};
 // Each wave takes rows gw, gw + W, gw + 2W, ... (W = waves in the grid, gw
 // its global index).  A wave loads a whole row with NC 16-byte loads per lane
 // (lane l holds columns 4 l + 256 u), multiplies it by the vectors, which the
@@ -306,14 +321,18 @@ __device__ __forceinline__ void gemv_n_rows_body(const Blk &b, const float *__re
   const int W = b.nx * (kBlock / kWave);
   const int gw = b.x * (kBlock / kWave) + w;
   double contrib = 0.0;
-  auto load = [&](f4 *dst, int r) {
+  using Pre = typename EpiPre<Epi>::type;
+  auto load = [&](f4 *dst, Pre &pre, int r) {
 #pragma unroll
     for (int u = 0; u < NC; ++u) {
       const int c = 4 * lane + 256 * u;
       dst[u] = c < ld ? *reinterpret_cast<const f4 *>(A + (size_t)r * ld + c) : f4{0.f, 0.f, 0.f, 0.f};
     }
+    if constexpr (EpiPre<Epi>::value) {
+      if (lane == 0) pre = epi.pre(r);
+    }
   };
-  auto compute = [&](const f4 *a, int r) {
+  auto compute = [&](const f4 *a, const Pre &pre, int r) {
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int u = 0; u < NC; ++u) {
@@ -329,19 +348,23 @@ __device__ __forceinline__ void gemv_n_rows_body(const Blk &b, const float *__re
     }
     s0 = wave_sum(s0);
     if constexpr (NRHS > 1) s1 = wave_sum(s1);
-    if (lane == 0) contrib += epi.row(r, s0, s1);
+    if (lane == 0) {
+      if constexpr (EpiPre<Epi>::value) contrib += epi.row(r, s0, s1, pre);
+      else contrib += epi.row(r, s0, s1);
+    }
   };
   f4 a0[NC], a1[NC];
+  Pre p0{}, p1{};
   int row = gw;
-  if (row < m) load(a0, row);
+  if (row < m) load(a0, p0, row);
   while (row < m) {
     const int r1 = row + W;
-    if (r1 < m) load(a1, r1);
-    compute(a0, row);
+    if (r1 < m) load(a1, p1, r1);
+    compute(a0, p0, row);
     if (r1 >= m) break;
     const int r2 = r1 + W;
-    if (r2 < m) load(a0, r2);
-    compute(a1, r1);
+    if (r2 < m) load(a0, p0, r2);
+    compute(a1, p1, r1);
     row = r2;
   }
   const double bsum = block_sum(contrib, bs);

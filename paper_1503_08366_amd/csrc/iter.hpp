@@ -217,51 +217,69 @@ template <typename T> struct EpiTallPass1 : EpiBase<T> {
   __device__ void tile_done(int tile, double v) const { this->p.s_dual[tile] = v; }
 };
 
+// Row epilogues also take their per-row inputs through pre(), which the
+// whole-row kernel issues together with the row's loads; row(i, s0, s1) is
+// the form the LDS-staged kernel and the grouped launches call.
+template <typename T> struct Pre1 {
+  T a;
+};
+template <typename T> struct Pre2 {
+  T a, b;
+};
+
 // m >= n, solve: x = K^{-1} rhs
 template <typename T> struct EpiTallSolve : EpiBase<T> {
-  __device__ double row(int j, double x, double) const {
+  __device__ Pre1<T> pre(int j) const { return Pre1<T>{this->p.cx[j]}; }
+  __device__ double row(int j, double x, double, const Pre1<T> &q) const {
     const IterArgs<T> &p = this->p;
     const T xv = (T)x;
     p.x[j] = xv;
-    p.xt[j] = p.cx[j] - xv;
+    p.xt[j] = q.a - xv;
     return 0.0;
   }
+  __device__ double row(int j, double x, double s) const { return row(j, x, s, pre(j)); }
   __device__ void block_done(int, double) const {}
 };
 
 // m >= n, pass 2: [y, t] = A [x, x_h]; then the stopping test
 template <typename T> struct EpiTallPass2 : EpiBase<T> {
-  __device__ double row(int i, double y, double t) const {
+  __device__ Pre2<T> pre(int i) const { return Pre2<T>{this->p.dy[i], this->p.yh[i]}; }
+  __device__ double row(int i, double y, double t, const Pre2<T> &q) const {
     const IterArgs<T> &p = this->p;
     const T yv = (T)y;
     p.y[i] = yv;
-    p.yt[i] = p.dy[i] - yv;
-    const double r = t - (double)p.yh[i];
+    p.yt[i] = q.a - yv;
+    const double r = t - (double)q.b;
     return r * r;
   }
+  __device__ double row(int i, double y, double t) const { return row(i, y, t, pre(i)); }
   __device__ void block_done(int b, double v) const { this->p.s_pri[b] = v; }
 };
 
 // m < n, pass 1: [u, t] = A [c, x_h]
 template <typename T> struct EpiWidePass1 : EpiBase<T> {
-  __device__ double row(int i, double u, double t) const {
+  __device__ Pre2<T> pre(int i) const { return Pre2<T>{this->p.dy[i], this->p.yh[i]}; }
+  __device__ double row(int i, double u, double t, const Pre2<T> &q) const {
     const IterArgs<T> &p = this->p;
-    p.rhs[i] = (T)(u - (double)p.dy[i]);
-    const double r = t - (double)p.yh[i];
+    p.rhs[i] = (T)(u - (double)q.a);
+    const double r = t - (double)q.b;
     return r * r;
   }
+  __device__ double row(int i, double u, double t) const { return row(i, u, t, pre(i)); }
   __device__ void block_done(int b, double v) const { this->p.s_pri[b] = v; }
 };
 
 // m < n, solve: y = d + K^{-1} rhs, y~ = d - y
 template <typename T> struct EpiWideSolve : EpiBase<T> {
-  __device__ double row(int i, double z, double) const {
+  __device__ Pre1<T> pre(int i) const { return Pre1<T>{this->p.dy[i]}; }
+  __device__ double row(int i, double z, double, const Pre1<T> &q) const {
     const IterArgs<T> &p = this->p;
-    const T yv = (T)((double)p.dy[i] + z);
+    const T yv = (T)((double)q.a + z);
     p.y[i] = yv;
-    p.yt[i] = p.dy[i] - yv;
+    p.yt[i] = q.a - yv;
     return 0.0;
   }
+  __device__ double row(int i, double z, double s) const { return row(i, z, s, pre(i)); }
   __device__ void block_done(int, double) const {}
 };
 
