@@ -321,22 +321,55 @@ def fn_eval(fn, y, tol: float = 0.0) -> float:
     return float(np.sum(term + p.d * y + 0.5 * p.e * y * y))
 
 
-def fn_conj(fn, nu, tol: float = 0.0) -> float:
-    """Conjugate f*(nu) of a parametric function with e = 0:
-    f*(nu) = c h*((nu - d)/(a c)) + b (nu - d)/a  (for c > 0, a != 0),
-    and the indicator of {nu = d} when c = 0.  ``tol`` is passed to h_conj."""
+def fn_conj_terms(fn, nu, tol: float = 0.0) -> np.ndarray:
+    """Elementwise conjugate of a parametric function (Section 2.1 conjugates of
+    the Section 5 form), f*(nu) = sup_y nu y - f(y):
+
+      e = 0, c > 0:  c h*((nu - d)/(a c)) + b (nu - d)/a
+      e = 0, c = 0:  indicator of {nu = d}
+      e > 0, c = 0:  (nu - d)^2 / (2 e)
+      e > 0, c > 0:  (nu - d) y* - (e/2) y*^2 - c h(a y* - b), where the
+                     supremum is attained at y* = argmin_y c h(a y - b) +
+                     (e/2)(y - (nu - d)/e)^2, the prox of the h term with
+                     penalty e at (nu - d)/e.
+
+    ``tol`` is passed to h_conj / h_eval (indicator domains)."""
     p = as_param(fn)
-    if np.any(p.e != 0.0):
-        raise ValueError("conjugate implemented for e = 0 only")
     nu = np.asarray(nu, dtype=np.float64)
     s = nu - p.d
     out = np.empty_like(nu)
-    zero_c = p.c == 0.0
-    out[zero_c] = np.where(np.abs(s[zero_c]) <= tol, 0.0, np.inf)
-    k = ~zero_c
-    hk = p.h if isinstance(p.h, str) else tuple(np.asarray(p.h, dtype=object)[k])
-    out[k] = p.c[k] * _h_map(h_conj, hk, s[k] / (p.a[k] * p.c[k]), tol) + p.b[k] * s[k] / p.a[k]
-    return float(np.sum(out))
+    e0, c0 = p.e == 0.0, p.c == 0.0
+    k = e0 & c0
+    out[k] = np.where(np.abs(s[k]) <= tol, 0.0, np.inf)
+    k = e0 & ~c0
+    if np.any(k):
+        hk = p.h if isinstance(p.h, str) else tuple(np.asarray(p.h, dtype=object)[k])
+        out[k] = p.c[k] * _h_map(h_conj, hk, s[k] / (p.a[k] * p.c[k]), tol) + p.b[k] * s[k] / p.a[k]
+    k = ~e0 & c0
+    out[k] = s[k] * s[k] / (2.0 * p.e[k])
+    k = ~e0 & ~c0
+    if np.any(k):
+        hk = p.h if isinstance(p.h, str) else tuple(np.asarray(p.h, dtype=object)[k])
+        a, b, c, e = p.a[k], p.b[k], p.c[k], p.e[k]
+        phi = Param(hk, a, b, c, np.zeros_like(a), np.zeros_like(a))
+        ys = prox_param(phi, s[k] / e, e)
+        out[k] = s[k] * ys - 0.5 * e * ys * ys - c * _h_map(h_eval, hk, a * ys - b, tol)
+    return out
+
+
+def fn_conj(fn, nu, tol: float = 0.0) -> float:
+    """Sum of fn_conj_terms."""
+    return float(np.sum(fn_conj_terms(fn, nu, tol)))
+
+
+def fn_eval_strict(fn, y) -> float:
+    """f(y) with every indicator taken exactly (+inf outside its domain)."""
+    p = as_param(fn)
+    y = np.asarray(y, dtype=np.float64)
+    hv = _h_map(h_eval, p.h, p.a * y - p.b, 0.0)
+    with np.errstate(invalid="ignore"):
+        term = np.where(p.c == 0.0, 0.0, p.c * hv)
+    return float(np.sum(term + p.d * y + 0.5 * p.e * y * y))
 
 
 def prox_param(fn, v, rho):
@@ -538,6 +571,7 @@ class Params:
     projection: str = "direct"  # "direct" (cached factor) or "cgls" (Section 3.5, indirect)
     cg_max_iter: int = 10       # reading: CGLS step cap per projection
     cg_tol: float = 0.1         # reading: CGLS stops when rho ||s|| <= cg_tol * eps_dual
+    stop: str = "residual"      # "residual" or "gap" (Section 3.4)
 
 
 @dataclasses.dataclass
@@ -558,6 +592,8 @@ class Result:
     E: np.ndarray
     history: Optional[dict] = None
     cg_steps: int = 0       # CGLS steps over all projections (projection = "cgls")
+    gap: float = float("nan")      # eta of the returned tuple (stop = "gap")
+    eps_gap: float = float("nan")
 
 
 def solve(A, f, g, params: Params = Params(), record: bool = False,
@@ -579,6 +615,10 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
          eps_pri = eps_abs + eps_rel ||y_h||, eps_dual = eps_abs + eps_rel ||mu_h||
                                                                     (Sec. 3.4)
       7. stop when r_pri < eps_pri and r_dual < eps_dual               (Alg. 3)
+         or, with stop = "gap", when the gap of the feasible tuple
+         (x, y, -rho x~, -rho y~) after step 5, f(y) + g(x) + f*(-rho y~) +
+         g*(-rho x~), is below eps_abs + eps_rel |f(y) + g(x)|; that tuple is
+         then the one returned                                       (Sec. 3.4)
       8. Algorithm 3 may change rho; (x~, y~) are then rescaled by
          rho_old / rho_new (Sec. 3.2, varying penalty).
     Readings: residuals and tolerances are taken in the scaled variables the
@@ -607,6 +647,11 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
     gh = scale_fn(g, E)
     if params.projection not in ("direct", "cgls"):
         raise ValueError(f"unknown projection {params.projection!r}")
+    if params.stop not in ("residual", "gap"):
+        raise ValueError(f"unknown stopping rule {params.stop!r}")
+    gap_stop = params.stop == "gap"
+    gap = eps_gap = float("nan")
+    by_gap = False
     cg = params.projection == "cgls"
     proj = None if cg else Projector(Ah)
     cg_steps = 0
@@ -624,7 +669,7 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
     rho = params.rho0
     l = u = 0
     hist = {"r_pri": [], "r_dual": [], "eps_pri": [], "eps_dual": [], "rho": [],
-            "inv_dual": [], "inv_primal": [], "cg": []} if record else None
+            "inv_dual": [], "inv_primal": [], "cg": [], "gap": []} if record else None
     converged = False
     k = 0
     for k in range(params.max_iter):
@@ -665,7 +710,19 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
             hist["rho"].append(rho)
             hist["inv_dual"].append(float(np.linalg.norm(xt + Ah.T @ yt)))
             hist["inv_primal"].append(float(np.linalg.norm(y - Ah @ x)))
-        if r_pri < eps_pri and r_dual < eps_dual:
+        if gap_stop:
+            # gap of the primal and dual feasible tuple (x, y, -rho x~, -rho y~)
+            # the projection just produced (Section 3.4, gap based stopping)
+            obj = fn_eval_strict(fh, y) + fn_eval_strict(gh, x)
+            with np.errstate(invalid="ignore"):
+                gap = obj + fn_conj(fh, -rho * yt) + fn_conj(gh, -rho * xt)
+            eps_gap = params.eps_abs + params.eps_rel * abs(obj)
+            if record:
+                hist["gap"].append(gap)
+            if gap < eps_gap:
+                converged = by_gap = True
+                break
+        elif r_pri < eps_pri and r_dual < eps_dual:
             converged = True
             break
         if params.adaptive_rho:
@@ -675,6 +732,8 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
                 xt = xt * (rho / rho_new)
                 yt = yt * (rho / rho_new)
                 rho = rho_new
+    if by_gap:
+        xh, yh, mu, nu = x, y, -rho * xt, -rho * yt
     x_out = E * xh
     y_out = yh / D
     mu_out = mu / E
@@ -682,7 +741,7 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
     # indicator domains checked to 1e-9 (prox outputs meet them up to rounding)
     optval = fn_eval(f, y_out, 1e-9) + fn_eval(g, x_out, 1e-9)
     return Result(x_out, y_out, mu_out, nu_out, k + 1, converged, rho, r_pri, r_dual,
-                  eps_pri, eps_dual, optval, D, E, hist, cg_steps)
+                  eps_pri, eps_dual, optval, D, E, hist, cg_steps, gap, eps_gap)
 
 
 # ---------------------------------------------------------------------------
