@@ -102,6 +102,19 @@ typedef struct {
  * fits.  Each step reads A twice. */
 typedef enum { POGS_PROJ_DIRECT = 0, POGS_PROJ_CGLS = 1 } pogs_projection;
 
+/* Stopping rule (Section 3.4).  RESIDUAL: stop when ||A x_h - y_h|| < eps_pri
+ * and ||A^T nu_h + mu_h|| < eps_dual; the half-step tuple is returned.  GAP:
+ * stop when the gap eta = f(y) + g(x) + f*(nu) + g*(mu) of the primal and dual
+ * feasible tuple the projection leaves, (x, y, mu, nu) = (x, A x, -rho x~,
+ * -rho y~), is below eps_abs + eps_rel |f(y) + g(x)|; that tuple is returned
+ * and bounds its own suboptimality by eta.  eta is +inf whenever the tuple
+ * violates a constraint of f or g or lies outside the domain of a conjugate
+ * (indicators, hinge, logistic, ...), so the rule suits functions with full
+ * domains (or e > 0); it is checked from the second iteration on, in the
+ * scaled variables (the gap is invariant under the scaling).  GAP needs the
+ * direct projection. */
+typedef enum { POGS_STOP_RESIDUAL = 0, POGS_STOP_GAP = 1 } pogs_stop_rule;
+
 /* Solver parameters; pogs_params_default fills the values of Section 5. */
 typedef struct {
   double eps_abs;        /* absolute tolerance (Section 3.4), default 1e-4 */
@@ -122,6 +135,7 @@ typedef struct {
   int32_t projection;    /* POGS_PROJ_DIRECT (default) or POGS_PROJ_CGLS */
   int32_t cg_max_iter;   /* CGLS steps per projection at most, 1..1000, default 10 */
   double cg_tol;         /* CGLS stops when rho ||s|| <= cg_tol * eps_dual, default 0.1 */
+  int32_t stop_rule;     /* POGS_STOP_RESIDUAL (default) or POGS_STOP_GAP */
 } pogs_params;
 
 /* Result of a solve: the half-step tuple (x, y, mu, nu) of the last iteration,
@@ -141,6 +155,8 @@ typedef struct {
   double ms_solve;   /* wall time of this solve (ms) */
   int32_t cg_steps;  /* CGLS steps over all projections (0 for DIRECT) */
   int32_t reserved;
+  double gap;        /* stop_rule GAP: eta of the last tuple tested (NaN otherwise) */
+  double eps_gap;    /* its tolerance eps_abs + eps_rel |f + g| (NaN otherwise) */
 } pogs_result;
 
 typedef struct pogs_ctx pogs_ctx;
@@ -177,9 +193,10 @@ int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, pogs_dtype dt
  * pair this state is a fixed point and the solve stops after one iteration.
  * The projection is params->projection: a context set up for the direct
  * projection also runs CGLS solves; a context set up for CGLS only runs CGLS.
+ * params->stop_rule selects the residual or the gap test (see pogs_stop_rule).
  * Errors: EINVAL (NULL ctx/f/g/out, wrong lengths, c < 0, e < 0, a == 0 with
  * c > 0, unknown h, non-finite parameters), EUNSUPPORTED (direct projection
- * on a context set up for CGLS), EDEVICE. */
+ * on a context set up for CGLS, the gap rule with CGLS), EDEVICE. */
 int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, const pogs_params *params,
                const void *x0, const void *nu0, pogs_result *out);
 
@@ -188,9 +205,10 @@ int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, const pogs_par
  * two passes over A are matrix-matrix products (one read of A per pass for
  * all R problems); each problem keeps its own rho, stopping test and status,
  * exactly as if solved alone up to rounding.  1 <= R <= 256.  Direct
- * projection only.
+ * projection and the residual test only.
  * Errors as pogs_solve; EUNSUPPORTED for m < n, params->projection ==
- * POGS_PROJ_CGLS or a context set up for CGLS. */
+ * POGS_PROJ_CGLS, params->stop_rule == POGS_STOP_GAP or a context set up for
+ * CGLS. */
 int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const pogs_fn *g,
                     const pogs_params *params, pogs_result *out);
 
@@ -236,8 +254,9 @@ int pogs_profile_iteration(pogs_ctx *ctx, int32_t reps, double *ms);
 /* ---- batched and served solves ------------------------------------------ */
 
 /* One problem for the batch engine (all pointers host memory, copied on
- * submit).  params.projection must be POGS_PROJ_DIRECT (EUNSUPPORTED
- * otherwise): the grouped path runs on cached factors. */
+ * submit).  params.projection must be POGS_PROJ_DIRECT and params.stop_rule
+ * POGS_STOP_RESIDUAL (EUNSUPPORTED otherwise): the grouped path runs on
+ * cached factors and the residual test. */
 typedef struct {
   int64_t m, n;
   const void *A;

@@ -12,6 +12,7 @@
 // whole-GPU path on a second thread and stream, overlapping the chunks.
 #include <algorithm>
 #include <cfloat>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -51,7 +52,8 @@ int check_problem(const pogs_problem *p) {
   if (p->ord != POGS_ROW_MAJOR && p->ord != POGS_COL_MAJOR) return POGS_EINVAL;
   if (p->lda < (p->ord == POGS_ROW_MAJOR ? p->n : p->m)) return POGS_EINVAL;
   if (check_params(p->params)) return POGS_EINVAL;
-  if (p->params.projection != POGS_PROJ_DIRECT) return POGS_EUNSUPPORTED;  // grouped path: cached factors
+  // grouped path: cached factors and the residual test
+  if (p->params.projection != POGS_PROJ_DIRECT || p->params.stop_rule != POGS_STOP_RESIDUAL) return POGS_EUNSUPPORTED;
   return POGS_OK;
 }
 
@@ -99,6 +101,8 @@ void fill_result(const GStatus &st, pogs_result *out, double ms_solve) {
   out->ms_setup = 0.0;
   out->ms_solve = ms_solve;
   out->cg_steps = 0;
+  out->gap = NAN;
+  out->eps_gap = NAN;
 }
 
 // Whole-GPU path for one problem (used for problems too large for a workgroup).

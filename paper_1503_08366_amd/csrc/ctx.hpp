@@ -184,6 +184,7 @@ struct pogs_ctx {
   hipGraphExec_t graph = nullptr;
   int graph_chunk = 0;
   int graph_cg_cap = 0;  // CGLS step cap of the captured graph (0: direct projection)
+  int graph_gap = 0;     // the captured graph runs the gap test
   bool solved = false;  // functions uploaded by a previous solve
 
   size_t esz() const { return dt == POGS_F32 ? 4 : 8; }
@@ -240,6 +241,8 @@ struct pogs_ctx {
     p.s_gam = p.s_dual + n_dual;     // 2 x n_dual
     p.s_sig = p.s_gam + 2 * n_dual;  // 2 x n_dual
     p.s_qq = p.s_sig + 2 * n_dual;   // n_pri
+    p.s_gobj = p.s_qq + n_pri;       // nbx + nby
+    p.s_gconj = p.s_gobj + nbx + nby;  // nbx + nby
     return p;
   }
   ~pogs_ctx() {

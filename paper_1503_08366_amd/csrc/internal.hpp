@@ -15,7 +15,8 @@ struct CtrlState {
   int l, u;         // Algorithm 3 markers
   int done;         // 0 running, else 1 + pogs status
   int pending;      // 1: the partial sums of iteration k wait for their stop test
-  int pad;
+  int by_gap;       // stopped by the gap test: the result is (x, y, -rho x~, -rho y~)
+  double eta, eps_gap;  // gap of the state after k iterations and its tolerance (gap rule)
 };
 
 // State of the CGLS projection (Section 3.5, indirect) of the current
@@ -45,7 +46,7 @@ struct Ctrl {
   CtrlState st[2];
   double cg_tol;  // CGLS tolerance factor (projection = CGLS)
   int cg_cap;     // CGLS step cap per projection
-  int pad;
+  int stop_gap;   // 1: gap-based stopping (Section 3.4) instead of the residual test
   CgState cg;
 };
 
@@ -78,6 +79,9 @@ template <typename T> struct IterArgs {
   // step parity); per row-block partials of ||q||^2 (n_pri)
   T *pv, *qv, *sv;
   double *s_gam, *s_sig, *s_qq;
+  // gap rule only: per prox-block partial sums of f^(y) + g^(x) and of
+  // f^*(-rho y~) + g^*(-rho x~) for the state entering the prox step
+  double *s_gobj, *s_gconj;
 };
 
 // ---- launchers (setup.hip) ------------------------------------------------
@@ -115,6 +119,12 @@ template <typename T> void launch_scale_fn(const uint8_t *h, const double *a, co
                                            T *oa, T *ob, T *oc, T *od, T *oe, hipStream_t s);
 template <typename T> void launch_iteration(const IterArgs<T> &p, int splits, int rows_per_split,
                                             int ncolp, hipStream_t s);
+// The same iteration with the gap test between the prox step and pass 1.
+template <typename T> void launch_iteration_gap(const IterArgs<T> &p, int splits, int rows_per_split,
+                                                int ncolp, hipStream_t s);
+// The gap test (Section 3.4) on the sums of the prox step just launched: sets
+// the stop flag of this iteration when eta < eps_abs + eps_rel |f + g|.
+template <typename T> void launch_gap_check(const IterArgs<T> &p, hipStream_t s);
 // Run the stop test of the last iteration of a launch sequence whose last
 // iteration had parity `par` (writes st[1 - par]); for the host's check.
 template <typename T> void launch_control_preview(const IterArgs<T> &p, int par, hipStream_t s);
@@ -122,12 +132,15 @@ template <typename T> void launch_iteration_part(const IterArgs<T> &p, int which
                                                  int ncolp, hipStream_t s);
 template <typename T> void launch_project(const IterArgs<T> &p, int splits, int rows_per_split,
                                           int ncolp, const T *c, const T *d, T *x, T *y, hipStream_t s);
+// from_state = 0 returns the half-step tuple; 1 returns the state
+// (x, y, -rho x~, -rho y~) the gap test accepted.
 template <typename T>
 void launch_unscale(const IterArgs<T> &p, const double *D, const double *E, const uint8_t *fh0,
                     const double *fa0, const double *fb0, const double *fc0, const double *fd0,
                     const double *fe0, const uint8_t *gh0, const double *ga0, const double *gb0,
                     const double *gc0, const double *gd0, const double *ge0, T *xo, T *yo, T *muo,
-                    T *nuo, double *obj_slots, double *obj_out, unsigned *cnt, hipStream_t s);
+                    T *nuo, double *obj_slots, double *obj_out, unsigned *cnt, int from_state, double rho,
+                    hipStream_t s);
 template <typename T> void launch_prox_eval(const uint8_t *h, const T *a, const T *b, const T *c,
                                             const T *d, const T *e, double rho, const T *v, T *out,
                                             int len, hipStream_t s);

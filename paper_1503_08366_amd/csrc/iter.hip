@@ -199,6 +199,13 @@ void launch_iteration(const IterArgs<T> &p, int splits, int rps, int ncolp, hipS
   for (int w = 0; w < 4; ++w) launch_iteration_part<T>(p, w, splits, rps, ncolp, s);
 }
 
+template <typename T>
+void launch_iteration_gap(const IterArgs<T> &p, int splits, int rps, int ncolp, hipStream_t s) {
+  launch_iteration_part<T>(p, 0, splits, rps, ncolp, s);
+  launch_gap_check<T>(p, s);
+  for (int w = 1; w < 4; ++w) launch_iteration_part<T>(p, w, splits, rps, ncolp, s);
+}
+
 template <typename T> void launch_control_preview(const IterArgs<T> &p, int par, hipStream_t s) {
   hipLaunchKernelGGL(control_preview_kernel<T>, dim3(1), dim3(kBlock), 0, s, p, par);
 }
@@ -289,9 +296,9 @@ __global__ __launch_bounds__(kBlock) void unscale_kernel(
     IterArgs<T> p, const double *D, const double *E, const uint8_t *fh, const double *fa,
     const double *fb, const double *fc, const double *fd, const double *fe, const uint8_t *gh,
     const double *ga, const double *gb, const double *gc, const double *gd, const double *ge, T *xo,
-    T *yo, T *muo, T *nuo, double *slots, double *obj, unsigned *cnt) {
+    T *yo, T *muo, T *nuo, double *slots, double *obj, unsigned *cnt, int from_state, double rho) {
   unscale_body<T>(hw_block(), p, D, E, fh, fa, fb, fc, fd, fe, gh, ga, gb, gc, gd, ge, xo, yo, muo, nuo, slots, obj,
-                  cnt);
+                  cnt, from_state, rho);
 }
 
 template <typename T>
@@ -299,9 +306,20 @@ void launch_unscale(const IterArgs<T> &p, const double *D, const double *E, cons
                     const double *fa0, const double *fb0, const double *fc0, const double *fd0,
                     const double *fe0, const uint8_t *gh0, const double *ga0, const double *gb0,
                     const double *gc0, const double *gd0, const double *ge0, T *xo, T *yo, T *muo,
-                    T *nuo, double *obj_slots, double *obj_out, unsigned *cnt, hipStream_t s) {
+                    T *nuo, double *obj_slots, double *obj_out, unsigned *cnt, int from_state, double rho,
+                    hipStream_t s) {
   hipLaunchKernelGGL(unscale_kernel<T>, dim3(p.nbx + p.nby), dim3(kBlock), 0, s, p, D, E, fh0, fa0, fb0,
-                     fc0, fd0, fe0, gh0, ga0, gb0, gc0, gd0, ge0, xo, yo, muo, nuo, obj_slots, obj_out, cnt);
+                     fc0, fd0, fe0, gh0, ga0, gb0, gc0, gd0, ge0, xo, yo, muo, nuo, obj_slots, obj_out, cnt,
+                     from_state, rho);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void gap_check_kernel(IterArgs<T> p) {
+  gap_check_body<T>(p);
+}
+
+template <typename T> void launch_gap_check(const IterArgs<T> &p, hipStream_t s) {
+  hipLaunchKernelGGL(gap_check_kernel<T>, dim3(1), dim3(kBlock), 0, s, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -323,6 +341,7 @@ void launch_prox_eval(const uint8_t *h, const T *a, const T *b, const T *c, cons
 
 #define POGS_INST(T)                                                                                   \
   template void launch_iteration<T>(const IterArgs<T> &, int, int, int, hipStream_t);                  \
+  template void launch_iteration_gap<T>(const IterArgs<T> &, int, int, int, hipStream_t);              \
   template void launch_iteration_part<T>(const IterArgs<T> &, int, int, int, int, hipStream_t);        \
   template void launch_control_preview<T>(const IterArgs<T> &, int, hipStream_t);                      \
   template void launch_project<T>(const IterArgs<T> &, int, int, int, const T *, const T *, T *, T *,  \
@@ -336,7 +355,9 @@ void launch_prox_eval(const uint8_t *h, const T *a, const T *b, const T *c, cons
                                   const uint8_t *, const double *, const double *, const double *,     \
                                   const double *, const double *, const uint8_t *, const double *,     \
                                   const double *, const double *, const double *, const double *, T *, \
-                                  T *, T *, T *, double *, double *, unsigned *, hipStream_t);         \
+                                  T *, T *, T *, double *, double *, unsigned *, int, double,          \
+                                  hipStream_t);                                                        \
+  template void launch_gap_check<T>(const IterArgs<T> &, hipStream_t);                                 \
   template void launch_prox_eval<T>(const uint8_t *, const T *, const T *, const T *, const T *,       \
                                     const T *, double, const T *, T *, int, hipStream_t);
 POGS_INST(float)

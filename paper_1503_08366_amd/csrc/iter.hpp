@@ -8,6 +8,7 @@
 
 #include "gemv.hpp"
 #include "internal.hpp"
+#include "gap.hpp"
 #include "prox.hpp"
 
 namespace pogs {
@@ -69,7 +70,7 @@ __device__ void control_apply(const IterArgs<T> &p, double part[4], CtrlState &s
     int done = 0;
     if (!isfinite(r_pri) || !isfinite(r_dual)) {
       done = 1 + POGS_NUMERICAL;
-    } else if (r_pri < eps_pri && r_dual < eps_dual) {
+    } else if (!q.stop_gap && r_pri < eps_pri && r_dual < eps_dual) {
       done = 1 + POGS_CONVERGED;
     } else {
       if (q.adaptive) {
@@ -168,11 +169,18 @@ __device__ __forceinline__ void prox_body(const Blk &b, const IterArgs<T> &p) {
   const T rho = (T)st.rho;
   const T resc = (T)st.rescale;
   const T alpha = (T)p.ctrl->alpha;
-  double contrib = 0.0;
+  const bool gap = !CG && p.ctrl->stop_gap;
+  double contrib = 0.0, gobj = 0.0, gconj = 0.0;
   if (i < len) {
     if (resc != T(1)) {
       vti *= resc;
       if constexpr (!CG) vt[i] = vti;
+    }
+    if (gap) {
+      // the state is primal and dual feasible: value at (x, y), conjugate at
+      // (mu, nu) = (-rho x~, -rho y~)
+      gobj = fn_value_strict(fh, fa, fb, fc, fd, fe, (double)vi);
+      gconj = fn_conj_value(fh, fa, fb, fc, fd, fe, -(double)st.rho * (double)vti);
     }
     const T arg = vi - vti;
     const T h = prox_param<T>(fh, fa, fb, fc, fd, fe, arg, rho);
@@ -194,6 +202,42 @@ __device__ __forceinline__ void prox_body(const Blk &b, const IterArgs<T> &p) {
   if (threadIdx.x == 0) {
     if (xs) p.s_mu[(size_t)par * p.nbx + blk] = s;
     else p.s_yh[(size_t)par * p.nby + blk] = s;
+  }
+  if (gap) {
+    const double so = block_sum(gobj, bs);
+    const double sc = block_sum(gconj, bs);
+    if (threadIdx.x == 0) {
+      p.s_gobj[b.x] = so;
+      p.s_gconj[b.x] = sc;
+    }
+  }
+}
+
+// Gap test of the state entering this iteration's prox step (one workgroup):
+// eta = sum of the prox blocks' value and conjugate sums, checked from the
+// second iteration on (the state after at least one projection).
+template <typename T>
+__device__ __forceinline__ void gap_check_body(const IterArgs<T> &p) {
+  __shared__ double bs[kBlock / kWave];
+  CtrlState &st = p.ctrl->st[p.par];
+  if (st.done || st.k == 0) return;
+  const int nb = p.nbx + p.nby;
+  double o = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    o += p.s_gobj[i];
+    c += p.s_gconj[i];
+  }
+  o = block_sum(o, bs);
+  c = block_sum(c, bs);
+  if (threadIdx.x == 0) {
+    const double eta = o + c;
+    const double eps = p.ctrl->eps_abs + p.ctrl->eps_rel * fabs(o);
+    st.eta = eta;
+    st.eps_gap = eps;
+    if (eta < eps) {
+      st.done = 1 + POGS_CONVERGED;
+      st.by_gap = 1;
+    }
   }
 }
 
@@ -328,7 +372,7 @@ __device__ __forceinline__ void unscale_body(
     const Blk &b, const IterArgs<T> &p, const double *D, const double *E, const uint8_t *fh, const double *fa,
     const double *fb, const double *fc, const double *fd, const double *fe, const uint8_t *gh,
     const double *ga, const double *gb, const double *gc, const double *gd, const double *ge, T *xo,
-    T *yo, T *muo, T *nuo, double *slots, double *obj, unsigned *cnt) {
+    T *yo, T *muo, T *nuo, double *slots, double *obj, unsigned *cnt, int from_state = 0, double rho = 0.0) {
   __shared__ double bs[kBlock / kWave];
   __shared__ int flag;
   const bool xs = b.x < p.nbx;
@@ -336,14 +380,18 @@ __device__ __forceinline__ void unscale_body(
   const int i = blk * kBlock + threadIdx.x;
   double contrib = 0.0;
   if (xs && i < p.n) {
-    const double x = E[i] * (double)p.xh[i];
+    const double xv = from_state ? (double)p.x[i] : (double)p.xh[i];
+    const double mv = from_state ? -rho * (double)p.xt[i] : (double)p.mu[i];
+    const double x = E[i] * xv;
     if (xo) xo[i] = (T)x;
-    if (muo) muo[i] = (T)((double)p.mu[i] / E[i]);
+    if (muo) muo[i] = (T)(mv / E[i]);
     contrib = fn_value(gh[i], ga[i], gb[i], gc[i], gd[i], ge[i], x);
   } else if (!xs && i < p.m) {
-    const double y = (double)p.yh[i] / D[i];
+    const double yv = from_state ? (double)p.y[i] : (double)p.yh[i];
+    const double nv = from_state ? -rho * (double)p.yt[i] : (double)p.nu[i];
+    const double y = yv / D[i];
     if (yo) yo[i] = (T)y;
-    if (nuo) nuo[i] = (T)(D[i] * (double)p.nu[i]);
+    if (nuo) nuo[i] = (T)(D[i] * nv);
     contrib = fn_value(fh[i], fa[i], fb[i], fc[i], fd[i], fe[i], y);
   }
   const double s = block_sum(contrib, bs);

@@ -4,6 +4,7 @@
 // state allocation, graph-captured iteration chunks, results.
 #include <chrono>
 #include <cstring>
+#include <cmath>
 #include <vector>
 
 #include "ctx.hpp"
@@ -43,7 +44,8 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
   if (ctx->dt != POGS_F32 || ctx->m < ctx->n) return POGS_EUNSUPPORTED;
   pogs_params prm = params ? *params : ctx->params;
   if (check_params(prm)) return POGS_EINVAL;
-  if (ctx->proj != POGS_PROJ_DIRECT || prm.projection != POGS_PROJ_DIRECT) return POGS_EUNSUPPORTED;
+  if (ctx->proj != POGS_PROJ_DIRECT || prm.projection != POGS_PROJ_DIRECT || prm.stop_rule != POGS_STOP_RESIDUAL)
+    return POGS_EUNSUPPORTED;
   const double t0 = now_ms();
   const int m = (int)ctx->m, n = (int)ctx->n;
   std::vector<HostFn> hf(R), hg(R);
@@ -208,6 +210,9 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
     out[r].status = hi[4 * Rp + r] < 0 ? POGS_MAXITER : hi[4 * Rp + r];
     out[r].ms_setup = ctx->ms_setup;
     out[r].ms_solve = ms;
+    out[r].cg_steps = 0;
+    out[r].gap = NAN;
+    out[r].eps_gap = NAN;
   }
   return POGS_OK;
 }

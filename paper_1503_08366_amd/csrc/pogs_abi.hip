@@ -3,6 +3,7 @@
 // that replays captured iteration chunks until the device stop flag is set.
 #include <algorithm>
 #include <cfloat>
+#include <cmath>
 #include <chrono>
 #include <cstring>
 #include <new>
@@ -55,6 +56,7 @@ int pogs_params_default(pogs_params *p) {
   p->projection = POGS_PROJ_DIRECT;
   p->cg_max_iter = 10;
   p->cg_tol = 0.1;
+  p->stop_rule = POGS_STOP_RESIDUAL;
   return POGS_OK;
 }
 
@@ -150,7 +152,8 @@ template <typename T> int alloc_iteration(pogs_ctx *c) {
   c->n_dual = (int)cdiv(n, kFinishCols);
   // prox sums (two parities), residual sums, CGLS sums (||s||^2 and s^T p by
   // step parity, ||q||^2), then the unscale kernel's sums
-  const int nslots = 2 * (c->nbx + c->nby) + c->n_pri + c->n_dual + 4 * c->n_dual + c->n_pri + c->nbx + c->nby;
+  const int nslots = 2 * (c->nbx + c->nby) + c->n_pri + c->n_dual + 4 * c->n_dual + c->n_pri +
+                     2 * (c->nbx + c->nby) + c->nbx + c->nby;
   const int ntiles = (int)cdiv(n, gemv_t_tile(sizeof(T)));
   // raw functions: fh0 | gh0 | f0 | g0, uploaded in one copy
   Carve raw;
@@ -287,19 +290,21 @@ int even_chunk(int requested) {
 
 // One chunk of iterations (chunk even: iteration parity is i % 2), then the
 // stop test of its last iteration so the state after the chunk is in st[0].
-// cg_cap > 0 selects the CGLS projection with that step cap.
-template <typename T> void launch_chunk(pogs_ctx *c, int chunk, int cg_cap, hipStream_t s) {
+// cg_cap > 0 selects the CGLS projection with that step cap; gap adds the
+// gap test after each prox step.
+template <typename T> void launch_chunk(pogs_ctx *c, int chunk, int cg_cap, int gap, hipStream_t s) {
   IterArgs<T> p = c->iter_args<T>();
   for (int i = 0; i < chunk; ++i) {
     p.par = i & 1;
     if (cg_cap > 0) launch_iteration_cg<T>(p, c->splits, c->rps, c->ncolp, cg_cap, s);
+    else if (gap) launch_iteration_gap<T>(p, c->splits, c->rps, c->ncolp, s);
     else launch_iteration<T>(p, c->splits, c->rps, c->ncolp, s);
   }
   launch_control_preview<T>(p, 1, s);
 }
 
-template <typename T> int ensure_graph(pogs_ctx *c, int chunk, int cg_cap) {
-  if (c->graph && c->graph_chunk == chunk && c->graph_cg_cap == cg_cap) return POGS_OK;
+template <typename T> int ensure_graph(pogs_ctx *c, int chunk, int cg_cap, int gap) {
+  if (c->graph && c->graph_chunk == chunk && c->graph_cg_cap == cg_cap && c->graph_gap == gap) return POGS_OK;
   if (c->graph) {
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
@@ -310,13 +315,14 @@ template <typename T> int ensure_graph(pogs_ctx *c, int chunk, int cg_cap) {
   if (!cap) POGS_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipGraph_t g;
   POGS_HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  launch_chunk<T>(c, chunk, cg_cap, cap);
+  launch_chunk<T>(c, chunk, cg_cap, gap, cap);
   POGS_HIP_TRY(hipStreamEndCapture(cap, &g));
   hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return POGS_EDEVICE;
   c->graph_chunk = chunk;
   c->graph_cg_cap = cg_cap;
+  c->graph_gap = gap;
   return POGS_OK;
 }
 
@@ -326,6 +332,7 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   const int m = (int)c->m, n = (int)c->n;
   hipStream_t s = c->stream;
   const int cg_cap = p.projection == POGS_PROJ_CGLS ? p.cg_max_iter : 0;
+  const int gap = p.stop_rule == POGS_STOP_GAP ? 1 : 0;
   int rc;
   if ((rc = upload_fns<T>(c, f, g))) return rc;
   // zero state (Algorithm 1 starts from x = y = x~ = y~ = 0), or the warm start
@@ -360,19 +367,20 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   }
   h.cg_tol = p.cg_tol;
   h.cg_cap = cg_cap;
+  h.stop_gap = gap;
   h.cg.stop = -1;
   *c->ctrl_host = h;
   POGS_HIP_TRY(hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   const int chunk = even_chunk(p.chunk_iters);
   // Without a graph for this chunk size yet, the first chunk is launched
   // directly and the graph is captured while the GPU runs it.
-  bool eager = !(c->graph && c->graph_chunk == chunk && c->graph_cg_cap == cg_cap);
+  bool eager = !(c->graph && c->graph_chunk == chunk && c->graph_cg_cap == cg_cap && c->graph_gap == gap);
   for (;;) {
-    if (eager) launch_chunk<T>(c, chunk, cg_cap, s);
+    if (eager) launch_chunk<T>(c, chunk, cg_cap, gap, s);
     else POGS_HIP_TRY(hipGraphLaunch(c->graph, s));
     POGS_HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     if (eager) {
-      if ((rc = ensure_graph<T>(c, chunk, cg_cap))) return rc;
+      if ((rc = ensure_graph<T>(c, chunk, cg_cap, gap))) return rc;
       eager = false;
     }
     POGS_HIP_TRY(hipStreamSynchronize(s));
@@ -392,9 +400,11 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
     nuo = (T *)out->nu;
   }
   double *fa = c->f0, *ga = c->g0;
+  const CtrlState &fin = c->ctrl_host->st[0];
   launch_unscale<T>(ia, c->D, c->E, c->fh0, fa, fa + m, fa + 2 * m, fa + 3 * m, fa + 4 * m, c->gh0, ga, ga + n,
-                    ga + 2 * n, ga + 3 * n, ga + 4 * n, xo, yo, muo, nuo, ia.s_qq + ia.n_pri,
-                    c->obj_dev, c->counters + (int)cdiv(n, gemv_t_tile(sizeof(T))) + 8, s);
+                    ga + 2 * n, ga + 3 * n, ga + 4 * n, xo, yo, muo, nuo, ia.s_gconj + ia.nbx + ia.nby,
+                    c->obj_dev, c->counters + (int)cdiv(n, gemv_t_tile(sizeof(T))) + 8, fin.by_gap,
+                    fin.rho, s);
   POGS_HIP_TRY(hipMemcpyAsync(c->obj_host, c->obj_dev, sizeof(double), hipMemcpyDeviceToHost, s));
   if (out->mem == POGS_HOST) {
     if (out->x) POGS_HIP_TRY(hipMemcpyAsync(out->x, xo, (size_t)n * sizeof(T), hipMemcpyDeviceToHost, s));
@@ -414,6 +424,8 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   out->iters = r.k;
   out->status = r.done - 1;
   out->cg_steps = c->ctrl_host->cg.steps_total;
+  out->gap = gap ? r.eta : NAN;
+  out->eps_gap = gap ? r.eps_gap : NAN;
   out->ms_setup = c->ms_setup;
   out->ms_solve = now_ms() - t0;
   c->solved = true;
@@ -442,7 +454,7 @@ template <typename T> int profile_impl(pogs_ctx *c, int reps, double *ms) {
   POGS_HIP_TRY(hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   const int chunk = even_chunk(c->params.chunk_iters);
   int rc;
-  if ((rc = ensure_graph<T>(c, chunk, cg_cap))) return rc;
+  if ((rc = ensure_graph<T>(c, chunk, cg_cap, 0))) return rc;
   hipEvent_t e0, e1;
   POGS_HIP_TRY(hipEventCreate(&e0));
   POGS_HIP_TRY(hipEventCreate(&e1));
@@ -485,8 +497,10 @@ extern "C" int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, con
   if (out->mem != POGS_HOST && out->mem != POGS_DEVICE) return POGS_EINVAL;
   pogs_params p = params ? *params : ctx->params;
   if (check_params(p)) return POGS_EINVAL;
-  // a context set up for CGLS has no factor for the direct projection
+  // a context set up for CGLS has no factor for the direct projection; the
+  // CGLS state does not keep x~ and y~ for the gap test
   if (p.projection == POGS_PROJ_DIRECT && ctx->proj != POGS_PROJ_DIRECT) return POGS_EUNSUPPORTED;
+  if (p.projection == POGS_PROJ_CGLS && p.stop_rule == POGS_STOP_GAP) return POGS_EUNSUPPORTED;
   HostFn hf, hg;
   int rc;
   if ((rc = expand_fn(f, ctx->m, &hf))) return rc;

@@ -51,7 +51,8 @@ class pogs_params(C.Structure):
                 ("rho0", C.c_double), ("alpha", C.c_double), ("delta", C.c_double),
                 ("tau", C.c_double), ("adaptive_rho", C.c_int32), ("equil_iters", C.c_int32),
                 ("eps_cmp", C.c_double), ("chunk_iters", C.c_int32), ("verbose", C.c_int32),
-                ("projection", C.c_int32), ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double)]
+                ("projection", C.c_int32), ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
+                ("stop_rule", C.c_int32)]
 
 
 class pogs_result(C.Structure):
@@ -60,7 +61,7 @@ class pogs_result(C.Structure):
                 ("r_dual", C.c_double), ("eps_pri", C.c_double), ("eps_dual", C.c_double),
                 ("rho", C.c_double), ("iters", C.c_int32), ("status", C.c_int32),
                 ("ms_setup", C.c_double), ("ms_solve", C.c_double), ("cg_steps", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("gap", C.c_double), ("eps_gap", C.c_double)]
 
 
 class pogs_problem(C.Structure):
@@ -144,11 +145,12 @@ def _check(rc: int, what: str):
 # --- marshalling helpers -----------------------------------------------------
 
 PROJECTIONS = {"direct": 0, "cgls": 1}
+STOP_RULES = {"residual": 0, "gap": 1}
 
 
 def default_params(**overrides) -> pogs_params:
-    """pogs_params_default with fields overridden by keyword; projection may be
-    given by name ("direct", "cgls")."""
+    """pogs_params_default with fields overridden by keyword; projection and
+    stop_rule may be given by name ("direct", "cgls"; "residual", "gap")."""
     p = pogs_params()
     _check(_lib().pogs_params_default(C.byref(p)), "pogs_params_default")
     for k, v in overrides.items():
@@ -156,6 +158,8 @@ def default_params(**overrides) -> pogs_params:
             raise KeyError(k)
         if k == "projection" and isinstance(v, str):
             v = PROJECTIONS[v]
+        if k == "stop_rule" and isinstance(v, str):
+            v = STOP_RULES[v]
         setattr(p, k, v)
     return p
 
@@ -218,6 +222,7 @@ class Result:
         self.status = r.status
         self.ms_setup, self.ms_solve = r.ms_setup, r.ms_solve
         self.cg_steps = r.cg_steps
+        self.gap, self.eps_gap = r.gap, r.eps_gap
 
     @property
     def converged(self) -> bool:
