@@ -181,6 +181,26 @@ int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, pogs_dtype dt
               pogs_order ord, int64_t lda, pogs_mem mem, const pogs_params *params,
               void *stream);
 
+/* Create a context for a sparse A (m x n) in compressed rows: row i holds the
+ * entries colind[rowptr[i] .. rowptr[i + 1]) (0-based column indices, any
+ * order, repeated indices add up) with values val (dtype dt); rowptr has
+ * m + 1 entries, rowptr[0] = 0 and rowptr[m] = nnz.  All three arrays in
+ * memory `mem`, copied (the caller may free them on return).  The library
+ * keeps A^ = D A E twice in compressed rows on the device, as A^ and as its
+ * transpose (built by a stable counting sort over the columns), runs
+ * Algorithm 2 and the Frobenius normalisation of Section 4.1.2 with row passes
+ * over both, and projects by CGLS (Section 3.5, indirect; no factorisation of
+ * a sparse K): solves on this context use POGS_PROJ_CGLS whatever
+ * params->projection says, with cg_max_iter and cg_tol as given.  Warm starts,
+ * the gap rule, pogs_project and pogs_solve_path are not available on it
+ * (EUNSUPPORTED).  Limits: nnz, m, n below 2^31 (int32 indices on the device).
+ * Errors: EINVAL (m, n <= 0, nnz < 0, NULL pointers, rowptr not
+ * non-decreasing from 0 to nnz, a column index outside [0, n), non-finite
+ * values, invalid params), ENOMEM, EDEVICE.  On error *out is set to NULL. */
+int pogs_init_sparse(pogs_ctx **out, int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                     const int32_t *colind, const void *val, pogs_dtype dt, pogs_mem mem,
+                     const pogs_params *params, void *stream);
+
 /* Solve with functions f (len m) and g (len n) on the context's matrix.
  * params may be NULL (the context's).
  * Warm start (Section 5: the caller may supply x0 and nu0): x0 (len n) and

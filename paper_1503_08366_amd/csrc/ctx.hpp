@@ -162,6 +162,12 @@ struct pogs_ctx {
   void *A = nullptr;     // scaled matrix, T
   void *Kinv = nullptr;  // (I + G)^{-1}, T (direct projection only)
   int proj = POGS_PROJ_DIRECT;  // projection the context was set up for
+  // sparse contexts: A^ and A^T in compressed rows (int32 indices, T values)
+  bool sparse = false;
+  int64_t nnz = 0;
+  int *sp_rp = nullptr, *sp_ci = nullptr, *sp_rpt = nullptr, *sp_cit = nullptr;
+  void *sp_va = nullptr, *sp_vat = nullptr;
+  int sp_lpr = 0, sp_grid = 0, sp_lprt = 0, sp_gridt = 0;
   double *D = nullptr, *E = nullptr;
   // iteration state (T): x y xt yt xh yh mu nu cx dy rhs, outputs xo yo muo nuo
   void *vec = nullptr;
@@ -243,6 +249,10 @@ struct pogs_ctx {
     p.s_qq = p.s_sig + 2 * n_dual;   // n_pri
     p.s_gobj = p.s_qq + n_pri;       // nbx + nby
     p.s_gconj = p.s_gobj + nbx + nby;  // nbx + nby
+    if (sparse) {
+      p.sa = Csr<T>{sp_rp, sp_ci, (T *)sp_va, (int)m, sp_lpr, sp_grid};
+      p.sat = Csr<T>{sp_rpt, sp_cit, (T *)sp_vat, (int)n, sp_lprt, sp_gridt};
+    }
     return p;
   }
   ~pogs_ctx() {

@@ -56,6 +56,16 @@ template <typename T> struct FnDev {
   const T *a, *b, *c, *d, *e;
 };
 
+// Sparse matrix in compressed rows on the device: row r holds the entries
+// ci[rp[r] .. rp[r + 1]) with values va.  The passes over it give each row lpr
+// lanes (a power of two up to 64) and launch `grid` workgroups.
+template <typename T> struct Csr {
+  const int *rp;
+  const int *ci;
+  T *va;
+  int rows, lpr, grid;
+};
+
 // Everything one iteration of the single-problem pipeline touches.
 template <typename T> struct IterArgs {
   int m, n, ld;          // scaled matrix A^ (row-major, leading dim ld)
@@ -82,6 +92,8 @@ template <typename T> struct IterArgs {
   // gap rule only: per prox-block partial sums of f^(y) + g^(x) and of
   // f^*(-rho y~) + g^*(-rho x~) for the state entering the prox step
   double *s_gobj, *s_gconj;
+  // sparse contexts only: A^ and A^T in compressed rows
+  Csr<T> sa, sat;
 };
 
 // ---- launchers (setup.hip) ------------------------------------------------
@@ -159,6 +171,8 @@ template <typename T> void launch_iteration_cg(const IterArgs<T> &p, int splits,
 // Parts of it for the profiler: 0 prox, 1 first passes, 2 one CG step.
 template <typename T> void launch_iteration_cg_part(const IterArgs<T> &p, int which, int splits, int rps,
                                                     int ncolp, hipStream_t s);
+// The prox step in the form the CGLS iteration reads its state.
+template <typename T> void launch_prox_cg(const IterArgs<T> &p, hipStream_t s);
 // State kept by the CGLS iteration from the direct state (x, y, x~, y~):
 // c = x + x~, d = y + y~ (then x~ = c - x, y = d - y~ as the prox step reads them).
 template <typename T> void launch_cg_from_state(const IterArgs<T> &p, hipStream_t s);
@@ -173,6 +187,20 @@ struct GemvNShape {
   int grid;
 };
 GemvNShape gemv_n_shape(int m, int n, int ld, int elem_size);
+
+// Sparse contexts (sparse.hip).  Lanes per row and grid of the passes over a
+// matrix with `rows` rows and `nnz` entries.
+void sparse_shape(int rows, int64_t nnz, int *lpr, int *grid);
+// Algorithm 2 and the Frobenius normalisation on the sparse pair (A, A^T),
+// then both scaled in place to D A E: fills D (m), E (n).  ws: 2 (m + n) + 1024
+// doubles.
+template <typename T>
+void run_equilibrate_sparse(Csr<T> A, Csr<T> At, int m, int n, int iters, double eps_cmp, double *D, double *E,
+                            double *ws, hipStream_t s);
+// One iteration with the CGLS projection on the sparse pair (two launches per CG step).
+template <typename T> void launch_iteration_cg_sparse(const IterArgs<T> &p, int cap, hipStream_t s);
+// Parts for the profiler: 0 prox, 1 first passes, 2 one CG step.
+template <typename T> void launch_iteration_cg_sparse_part(const IterArgs<T> &p, int which, hipStream_t s);
 
 // Iteration geometry helpers.
 int gemv_t_tile(int elem_size);

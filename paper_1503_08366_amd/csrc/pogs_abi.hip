@@ -144,12 +144,14 @@ template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, 
 template <typename T> int alloc_iteration(pogs_ctx *c) {
   static_assert(sizeof(Ctrl) <= PinnedSlab::kChunk, "control block larger than a pinned slab chunk");
   const int m = (int)c->m, n = (int)c->n;
-  // gemv_t geometry over the n columns (same for both orientations)
+  // gemv_t geometry over the n columns (same for both orientations); a sparse
+  // context's residual sums come from its row passes over A^ and A^T
   gemv_t_geometry(m, n, sizeof(T), &c->splits, &c->rps, &c->ncolp);
   c->nbx = (int)cdiv(n, kBlock);
   c->nby = (int)cdiv(m, kBlock);
-  c->n_pri = gemv_n_blocks(m, n, sizeof(T), 0);
-  c->n_dual = (int)cdiv(n, kFinishCols);
+  c->n_pri = c->sparse ? c->sp_grid : gemv_n_blocks(m, n, sizeof(T), 0);
+  c->n_dual = c->sparse ? c->sp_gridt : (int)cdiv(n, kFinishCols);
+  if (c->sparse) c->splits = 1;  // no column-sum partials
   // prox sums (two parities), residual sums, CGLS sums (||s||^2 and s^T p by
   // step parity, ||q||^2), then the unscale kernel's sums
   const int nslots = 2 * (c->nbx + c->nby) + c->n_pri + c->n_dual + 4 * c->n_dual + c->n_pri +
@@ -253,6 +255,155 @@ extern "C" int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, po
 
 namespace {
 
+// Host copy of a CSR input checked entry by entry (values widened to double).
+struct HostCsr {
+  std::vector<int> rp, ci;
+  std::vector<double> va;
+};
+
+int read_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *colind, const void *val,
+             pogs_dtype dt, pogs_mem mem, HostCsr *h) {
+  std::vector<int64_t> rp((size_t)m + 1);
+  std::vector<int32_t> ci((size_t)nnz);
+  const size_t es = dt == POGS_F32 ? 4 : 8;
+  std::vector<char> raw((size_t)nnz * es);
+  if (mem == POGS_DEVICE) {
+    if (hipMemcpy(rp.data(), rowptr, rp.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return POGS_EDEVICE;
+    if (nnz && hipMemcpy(ci.data(), colind, ci.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return POGS_EDEVICE;
+    if (nnz && hipMemcpy(raw.data(), val, raw.size(), hipMemcpyDeviceToHost) != hipSuccess) return POGS_EDEVICE;
+  } else {
+    std::memcpy(rp.data(), rowptr, rp.size() * 8);
+    if (nnz) std::memcpy(ci.data(), colind, ci.size() * 4);
+    if (nnz) std::memcpy(raw.data(), val, raw.size());
+  }
+  if (rp[0] != 0 || rp[(size_t)m] != nnz) return POGS_EINVAL;
+  for (int64_t i = 0; i < m; ++i)
+    if (rp[(size_t)i + 1] < rp[(size_t)i]) return POGS_EINVAL;
+  h->rp.resize((size_t)m + 1);
+  for (int64_t i = 0; i <= m; ++i) h->rp[(size_t)i] = (int)rp[(size_t)i];
+  h->ci.assign(ci.begin(), ci.end());
+  h->va.resize((size_t)nnz);
+  for (int64_t k = 0; k < nnz; ++k) {
+    if (ci[(size_t)k] < 0 || ci[(size_t)k] >= n) return POGS_EINVAL;
+    const double v = dt == POGS_F32 ? (double)((const float *)raw.data())[k] : ((const double *)raw.data())[k];
+    if (!std::isfinite(v)) return POGS_EINVAL;
+    h->va[(size_t)k] = v;
+  }
+  return POGS_OK;
+}
+
+// A^T in compressed rows, by a counting sort over the columns that keeps the
+// row order inside each column (deterministic).
+void transpose_csr(const HostCsr &a, int n, HostCsr *t) {
+  const size_t nnz = a.ci.size();
+  t->rp.assign((size_t)n + 1, 0);
+  for (size_t k = 0; k < nnz; ++k) ++t->rp[(size_t)a.ci[k] + 1];
+  for (int j = 0; j < n; ++j) t->rp[(size_t)j + 1] += t->rp[(size_t)j];
+  std::vector<int> cur(t->rp.begin(), t->rp.end() - 1);
+  t->ci.resize(nnz);
+  t->va.resize(nnz);
+  const int m = (int)a.rp.size() - 1;
+  for (int i = 0; i < m; ++i)
+    for (int k = a.rp[(size_t)i]; k < a.rp[(size_t)i + 1]; ++k) {
+      const int pos = cur[(size_t)a.ci[(size_t)k]]++;
+      t->ci[(size_t)pos] = i;
+      t->va[(size_t)pos] = a.va[(size_t)k];
+    }
+}
+
+template <typename T> int init_sparse_impl(pogs_ctx *c, const HostCsr &a, const HostCsr &t) {
+  const int m = (int)c->m, n = (int)c->n;
+  const size_t nnz = a.ci.size();
+  hipStream_t s = c->stream;
+  int rc;
+  sparse_shape(m, (int64_t)nnz, &c->sp_lpr, &c->sp_grid);
+  sparse_shape(n, (int64_t)nnz, &c->sp_lprt, &c->sp_gridt);
+  if ((rc = c->arena.alloc((void **)&c->sp_rp, ((size_t)m + 1) * 4))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->sp_rpt, ((size_t)n + 1) * 4))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->sp_ci, std::max<size_t>(nnz, 1) * 4))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->sp_cit, std::max<size_t>(nnz, 1) * 4))) return rc;
+  if ((rc = c->arena.alloc(&c->sp_va, std::max<size_t>(nnz, 1) * sizeof(T)))) return rc;
+  if ((rc = c->arena.alloc(&c->sp_vat, std::max<size_t>(nnz, 1) * sizeof(T)))) return rc;
+  std::vector<T> va(a.va.begin(), a.va.end()), vat(t.va.begin(), t.va.end());
+  POGS_HIP_TRY(hipMemcpyAsync(c->sp_rp, a.rp.data(), a.rp.size() * 4, hipMemcpyHostToDevice, s));
+  POGS_HIP_TRY(hipMemcpyAsync(c->sp_rpt, t.rp.data(), t.rp.size() * 4, hipMemcpyHostToDevice, s));
+  if (nnz) {
+    POGS_HIP_TRY(hipMemcpyAsync(c->sp_ci, a.ci.data(), nnz * 4, hipMemcpyHostToDevice, s));
+    POGS_HIP_TRY(hipMemcpyAsync(c->sp_cit, t.ci.data(), nnz * 4, hipMemcpyHostToDevice, s));
+    POGS_HIP_TRY(hipMemcpyAsync(c->sp_va, va.data(), nnz * sizeof(T), hipMemcpyHostToDevice, s));
+    POGS_HIP_TRY(hipMemcpyAsync(c->sp_vat, vat.data(), nnz * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  if ((rc = c->arena.alloc((void **)&c->D, (size_t)m * 8))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->E, (size_t)n * 8))) return rc;
+  DevArena tmp(s);
+  double *ws;
+  if ((rc = tmp.alloc((void **)&ws, (2 * ((size_t)m + n) + 1024) * 8))) return rc;
+  const double eps = c->params.eps_cmp > 0.0 ? c->params.eps_cmp : (sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON);
+  const IterArgs<T> ia = c->iter_args<T>();
+  run_equilibrate_sparse<T>(ia.sa, ia.sat, m, n, c->params.equil_iters, eps, c->D, c->E, ws, s);
+  POGS_HIP_TRY(hipStreamSynchronize(s));  // the host copies above are pageable
+  POGS_HIP_TRY(hipGetLastError());
+  return POGS_OK;
+}
+
+}  // namespace
+
+extern "C" int pogs_init_sparse(pogs_ctx **out, int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                                const int32_t *colind, const void *val, pogs_dtype dt, pogs_mem mem,
+                                const pogs_params *params, void *stream) {
+  if (!out) return POGS_EINVAL;
+  *out = nullptr;
+  if (m <= 0 || n <= 0 || nnz < 0 || !rowptr || (nnz > 0 && (!colind || !val))) return POGS_EINVAL;
+  if (m > (1LL << 31) - 2 || n > (1LL << 31) - 2 || nnz > (1LL << 31) - 1) return POGS_EINVAL;
+  if ((dt != POGS_F32 && dt != POGS_F64) || (mem != POGS_HOST && mem != POGS_DEVICE)) return POGS_EINVAL;
+  pogs_params p;
+  pogs_params_default(&p);
+  if (params) p = *params;
+  p.projection = POGS_PROJ_CGLS;
+  if (check_params(p)) return POGS_EINVAL;
+  const double t0 = now_ms();
+  HostCsr a, t;
+  int rc = read_csr(m, n, nnz, rowptr, colind, val, dt, mem, &a);
+  if (rc) return rc;
+  transpose_csr(a, (int)n, &t);
+  pogs_ctx *c = new (std::nothrow) pogs_ctx();
+  if (!c) return POGS_ENOMEM;
+  c->m = m;
+  c->n = n;
+  c->dt = dt;
+  c->params = p;
+  c->proj = POGS_PROJ_CGLS;
+  c->sparse = true;
+  c->nnz = nnz;
+  c->ld = (int)round_up(n, 64);
+  c->q = (int)std::min(m, n);
+  c->Q = (int)round_up(c->q, 64);
+  c->ldk = c->Q;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return POGS_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  c->arena.stream = c->stream;
+  rc = dt == POGS_F32 ? init_sparse_impl<float>(c, a, t) : init_sparse_impl<double>(c, a, t);
+  if (!rc) rc = dt == POGS_F32 ? alloc_iteration<float>(c) : alloc_iteration<double>(c);
+  if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = POGS_EDEVICE;
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  c->ms_setup = now_ms() - t0;
+  *out = c;
+  return POGS_OK;
+}
+
+
+namespace {
+
 template <typename T> int upload_fns(pogs_ctx *c, const HostFn &f, const HostFn &g) {
   const int m = (int)c->m, n = (int)c->n;
   hipStream_t s = c->stream;
@@ -296,7 +447,8 @@ template <typename T> void launch_chunk(pogs_ctx *c, int chunk, int cg_cap, int 
   IterArgs<T> p = c->iter_args<T>();
   for (int i = 0; i < chunk; ++i) {
     p.par = i & 1;
-    if (cg_cap > 0) launch_iteration_cg<T>(p, c->splits, c->rps, c->ncolp, cg_cap, s);
+    if (c->sparse) launch_iteration_cg_sparse<T>(p, cg_cap, s);
+    else if (cg_cap > 0) launch_iteration_cg<T>(p, c->splits, c->rps, c->ncolp, cg_cap, s);
     else if (gap) launch_iteration_gap<T>(p, c->splits, c->rps, c->ncolp, s);
     else launch_iteration<T>(p, c->splits, c->rps, c->ncolp, s);
   }
@@ -469,7 +621,8 @@ template <typename T> int profile_impl(pogs_ctx *c, int reps, double *ms) {
   ms[0] = (double)t / ((double)launches * chunk);
   const IterArgs<T> p = c->iter_args<T>();
   auto part = [&](int w) {
-    if (cg_cap > 0) launch_iteration_cg_part<T>(p, w, c->splits, c->rps, c->ncolp, s);
+    if (c->sparse) launch_iteration_cg_sparse_part<T>(p, w, s);
+    else if (cg_cap > 0) launch_iteration_cg_part<T>(p, w, c->splits, c->rps, c->ncolp, s);
     else launch_iteration_part<T>(p, w, c->splits, c->rps, c->ncolp, s);
   };
   ms[4] = 0.0;
@@ -497,6 +650,10 @@ extern "C" int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, con
   if (out->mem != POGS_HOST && out->mem != POGS_DEVICE) return POGS_EINVAL;
   pogs_params p = params ? *params : ctx->params;
   if (check_params(p)) return POGS_EINVAL;
+  if (ctx->sparse) {  // a sparse context always projects by CGLS; no warm start
+    p.projection = POGS_PROJ_CGLS;
+    if (x0 || nu0) return POGS_EUNSUPPORTED;
+  }
   // a context set up for CGLS has no factor for the direct projection; the
   // CGLS state does not keep x~ and y~ for the gap test
   if (p.projection == POGS_PROJ_DIRECT && ctx->proj != POGS_PROJ_DIRECT) return POGS_EUNSUPPORTED;

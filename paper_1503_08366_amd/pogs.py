@@ -83,6 +83,9 @@ _SIGS = {
     "pogs_params_default": (C.c_int, [C.POINTER(pogs_params)]),
     "pogs_init": (C.c_int, [C.POINTER(C.c_void_p), C.c_int64, C.c_int64, C.c_void_p, C.c_int, C.c_int,
                             C.c_int64, C.c_int, C.POINTER(pogs_params), C.c_void_p]),
+    "pogs_init_sparse": (C.c_int, [C.POINTER(C.c_void_p), C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.POINTER(pogs_params),
+                                   C.c_void_p]),
     "pogs_solve": (C.c_int, [C.c_void_p, C.POINTER(pogs_fn), C.POINTER(pogs_fn), C.POINTER(pogs_params),
                              C.c_void_p, C.c_void_p, C.POINTER(pogs_result)]),
     "pogs_solve_path": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(pogs_fn), C.POINTER(pogs_fn),
@@ -438,6 +441,51 @@ class Context:
                                    x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p), POGS_HOST),
                "pogs_project")
         return x, y
+
+
+
+class SparseContext(Context):
+    """A pogs_ctx on a sparse matrix in compressed rows (pogs_init_sparse).
+
+    ``A`` is anything with ``indptr``, ``indices``, ``data`` and ``shape``
+    (a SciPy CSR matrix, or a torch sparse CSR tensor on the device for
+    device input).  Solves project by CGLS."""
+
+    def __init__(self, A, params: Optional[pogs_params] = None, stream=None):
+        lib = _lib()
+        if _is_torch(A):
+            import torch
+            rp = A.crow_indices().to(torch.int64).contiguous()
+            ci = A.col_indices().to(torch.int32).contiguous()
+            va = A.values().contiguous()
+            keep = (rp, ci, va)
+            ptrs = (rp.data_ptr(), ci.data_ptr(), va.data_ptr())
+            mem = POGS_DEVICE
+            dt = _dtype_code(va)
+            if stream is None:
+                stream = torch.cuda.current_stream()
+        else:
+            rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+            ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+            va = np.ascontiguousarray(A.data)
+            if va.dtype not in (np.float32, np.float64):
+                va = va.astype(np.float64)
+            keep = (rp, ci, va)
+            ptrs = (rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+            mem = POGS_HOST
+            dt = POGS_F32 if va.dtype == np.float32 else POGS_F64
+        m, n = int(A.shape[0]), int(A.shape[1])
+        self.dtype = dt
+        self.m, self.n = m, n
+        self.stream = stream
+        self.projection = PROJECTIONS["cgls"]
+        self.nnz = int(len(keep[1]))
+        handle = C.c_void_p()
+        rc = lib.pogs_init_sparse(C.byref(handle), m, n, self.nnz, C.c_void_p(ptrs[0]), C.c_void_p(ptrs[1]),
+                                  C.c_void_p(ptrs[2]), dt, mem, C.byref(params) if params is not None else None,
+                                  _stream_handle(stream))
+        _check(rc, "pogs_init_sparse")
+        self.handle = handle
 
 
 def _problem_struct(p, params: Optional[pogs_params], keep: list) -> pogs_problem:

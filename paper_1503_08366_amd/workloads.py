@@ -316,6 +316,58 @@ def portfolio(k: int, n: int, seed: int, dtype=np.float32, gamma: float = 1.0,
                          "seed": seed})
 
 
+def sparse_matrix(m: int, n: int, k: int, rng: np.random.Generator, dtype=np.float32):
+    """m x n matrix in compressed rows (SciPy CSR) with exactly min(k, n)
+    entries per row at distinct uniformly drawn columns, values N(0, 1/k)."""
+    import scipy.sparse as sp
+    k = min(k, n)
+    cols = np.empty((m, k), dtype=np.int64)
+    for i in range(m):
+        cols[i] = rng.choice(n, size=k, replace=False)
+    cols.sort(axis=1)
+    vals = (rng.standard_normal((m, k)) / math.sqrt(k)).astype(dtype)
+    indptr = np.arange(0, m * k + 1, k, dtype=np.int64)
+    return sp.csr_matrix((vals.ravel(), cols.ravel(), indptr), shape=(m, n))
+
+
+def sparse_problem(kind: str, m: int, n: int, k: int, seed: int, dtype=np.float32,
+                   max_iter: int = 10000) -> Problem:
+    """A problem of the given kind (lasso, nnls, logistic, lp) on a sparse A
+    with k entries per row (sparse_matrix); the functions follow the dense
+    generators' recipes with A^T b etc. formed from the rounded sparse A.
+    ``Problem.A`` is the SciPy CSR matrix."""
+    rng = np.random.default_rng(seed)
+    A = sparse_matrix(m, n, k, rng, dtype)
+    A64 = A.astype(np.float64)
+    if kind in ("lasso", "nnls"):
+        x_true = _sparse_truth(rng, n, 0.1)
+        b = A64 @ x_true + 0.01 * rng.standard_normal(m)
+        f = Fn("square", m, a=1.0, b=b, c=1.0)
+        if kind == "lasso":
+            g = Fn("abs", n, c=0.1 * float(np.max(np.abs(A64.T @ b))))
+        else:
+            g = Fn("ind_ge0", n)
+        meta = {"b": b}
+    elif kind == "logistic":
+        x_true = _sparse_truth(rng, n, 0.1)
+        sgn = np.sign(A64 @ x_true + 0.01 * rng.standard_normal(m))
+        sgn[sgn == 0] = 1.0
+        b01 = 0.5 * (1.0 + sgn)
+        f = Fn("logistic", m, d=-b01)
+        g = Fn("abs", n, c=0.1 * float(np.max(np.abs(A64.T @ (0.5 - b01)))))
+        meta = {"labels01": b01}
+    elif kind == "lp":
+        v = rng.random(n)
+        b = A64 @ v + rng.uniform(0.0, 0.1, m)
+        f = Fn("ind_le0", m, b=b)
+        g = Fn("ind_box01", n, d=rng.random(n))
+        meta = {"b": b}
+    else:
+        raise ValueError(kind)
+    meta.update({"seed": seed, "nnz_per_row": k})
+    return Problem(f"sparse_{kind}", A, f, g, max_iter=max_iter, meta=meta)
+
+
 # ---------------------------------------------------------------------------
 # Named benchmark workloads
 # ---------------------------------------------------------------------------

@@ -116,3 +116,34 @@ def test_batch_rejects_null(lib):
     from paper_1503_08366_amd import pogs
     assert lib.pogs_batch_submit(None, None, None) in (pogs.POGS_EINVAL, pogs.POGS_EUNSUPPORTED)
     assert lib.pogs_batch_destroy(None) == pogs.POGS_OK
+
+
+def test_init_sparse_rejects_bad_inputs_without_device(lib):
+    """Every check of pogs_init_sparse on host input runs before any device
+    call: malformed row pointers, column indices out of range, non-finite
+    values, bad sizes and parameters."""
+    from paper_1503_08366_amd import pogs
+    E = pogs.POGS_EINVAL
+    h = C.c_void_p()
+
+    def call(m, n, rp, ci, va, dt=pogs.POGS_F64, prm=None):
+        rp = np.ascontiguousarray(rp, dtype=np.int64)
+        ci = np.ascontiguousarray(ci, dtype=np.int32)
+        va = np.ascontiguousarray(va, dtype=np.float64 if dt == pogs.POGS_F64 else np.float32)
+        return lib.pogs_init_sparse(C.byref(h), m, n, len(ci), C.c_void_p(rp.ctypes.data),
+                                    C.c_void_p(ci.ctypes.data), C.c_void_p(va.ctypes.data), dt, pogs.POGS_HOST,
+                                    C.byref(prm) if prm is not None else None, None)
+
+    good_rp, good_ci, good_va = [0, 2, 3], [0, 2, 1], [1.0, 2.0, 3.0]
+    assert call(2, 3, [1, 2, 3], good_ci, good_va) == E           # rowptr[0] != 0
+    assert call(2, 3, [0, 2, 2], good_ci, good_va) == E           # rowptr[m] != nnz
+    assert call(2, 3, [0, 3, 2], good_ci, good_va) == E           # decreasing
+    assert call(2, 3, good_rp, [0, 3, 1], good_va) == E           # column index = n
+    assert call(2, 3, good_rp, [0, -1, 1], good_va) == E          # negative column index
+    assert call(2, 3, good_rp, good_ci, [1.0, np.nan, 3.0]) == E  # non-finite value
+    assert call(2, 3, good_rp, good_ci, [1.0, np.inf, 3.0], dt=pogs.POGS_F32) == E
+    assert call(0, 3, [0], [], []) == E                           # m = 0
+    assert call(2, 3, good_rp, good_ci, good_va, dt=9) == E       # dtype
+    assert call(2, 3, good_rp, good_ci, good_va, prm=pogs.default_params(cg_max_iter=0)) == E
+    assert lib.pogs_init_sparse(None, 2, 3, 3, None, None, None, 1, 0, None, None) == E
+    assert h.value is None

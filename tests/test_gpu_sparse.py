@@ -1,0 +1,104 @@
+"""GPU tests of sparse A (compressed rows, pogs_init_sparse) with the CGLS
+projection, through the C ABI, against the FP64 oracle on the same matrix
+(densified: the method does not depend on the storage).
+
+Tolerances: D, E relative 1e-10 (both sides accumulate in float64 from the
+same values); objective |p - p_oracle| <= 1e-3 max(|p_oracle|, 1); float64
+runs stop within one iteration of the oracle's.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import pogs_oracle as O
+from paper_1503_08366_amd import pogs as P
+from paper_1503_08366_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EPS = {np.float32: float(np.finfo(np.float32).eps), np.float64: float(np.finfo(np.float64).eps)}
+
+
+def _dense(A):
+    return np.asarray(A.toarray(), dtype=np.float64)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+@pytest.mark.parametrize("shape,k", [((500, 120), 6), ((120, 400), 30), ((3000, 700), 40)])
+def test_sparse_equilibration_parity(shape, k, dt):
+    p = W.sparse_problem("lasso", *shape, k, seed=shape[0] + k, dtype=dt)
+    with P.SparseContext(p.A) as ctx:
+        D, E = ctx.scaling()
+    Dr, Er = O.equilibrate(_dense(p.A), EPS[dt], 10)
+    np.testing.assert_allclose(D, Dr, rtol=1e-10)
+    np.testing.assert_allclose(E, Er, rtol=1e-10)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+@pytest.mark.parametrize("kind,shape,k", [
+    ("lasso", (600, 150), 10), ("lasso", (150, 500), 40), ("nnls", (500, 100), 8),
+    ("logistic", (800, 120), 12), ("lp", (200, 60), 10), ("lasso", (5000, 1200), 3),
+])
+def test_sparse_solve_matches_oracle(kind, shape, k, dt):
+    p = W.sparse_problem(kind, *shape, k, seed=7 * shape[0] + k, dtype=dt)
+    with P.SparseContext(p.A) as ctx:
+        r = ctx.solve(p.f, p.g)
+    ref = O.solve(_dense(p.A), p.f, p.g, O.Params(eps_cmp=EPS[dt], projection="cgls"))
+    assert ref.converged and r.status == P.POGS_CONVERGED, (r, ref.iters)
+    tol = 1e-3 * max(abs(ref.optval), 1.0)
+    assert abs(r.optval - ref.optval) <= tol, (r.optval, ref.optval, r.iters, ref.iters)
+    if dt == np.float64:
+        assert abs(r.iters - ref.iters) <= 1, (r.iters, ref.iters)
+    print(f"{kind} {shape} k={k} {np.dtype(dt).name}: iters {r.iters} (oracle {ref.iters}), "
+          f"CG steps {r.cg_steps} (oracle {ref.cg_steps})")
+
+
+def test_sparse_with_empty_rows_and_columns():
+    """Rows and columns without entries (a zero row of A, an unused variable)."""
+    rng = np.random.default_rng(3)
+    A = W.sparse_matrix(300, 90, 5, rng, np.float64).tolil()
+    A[17, :] = 0.0
+    A[200:210, :] = 0.0
+    A[:, 40] = 0.0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    b = rng.normal(size=300)
+    f = W.Fn("square", 300, b=b)
+    g = W.Fn("abs", 90, c=0.05)
+    with P.SparseContext(A) as ctx:
+        r = ctx.solve(f, g)
+    ref = O.solve(_dense(A), f, g, O.Params(eps_cmp=EPS[np.float64], projection="cgls"))
+    assert r.converged and ref.converged
+    assert abs(r.optval - ref.optval) <= 1e-3 * max(1.0, abs(ref.optval))
+    assert abs(r.x[40]) < 1e-8  # unused variable under an l1 penalty stays at 0
+
+
+def test_sparse_matches_dense_cgls_on_gpu():
+    p = W.sparse_problem("lasso", 2000, 500, 20, seed=11)
+    with P.SparseContext(p.A) as ctx:
+        rs = ctx.solve(p.f, p.g)
+    with P.Context(np.ascontiguousarray(p.A.toarray()), P.default_params(projection="cgls")) as ctx:
+        rd = ctx.solve(p.f, p.g, P.default_params(projection="cgls"))
+    assert rs.converged and rd.converged
+    assert abs(rs.optval - rd.optval) <= 1e-3 * max(1.0, abs(rd.optval))
+    assert abs(rs.iters - rd.iters) <= max(2, rd.iters // 20), (rs.iters, rd.iters)
+
+
+def test_sparse_device_input_and_rejections():
+    import torch
+    p = W.sparse_problem("lasso", 400, 100, 8, seed=12)
+    A = p.A
+    At = torch.sparse_csr_tensor(torch.from_numpy(A.indptr.astype(np.int64)), torch.from_numpy(A.indices.astype(np.int32)),
+                                 torch.from_numpy(A.data), size=A.shape, device="cuda")
+    with P.SparseContext(A) as c_host, P.SparseContext(At) as c_dev:
+        r1 = c_host.solve(p.f, p.g)
+        r2 = c_dev.solve(p.f, p.g)
+        assert r1.converged and r2.converged
+        assert r1.iters == r2.iters and abs(r1.optval - r2.optval) <= 1e-12 * max(1.0, abs(r1.optval))
+        for call in (lambda: c_host.solve(p.f, p.g, x0=np.zeros(100, np.float32)),
+                     lambda: c_host.solve(p.f, p.g, P.default_params(stop_rule="gap")),
+                     lambda: c_host.project(np.zeros(100, np.float32), np.zeros(400, np.float32)),
+                     lambda: c_host.solve_path([p.f], [p.g])):
+            with pytest.raises(P.PogsError) as ei:
+                call()
+            assert ei.value.code == P.POGS_EUNSUPPORTED
