@@ -317,17 +317,17 @@ def portfolio(k: int, n: int, seed: int, dtype=np.float32, gamma: float = 1.0,
 
 
 def sparse_matrix(m: int, n: int, k: int, rng: np.random.Generator, dtype=np.float32):
-    """m x n matrix in compressed rows (SciPy CSR) with exactly min(k, n)
-    entries per row at distinct uniformly drawn columns, values N(0, 1/k)."""
+    """m x n matrix in compressed rows (SciPy CSR): each row draws k column
+    indices uniformly with replacement and values N(0, 1/k); repeated columns
+    of a row are merged (summed), so a row has at most k entries, sorted."""
     import scipy.sparse as sp
     k = min(k, n)
-    cols = np.empty((m, k), dtype=np.int64)
-    for i in range(m):
-        cols[i] = rng.choice(n, size=k, replace=False)
-    cols.sort(axis=1)
-    vals = (rng.standard_normal((m, k)) / math.sqrt(k)).astype(dtype)
+    cols = rng.integers(0, n, size=(m, k), dtype=np.int64)
+    vals = rng.standard_normal((m, k)) / math.sqrt(k)
     indptr = np.arange(0, m * k + 1, k, dtype=np.int64)
-    return sp.csr_matrix((vals.ravel(), cols.ravel(), indptr), shape=(m, n))
+    A = sp.csr_matrix((vals.ravel(), cols.ravel(), indptr), shape=(m, n))
+    A.sum_duplicates()
+    return A.astype(dtype)
 
 
 def sparse_problem(kind: str, m: int, n: int, k: int, seed: int, dtype=np.float32,
