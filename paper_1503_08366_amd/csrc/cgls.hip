@@ -44,47 +44,56 @@ __global__ __launch_bounds__(kBlock) void cg_finish_kernel(IterArgs<T> p, int j,
   gemv_t_finish_body<2, EpiCgStep<T>>(hw_block(), p.n, splits, p.part, ncolp, e);
 }
 
-template <int NC>
+template <int NC, bool NT>
 __global__ __launch_bounds__(kBlock) void cg_rows_f32_kernel(IterArgs<float> p, int j, int cap) {
   EpiCgRows<float> e;
   if (!cg_rows_enter<float>(p, j, cap, &e)) return;
-  gemv_n_rows_body<1, NC, EpiCgRows<float>>(hw_block(), p.A, p.m, p.n, p.ld, p.sv, p.sv, e);
+  gemv_n_rows_body<1, NC, EpiCgRows<float>, NT>(hw_block(), p.A, p.m, p.n, p.ld, p.sv, p.sv, e);
 }
 
-template <typename T, int LPR, int RPT>
+template <typename T, int LPR, int RPT, bool NT>
 __global__ __launch_bounds__(kBlock) void cg_rows_lds_kernel(IterArgs<T> p, int j, int cap) {
   EpiCgRows<T> e;
   if (!cg_rows_enter<T>(p, j, cap, &e)) return;
-  gemv_n_body<T, T, 1, false, LPR, RPT, EpiCgRows<T>>(hw_block(), p.A, p.m, p.n, p.ld, p.sv, p.sv, e);
+  gemv_n_body<T, T, 1, false, LPR, RPT, EpiCgRows<T>, NT>(hw_block(), p.A, p.m, p.n, p.ld, p.sv, p.sv, e);
 }
 
-template <typename T> static void launch_cg_rows(const IterArgs<T> &p, int j, int cap, hipStream_t s) {
+template <typename T, bool NT> static void launch_cg_rows_nt(const IterArgs<T> &p, int j, int cap, hipStream_t s) {
   const GemvNShape sh = gemv_n_shape(p.m, p.n, p.ld, sizeof(T));
   const dim3 grid(sh.grid), block(kBlock);
   if constexpr (sizeof(T) == 4) {
     switch (sh.variant) {
-      case GEMV_N_ROWS1: hipLaunchKernelGGL(cg_rows_f32_kernel<1>, grid, block, 0, s, p, j, cap); return;
-      case GEMV_N_ROWS2: hipLaunchKernelGGL(cg_rows_f32_kernel<2>, grid, block, 0, s, p, j, cap); return;
-      case GEMV_N_ROWS4: hipLaunchKernelGGL(cg_rows_f32_kernel<4>, grid, block, 0, s, p, j, cap); return;
-      case GEMV_N_ROWS8: hipLaunchKernelGGL(cg_rows_f32_kernel<8>, grid, block, 0, s, p, j, cap); return;
+      case GEMV_N_ROWS1: hipLaunchKernelGGL((cg_rows_f32_kernel<1, NT>), grid, block, 0, s, p, j, cap); return;
+      case GEMV_N_ROWS2: hipLaunchKernelGGL((cg_rows_f32_kernel<2, NT>), grid, block, 0, s, p, j, cap); return;
+      case GEMV_N_ROWS4: hipLaunchKernelGGL((cg_rows_f32_kernel<4, NT>), grid, block, 0, s, p, j, cap); return;
+      case GEMV_N_ROWS8: hipLaunchKernelGGL((cg_rows_f32_kernel<8, NT>), grid, block, 0, s, p, j, cap); return;
       default: break;
     }
   }
   switch (sh.variant) {
-    case GEMV_N_L64R4: hipLaunchKernelGGL((cg_rows_lds_kernel<T, 64, 4>), grid, block, 0, s, p, j, cap); break;
-    case GEMV_N_L64R1: hipLaunchKernelGGL((cg_rows_lds_kernel<T, 64, 1>), grid, block, 0, s, p, j, cap); break;
-    case GEMV_N_L16R4: hipLaunchKernelGGL((cg_rows_lds_kernel<T, 16, 4>), grid, block, 0, s, p, j, cap); break;
-    default: hipLaunchKernelGGL((cg_rows_lds_kernel<T, 16, 1>), grid, block, 0, s, p, j, cap); break;
+    case GEMV_N_L64R4: hipLaunchKernelGGL((cg_rows_lds_kernel<T, 64, 4, NT>), grid, block, 0, s, p, j, cap); break;
+    case GEMV_N_L64R1: hipLaunchKernelGGL((cg_rows_lds_kernel<T, 64, 1, NT>), grid, block, 0, s, p, j, cap); break;
+    case GEMV_N_L16R4: hipLaunchKernelGGL((cg_rows_lds_kernel<T, 16, 4, NT>), grid, block, 0, s, p, j, cap); break;
+    default: hipLaunchKernelGGL((cg_rows_lds_kernel<T, 16, 1, NT>), grid, block, 0, s, p, j, cap); break;
   }
+}
+
+template <typename T> static void launch_cg_rows(const IterArgs<T> &p, int j, int cap, hipStream_t s) {
+  if (p.stream_a) launch_cg_rows_nt<T, true>(p, j, cap, s);
+  else launch_cg_rows_nt<T, false>(p, j, cap, s);
 }
 
 template <typename T> static void launch_first(const IterArgs<T> &p, int splits, int rps, int ncolp, hipStream_t s) {
   EpiCgStart<T> e0{{p}};
-  gemv_n<T, T, 1>(p.A, p.m, p.n, p.ld, p.x, p.x, e0, s);
+  gemv_n<T, T, 1>(p.A, p.m, p.n, p.ld, p.x, p.x, e0, s, p.stream_a);
   const int tiles = (int)cdiv(p.n, gemv_t_tile(sizeof(T)));
   EpiBase<T> eb{p};
-  hipLaunchKernelGGL((gemv_t_kernel<T, T, 2, false, EpiBase<T>>), dim3(tiles, splits), dim3(kBlock), 0, s, p.A, p.m,
-                     p.n, p.ld, (const T *)p.yt, (const T *)p.nu, rps, p.part, ncolp, eb);
+  if (p.stream_a)
+    hipLaunchKernelGGL((gemv_t_kernel<T, T, 2, false, EpiBase<T>, true>), dim3(tiles, splits), dim3(kBlock), 0, s, p.A,
+                       p.m, p.n, p.ld, (const T *)p.yt, (const T *)p.nu, rps, p.part, ncolp, eb);
+  else
+    hipLaunchKernelGGL((gemv_t_kernel<T, T, 2, false, EpiBase<T>, false>), dim3(tiles, splits), dim3(kBlock), 0, s,
+                       p.A, p.m, p.n, p.ld, (const T *)p.yt, (const T *)p.nu, rps, p.part, ncolp, eb);
   hipLaunchKernelGGL(cg_first_finish_kernel<T>, dim3(cdiv(p.n, kFinishCols)), dim3(kBlock), 0, s, p, splits, ncolp);
 }
 
@@ -93,8 +102,12 @@ template <typename T> static void launch_step(const IterArgs<T> &p, int j, int c
   launch_cg_rows<T>(p, j, cap, s);
   const int tiles = (int)cdiv(p.n, gemv_t_tile(sizeof(T)));
   EpiCgSkip<T> ek{p};
-  hipLaunchKernelGGL((gemv_t_kernel<T, T, 2, false, EpiCgSkip<T>>), dim3(tiles, splits), dim3(kBlock), 0, s, p.A,
-                     p.m, p.n, p.ld, (const T *)p.yt, (const T *)p.qv, rps, p.part, ncolp, ek);
+  if (p.stream_a)
+    hipLaunchKernelGGL((gemv_t_kernel<T, T, 2, false, EpiCgSkip<T>, true>), dim3(tiles, splits), dim3(kBlock), 0, s,
+                       p.A, p.m, p.n, p.ld, (const T *)p.yt, (const T *)p.qv, rps, p.part, ncolp, ek);
+  else
+    hipLaunchKernelGGL((gemv_t_kernel<T, T, 2, false, EpiCgSkip<T>, false>), dim3(tiles, splits), dim3(kBlock), 0, s,
+                       p.A, p.m, p.n, p.ld, (const T *)p.yt, (const T *)p.qv, rps, p.part, ncolp, ek);
   hipLaunchKernelGGL(cg_finish_kernel<T>, dim3(cdiv(p.n, kFinishCols)), dim3(kBlock), 0, s, p, j, splits, ncolp);
 }
 

@@ -241,6 +241,7 @@ struct pogs_ctx {
     p.n_pri = n_pri;
     p.n_dual = n_dual;
     p.ctrl = ctrl;
+    p.stream_a = (size_t)m * ld * sizeof(T) > kStreamMatrixBytes ? 1 : 0;
     p.pv = vecp<T>(15);
     p.qv = vecp<T>(16);
     p.sv = vecp<T>(17);

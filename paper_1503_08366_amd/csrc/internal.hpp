@@ -66,6 +66,11 @@ template <typename T> struct Csr {
   int rows, lpr, grid;
 };
 
+// A matrix larger than this is streamed with non-temporal loads in the
+// passes of an iteration (the MI355X last-level cache holds 256 MB; below
+// this size A partly stays cached from one pass to the next).
+constexpr size_t kStreamMatrixBytes = (size_t)192 << 20;
+
 // Everything one iteration of the single-problem pipeline touches.
 template <typename T> struct IterArgs {
   int m, n, ld;          // scaled matrix A^ (row-major, leading dim ld)
@@ -94,6 +99,7 @@ template <typename T> struct IterArgs {
   double *s_gobj, *s_gconj;
   // sparse contexts only: A^ and A^T in compressed rows
   Csr<T> sa, sat;
+  int stream_a;          // 1: the passes over A use non-temporal loads
 };
 
 // ---- launchers (setup.hip) ------------------------------------------------

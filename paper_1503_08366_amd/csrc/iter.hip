@@ -167,10 +167,10 @@ void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps,
     case 1:
       if (tall) {
         EpiTallPass1<T> e{{p}};
-        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.dy, p.nu, splits, rps, p.part, ncolp, e, s);
+        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.dy, p.nu, splits, rps, p.part, ncolp, e, s, p.stream_a);
       } else {
         EpiWidePass1<T> e{{p}};
-        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.cx, p.xh, e, s);
+        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.cx, p.xh, e, s, p.stream_a);
       }
       break;
     case 2:
@@ -185,10 +185,10 @@ void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps,
     default:
       if (tall) {
         EpiTallPass2<T> e{{p}};
-        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.x, p.xh, e, s);
+        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.x, p.xh, e, s, p.stream_a);
       } else {
         EpiWidePass2<T> e{{p}};
-        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.yt, p.nu, splits, rps, p.part, ncolp, e, s);
+        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.yt, p.nu, splits, rps, p.part, ncolp, e, s, p.stream_a);
       }
       break;
   }
