@@ -168,6 +168,7 @@ struct pogs_ctx {
   int *sp_rp = nullptr, *sp_ci = nullptr, *sp_rpt = nullptr, *sp_cit = nullptr;
   void *sp_va = nullptr, *sp_vat = nullptr;
   int sp_lpr = 0, sp_grid = 0, sp_lprt = 0, sp_gridt = 0;
+  void *sp_pair = nullptr;  // 2 m entries of T
   double *D = nullptr, *E = nullptr;
   // iteration state (T): x y xt yt xh yh mu nu cx dy rhs, outputs xo yo muo nuo
   void *vec = nullptr;
@@ -253,6 +254,7 @@ struct pogs_ctx {
     if (sparse) {
       p.sa = Csr<T>{sp_rp, sp_ci, (T *)sp_va, (int)m, sp_lpr, sp_grid};
       p.sat = Csr<T>{sp_rpt, sp_cit, (T *)sp_vat, (int)n, sp_lprt, sp_gridt};
+      p.pair = (T *)sp_pair;
     }
     return p;
   }

@@ -97,8 +97,11 @@ template <typename T> struct IterArgs {
   // gap rule only: per prox-block partial sums of f^(y) + g^(x) and of
   // f^*(-rho y~) + g^*(-rho x~) for the state entering the prox step
   double *s_gobj, *s_gconj;
-  // sparse contexts only: A^ and A^T in compressed rows
+  // sparse contexts only: A^ and A^T in compressed rows, and the two vectors
+  // the pass over A^T gathers kept interleaved (2 m entries: (r1, nu_h) for
+  // the first pass, (r1, q) for the CG steps), one gather per entry
   Csr<T> sa, sat;
+  T *pair;
   int stream_a;          // 1: the passes over A use non-temporal loads
 };
 

@@ -324,6 +324,7 @@ template <typename T> int init_sparse_impl(pogs_ctx *c, const HostCsr &a, const 
   if ((rc = c->arena.alloc((void **)&c->sp_cit, std::max<size_t>(nnz, 1) * 4))) return rc;
   if ((rc = c->arena.alloc(&c->sp_va, std::max<size_t>(nnz, 1) * sizeof(T)))) return rc;
   if ((rc = c->arena.alloc(&c->sp_vat, std::max<size_t>(nnz, 1) * sizeof(T)))) return rc;
+  if ((rc = c->arena.alloc(&c->sp_pair, (size_t)2 * m * sizeof(T)))) return rc;
   std::vector<T> va(a.va.begin(), a.va.end()), vat(t.va.begin(), t.va.end());
   POGS_HIP_TRY(hipMemcpyAsync(c->sp_rp, a.rp.data(), a.rp.size() * 4, hipMemcpyHostToDevice, s));
   POGS_HIP_TRY(hipMemcpyAsync(c->sp_rpt, t.rp.data(), t.rp.size() * 4, hipMemcpyHostToDevice, s));

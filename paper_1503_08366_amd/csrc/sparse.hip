@@ -29,10 +29,12 @@ __device__ inline void acc_add(Sum2 &a, const Sum2 &b) {
 }
 
 // Epilogue interface: R row(int i, double s0, double s1) with R double or
-// Sum2, and block_done(int block, R sum) in thread 0.
-template <int LPR, int NRHS, bool SQUARE, typename T, typename TV, class Epi>
+// Sum2, and block_done(int block, R sum) in thread 0.  PAIRED: the two
+// right-hand sides are interleaved in v0 (v0[2j], v0[2j + 1]).
+template <int LPR, int NRHS, bool SQUARE, typename T, typename TV, class Epi, bool PAIRED = false>
 __device__ __forceinline__ void spmv_body(const Csr<T> &A, const TV *__restrict__ v0, const TV *__restrict__ v1,
                                           const Epi &epi) {
+  typedef TV TV2 __attribute__((ext_vector_type(2)));
   constexpr int G = kBlock / LPR;
   __shared__ double bs[kBlock / kWave];
   const int grp = threadIdx.x / LPR, sub = threadIdx.x % LPR;
@@ -45,8 +47,14 @@ __device__ __forceinline__ void spmv_body(const Csr<T> &A, const TV *__restrict_
       double a = (double)A.va[k];
       if constexpr (SQUARE) a *= a;
       const int j = A.ci[k];
-      s0 = fma(a, (double)v0[j], s0);
-      if constexpr (NRHS > 1) s1 = fma(a, (double)v1[j], s1);
+      if constexpr (PAIRED) {
+        const TV2 v = reinterpret_cast<const TV2 *>(v0)[j];
+        s0 = fma(a, (double)v.x, s0);
+        s1 = fma(a, (double)v.y, s1);
+      } else {
+        s0 = fma(a, (double)v0[j], s0);
+        if constexpr (NRHS > 1) s1 = fma(a, (double)v1[j], s1);
+      }
     }
     s0 = group_sum<LPR>(s0);
     if constexpr (NRHS > 1) s1 = group_sum<LPR>(s1);
@@ -160,12 +168,48 @@ void run_equilibrate_sparse(Csr<T> A, Csr<T> At, int m, int n, int iters, double
 // ---------------------------------------------------------------------------
 // CGLS iteration
 // ---------------------------------------------------------------------------
-// C0: t = A^ x_h -> r1 = d - t, primal residual sums
+// C0: t = A^ x_h -> r1 = d - t, primal residual sums (the dense epilogue's
+// arithmetic), and the pair (r1, nu_h) for the pass over A^T
+template <typename T> struct EpiSpStart : EpiBase<T> {
+  __device__ double row(int i, double t, double) const {
+    const IterArgs<T> &p = this->p;
+    const T r1 = (T)((double)p.dy[i] - t);
+    p.yt[i] = r1;
+    p.pair[2 * (size_t)i] = r1;
+    p.pair[2 * (size_t)i + 1] = p.nu[i];
+    const double r = t - (double)p.yh[i];
+    return r * r;
+  }
+  __device__ void block_done(int b, double v) const { this->p.s_pri[b] = v; }
+};
+
+// KA: the arithmetic of EpiCgRows, and the pair (r1, q_j)
+template <typename T> struct EpiSpRows {
+  EpiCgRows<T> c;
+  __device__ double row(int i, double as, double) const {
+    const IterArgs<T> &p = c.p;
+    T r1 = p.yt[i];
+    double qn = as;
+    if (c.has_prev) {
+      const double qo = (double)p.qv[i];
+      r1 = (T)((double)r1 - c.alpha_prev * qo);
+      p.yt[i] = r1;
+      qn = as + c.beta * qo;
+    }
+    const T qt = (T)qn;
+    p.qv[i] = qt;
+    p.pair[2 * (size_t)i] = r1;
+    p.pair[2 * (size_t)i + 1] = qt;
+    return (double)qt * (double)qt;
+  }
+  __device__ void block_done(int b, double v) const { c.p.s_qq[b] = v; }
+};
+
 template <int LPR, typename T>
 __global__ __launch_bounds__(kBlock) void sp_start_kernel(IterArgs<T> p) {
-  EpiCgStart<T> e{{p}};
+  EpiSpStart<T> e{{p}};
   if (e.skip()) return;
-  spmv_body<LPR, 1, false, T, T, EpiCgStart<T>>(p.sa, p.x, p.x, e);
+  spmv_body<LPR, 1, false, T, T, EpiSpStart<T>>(p.sa, p.x, p.x, e);
 }
 
 // C1 with its finish: s_0 = A^T r1 + c - x, dual residual sums, ||s_0||^2
@@ -173,15 +217,15 @@ template <int LPR, typename T>
 __global__ __launch_bounds__(kBlock) void sp_first_kernel(IterArgs<T> p) {
   if (!cg_first_enter<T>(p)) return;
   ColRows<EpiCgFirst<T>> e{EpiCgFirst<T>{p}};
-  spmv_body<LPR, 2, false, T, T, ColRows<EpiCgFirst<T>>>(p.sat, p.yt, p.nu, e);
+  spmv_body<LPR, 2, false, T, T, ColRows<EpiCgFirst<T>>, true>(p.sat, p.pair, p.pair, e);
 }
 
 // KA: q_j = A^ s_j + beta q_{j-1}, pending r1 update
 template <int LPR, typename T>
 __global__ __launch_bounds__(kBlock) void sp_rows_kernel(IterArgs<T> p, int j, int cap) {
-  EpiCgRows<T> e;
-  if (!cg_rows_enter<T>(p, j, cap, &e)) return;
-  spmv_body<LPR, 1, false, T, T, EpiCgRows<T>>(p.sa, p.sv, p.sv, e);
+  EpiSpRows<T> e;
+  if (!cg_rows_enter<T>(p, j, cap, &e.c)) return;
+  spmv_body<LPR, 1, false, T, T, EpiSpRows<T>>(p.sa, p.sv, p.sv, e);
 }
 
 // KB and KC together: A^T [r1, q_j] on the rows of A^T, then p_j, x, s_{j+1}
@@ -190,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void sp_step_kernel(IterArgs<T> p, int j) {
   EpiCgStep<T> e;
   if (!cg_step_enter<T>(p, j, &e)) return;
   ColRows<EpiCgStep<T>> c{e};
-  spmv_body<LPR, 2, false, T, T, ColRows<EpiCgStep<T>>>(p.sat, p.yt, p.qv, c);
+  spmv_body<LPR, 2, false, T, T, ColRows<EpiCgStep<T>>, true>(p.sat, p.pair, p.pair, c);
 }
 
 #define POGS_SP_DISPATCH(lpr, KERNEL, grid, s, ...)                                                        \
