@@ -136,6 +136,13 @@ typedef struct {
   int32_t cg_max_iter;   /* CGLS steps per projection at most, 1..1000, default 10 */
   double cg_tol;         /* CGLS stops when rho ||s|| <= cg_tol * eps_dual, default 0.1 */
   int32_t stop_rule;     /* POGS_STOP_RESIDUAL (default) or POGS_STOP_GAP */
+  int32_t autotune;      /* 1 (default): pogs_init times the load policy of the
+                            passes over A (cached or non-temporal loads, for the
+                            row passes and the column passes) on the projection
+                            (pass 1, solve, pass 2) of the context's shape and
+                            keeps the fastest; the choice is cached per
+                            (m, n, dtype) in the process and changes no result
+                            bit.  0: a matrix above 192 MB streams, others cache. */
 } pogs_params;
 
 /* Result of a solve: the half-step tuple (x, y, mu, nu) of the last iteration,

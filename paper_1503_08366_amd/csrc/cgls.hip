@@ -79,16 +79,16 @@ template <typename T, bool NT> static void launch_cg_rows_nt(const IterArgs<T> &
 }
 
 template <typename T> static void launch_cg_rows(const IterArgs<T> &p, int j, int cap, hipStream_t s) {
-  if (p.stream_a) launch_cg_rows_nt<T, true>(p, j, cap, s);
+  if (p.nt_rows) launch_cg_rows_nt<T, true>(p, j, cap, s);
   else launch_cg_rows_nt<T, false>(p, j, cap, s);
 }
 
 template <typename T> static void launch_first(const IterArgs<T> &p, int splits, int rps, int ncolp, hipStream_t s) {
   EpiCgStart<T> e0{{p}};
-  gemv_n<T, T, 1>(p.A, p.m, p.n, p.ld, p.x, p.x, e0, s, p.stream_a);
+  gemv_n<T, T, 1>(p.A, p.m, p.n, p.ld, p.x, p.x, e0, s, p.nt_rows);
   const int tiles = (int)cdiv(p.n, gemv_t_tile(sizeof(T)));
   EpiBase<T> eb{p};
-  if (p.stream_a)
+  if (p.nt_cols)
     hipLaunchKernelGGL((gemv_t_kernel<T, T, 2, false, EpiBase<T>, true>), dim3(tiles, splits), dim3(kBlock), 0, s, p.A,
                        p.m, p.n, p.ld, (const T *)p.yt, (const T *)p.nu, rps, p.part, ncolp, eb);
   else
@@ -102,7 +102,7 @@ template <typename T> static void launch_step(const IterArgs<T> &p, int j, int c
   launch_cg_rows<T>(p, j, cap, s);
   const int tiles = (int)cdiv(p.n, gemv_t_tile(sizeof(T)));
   EpiCgSkip<T> ek{p};
-  if (p.stream_a)
+  if (p.nt_cols)
     hipLaunchKernelGGL((gemv_t_kernel<T, T, 2, false, EpiCgSkip<T>, true>), dim3(tiles, splits), dim3(kBlock), 0, s,
                        p.A, p.m, p.n, p.ld, (const T *)p.yt, (const T *)p.qv, rps, p.part, ncolp, ek);
   else

@@ -192,6 +192,7 @@ struct pogs_ctx {
   int graph_chunk = 0;
   int graph_cg_cap = 0;  // CGLS step cap of the captured graph (0: direct projection)
   int graph_gap = 0;     // the captured graph runs the gap test
+  int nt_rows = 0, nt_cols = 0;  // load policy of the passes over A (size rule or autotuned)
   bool solved = false;  // functions uploaded by a previous solve
 
   size_t esz() const { return dt == POGS_F32 ? 4 : 8; }
@@ -242,7 +243,8 @@ struct pogs_ctx {
     p.n_pri = n_pri;
     p.n_dual = n_dual;
     p.ctrl = ctrl;
-    p.stream_a = (size_t)m * ld * sizeof(T) > kStreamMatrixBytes ? 1 : 0;
+    p.nt_rows = nt_rows;
+    p.nt_cols = nt_cols;
     p.pv = vecp<T>(15);
     p.qv = vecp<T>(16);
     p.sv = vecp<T>(17);

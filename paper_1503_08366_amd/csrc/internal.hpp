@@ -66,9 +66,10 @@ template <typename T> struct Csr {
   int rows, lpr, grid;
 };
 
-// A matrix larger than this is streamed with non-temporal loads in the
-// passes of an iteration (the MI355X last-level cache holds 256 MB; below
-// this size A partly stays cached from one pass to the next).
+// Default load policy of the passes over A (when not tuned): a matrix larger
+// than this is streamed with non-temporal loads (the MI355X last-level cache
+// holds 256 MB; below this size A partly stays cached from one pass to the
+// next).
 constexpr size_t kStreamMatrixBytes = (size_t)192 << 20;
 
 // Everything one iteration of the single-problem pipeline touches.
@@ -102,7 +103,7 @@ template <typename T> struct IterArgs {
   // the first pass, (r1, q) for the CG steps), one gather per entry
   Csr<T> sa, sat;
   T *pair;
-  int stream_a;          // 1: the passes over A use non-temporal loads
+  int nt_rows, nt_cols;  // 1: the row passes (A v) / column passes (A^T v) over A load non-temporally
 };
 
 // ---- launchers (setup.hip) ------------------------------------------------

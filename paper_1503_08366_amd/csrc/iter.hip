@@ -167,13 +167,14 @@ void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps,
     case 1:
       if (tall) {
         EpiTallPass1<T> e{{p}};
-        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.dy, p.nu, splits, rps, p.part, ncolp, e, s, p.stream_a);
+        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.dy, p.nu, splits, rps, p.part, ncolp, e, s, p.nt_cols);
       } else {
         EpiWidePass1<T> e{{p}};
-        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.cx, p.xh, e, s, p.stream_a);
+        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.cx, p.xh, e, s, p.nt_rows);
       }
       break;
     case 2:
+      if (!p.Kinv) break;  // no factor (a context set up for CGLS): nothing to solve with
       if (tall) {
         EpiTallSolve<T> e{{p}};
         gemv_n<T, T, 1>(p.Kinv, p.q, p.q, p.ldk, p.rhs, p.rhs, e, s);
@@ -185,10 +186,10 @@ void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps,
     default:
       if (tall) {
         EpiTallPass2<T> e{{p}};
-        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.x, p.xh, e, s, p.stream_a);
+        gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.x, p.xh, e, s, p.nt_rows);
       } else {
         EpiWidePass2<T> e{{p}};
-        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.yt, p.nu, splits, rps, p.part, ncolp, e, s, p.stream_a);
+        gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.yt, p.nu, splits, rps, p.part, ncolp, e, s, p.nt_cols);
       }
       break;
   }

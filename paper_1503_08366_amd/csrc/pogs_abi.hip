@@ -6,6 +6,8 @@
 #include <cmath>
 #include <chrono>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -57,6 +59,7 @@ int pogs_params_default(pogs_params *p) {
   p->cg_max_iter = 10;
   p->cg_tol = 0.1;
   p->stop_rule = POGS_STOP_RESIDUAL;
+  p->autotune = 1;
   return POGS_OK;
 }
 
@@ -201,6 +204,82 @@ template <typename T> int alloc_iteration(pogs_ctx *c) {
   return POGS_OK;
 }
 
+// Load policy of the passes over A.  Default: stream (non-temporal loads) a
+// matrix larger than kStreamMatrixBytes.  With params.autotune the four
+// policies (row passes x column passes, cached or streamed) are timed on the
+// context: after one warm projection, four projections (pass 1, the solve with
+// K^-1, pass 2) each, in sequence so that what one pass leaves in the caches
+// for the next counts, with HIP events on the context's stream; the fastest is
+// kept, per (m, n, dtype) for the process.  The policy changes no arithmetic.
+struct TuneKey {
+  int64_t m, n;
+  int dt;
+  bool operator<(const TuneKey &o) const {
+    return m != o.m ? m < o.m : n != o.n ? n < o.n : dt < o.dt;
+  }
+};
+std::mutex &tune_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+std::map<TuneKey, std::pair<int, int>> &tune_table() {
+  static std::map<TuneKey, std::pair<int, int>> t;
+  return t;
+}
+
+template <typename T> int tune_loads(pogs_ctx *c) {
+  const int big = (size_t)c->m * c->ld * sizeof(T) > kStreamMatrixBytes ? 1 : 0;
+  c->nt_rows = c->nt_cols = big;
+  if (!c->params.autotune) return POGS_OK;
+  const TuneKey key{c->m, c->n, (int)c->dt};
+  {
+    std::lock_guard<std::mutex> g(tune_mutex());
+    auto it = tune_table().find(key);
+    if (it != tune_table().end()) {
+      c->nt_rows = it->second.first;
+      c->nt_cols = it->second.second;
+      return POGS_OK;
+    }
+  }
+  hipStream_t s = c->stream;
+  POGS_HIP_TRY(hipMemsetAsync(c->ctrl, 0, sizeof(Ctrl), s));  // no stop flag: every pass runs
+  hipEvent_t e0, e1;
+  POGS_HIP_TRY(hipEventCreate(&e0));
+  POGS_HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_r = big, best_c = big;
+  for (int cand = 0; cand < 4; ++cand) {
+    IterArgs<T> p = c->iter_args<T>();
+    p.nt_rows = cand & 1;
+    p.nt_cols = cand >> 1;
+    // the solve only where the factor exists (a CGLS context has none)
+    const bool solve = c->Kinv != nullptr;
+    for (int w = 1; w < 4; ++w)
+      if (w != 2 || solve) launch_iteration_part<T>(p, w, c->splits, c->rps, c->ncolp, s);
+    POGS_HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < 4; ++r)
+      for (int w = 1; w < 4; ++w)
+        if (w != 2 || solve) launch_iteration_part<T>(p, w, c->splits, c->rps, c->ncolp, s);
+    POGS_HIP_TRY(hipEventRecord(e1, s));
+    POGS_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    POGS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_r = p.nt_rows;
+      best_c = p.nt_cols;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  POGS_HIP_TRY(hipGetLastError());
+  c->nt_rows = best_r;
+  c->nt_cols = best_c;
+  std::lock_guard<std::mutex> g(tune_mutex());
+  tune_table()[key] = {best_r, best_c};
+  return POGS_OK;
+}
+
 }  // namespace
 
 extern "C" int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, pogs_dtype dt, pogs_order ord,
@@ -243,6 +322,7 @@ extern "C" int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, po
   c->arena.stream = c->stream;
   int rc = dt == POGS_F32 ? init_impl<float>(c, A, dt, ord, lda, mem) : init_impl<double>(c, A, dt, ord, lda, mem);
   if (!rc) rc = dt == POGS_F32 ? alloc_iteration<float>(c) : alloc_iteration<double>(c);
+  if (!rc) rc = dt == POGS_F32 ? tune_loads<float>(c) : tune_loads<double>(c);
   if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = POGS_EDEVICE;
   if (rc) {
     delete c;

@@ -259,3 +259,20 @@ def test_big_setup_and_projection(big):
 def test_big_solve(big, kind):
     prob = big if kind == "lasso" else W.nnls_from(big)
     _check_solve(prob, np.float32)
+
+
+@pytest.mark.parametrize("shape", [(3000, 700), (700, 3000)])
+def test_autotuned_load_policy_changes_no_bit(shape):
+    """The tuner picks only the load policy of the passes (cached or
+    non-temporal), so a solve gives the same bits with and without it."""
+    prob = W.lasso(*shape, seed=sum(shape))
+    out = []
+    for tune in (0, 1):
+        prm = P.default_params(autotune=tune)
+        with P.Context(prob.A, prm) as ctx:
+            r = ctx.solve(prob.f, prob.g, prm)
+        out.append(r)
+    assert out[0].iters == out[1].iters
+    np.testing.assert_array_equal(out[0].x, out[1].x)
+    np.testing.assert_array_equal(out[0].nu, out[1].nu)
+    assert out[0].optval == out[1].optval
