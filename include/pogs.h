@@ -198,9 +198,10 @@ int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, pogs_dtype dt
  * Algorithm 2 and the Frobenius normalisation of Section 4.1.2 with row passes
  * over both, and projects by CGLS (Section 3.5, indirect; no factorisation of
  * a sparse K): solves on this context use POGS_PROJ_CGLS whatever
- * params->projection says, with cg_max_iter and cg_tol as given.  Warm starts,
- * the gap rule, pogs_project and pogs_solve_path are not available on it
- * (EUNSUPPORTED).  Limits: nnz, m, n below 2^31 (int32 indices on the device).
+ * params->projection says, with cg_max_iter and cg_tol as given.  Warm starts
+ * work as on a dense context (y = A^ x and x~ = -A^T y~ as row passes over
+ * the two copies).  The gap rule, pogs_project and pogs_solve_path are not
+ * available on it (EUNSUPPORTED).  Limits: nnz, m, n below 2^31 (int32 indices on the device).
  * Errors: EINVAL (m, n <= 0, nnz < 0, NULL pointers, rowptr not
  * non-decreasing from 0 to nnz, a column index outside [0, n), non-finite
  * values, invalid params), ENOMEM, EDEVICE.  On error *out is set to NULL. */

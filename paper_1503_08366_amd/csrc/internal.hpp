@@ -211,6 +211,11 @@ void run_equilibrate_sparse(Csr<T> A, Csr<T> At, int m, int n, int iters, double
 template <typename T> void launch_iteration_cg_sparse(const IterArgs<T> &p, int cap, hipStream_t s);
 // Parts for the profiler: 0 prox, 1 first passes, 2 one CG step.
 template <typename T> void launch_iteration_cg_sparse_part(const IterArgs<T> &p, int which, hipStream_t s);
+// Warm start on the sparse pair: the state the dense warm start sets, with
+// y = A^ x and x~ = -A^T y~ as row passes over A^ and A^T.
+template <typename T>
+void launch_warm_start_sparse(const IterArgs<T> &p, const double *D, const double *E, double rho0, const T *x0,
+                              const T *nu0, hipStream_t s);
 
 // Iteration geometry helpers.
 int gemv_t_tile(int elem_size);

@@ -240,12 +240,6 @@ void launch_project(const IterArgs<T> &p, int splits, int rps, int ncolp, const 
 // the prox step returns when it leaves y unchanged); x~ = -A^T y~ (the
 // relation every projection restores).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void warm_scale_kernel(const T *v0, const double *S, bool divide, double f,
-                                                            int len, T *out) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < len) out[i] = (T)(f * (divide ? (double)v0[i] / S[i] : (double)v0[i] * S[i]));
-}
 template <typename T> struct EpiWarmY : EpiNoSkip<T> {  // y = A x
   T *y;
   __device__ double row(int i, double v, double) const { y[i] = (T)v; return 0.0; }

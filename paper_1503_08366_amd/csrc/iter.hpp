@@ -404,5 +404,12 @@ __device__ __forceinline__ void unscale_body(
   }
 }
 
+// out = f * (v0 / S) or f * (v0 * S), elementwise (the warm start's change of variables)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void warm_scale_kernel(const T *v0, const double *S, bool divide, double f,
+                                                            int len, T *out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < len) out[i] = (T)(f * (divide ? (double)v0[i] / S[i] : (double)v0[i] * S[i]));
+}
 
 }  // namespace pogs

@@ -582,7 +582,8 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
         dnu0 = c->vecp<T>(14);
       }
     }
-    launch_warm_start<T>(c->iter_args<T>(), c->splits, c->rps, c->ncolp, c->D, c->E, p.rho0, dx0, dnu0, s);
+    if (c->sparse) launch_warm_start_sparse<T>(c->iter_args<T>(), c->D, c->E, p.rho0, dx0, dnu0, s);
+    else launch_warm_start<T>(c->iter_args<T>(), c->splits, c->rps, c->ncolp, c->D, c->E, p.rho0, dx0, dnu0, s);
     if (cg_cap > 0) launch_cg_from_state<T>(c->iter_args<T>(), s);
     if (out->mem == POGS_HOST) POGS_HIP_TRY(hipStreamSynchronize(s));  // host x0, nu0 may be pageable
   }
@@ -731,10 +732,7 @@ extern "C" int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, con
   if (out->mem != POGS_HOST && out->mem != POGS_DEVICE) return POGS_EINVAL;
   pogs_params p = params ? *params : ctx->params;
   if (check_params(p)) return POGS_EINVAL;
-  if (ctx->sparse) {  // a sparse context always projects by CGLS; no warm start
-    p.projection = POGS_PROJ_CGLS;
-    if (x0 || nu0) return POGS_EUNSUPPORTED;
-  }
+  if (ctx->sparse) p.projection = POGS_PROJ_CGLS;  // a sparse context always projects by CGLS
   // a context set up for CGLS has no factor for the direct projection; the
   // CGLS state does not keep x~ and y~ for the gap test
   if (p.projection == POGS_PROJ_DIRECT && ctx->proj != POGS_PROJ_DIRECT) return POGS_EUNSUPPORTED;

@@ -273,13 +273,48 @@ template <typename T> void launch_iteration_cg_sparse_part(const IterArgs<T> &p,
   else launch_sp_step<T>(p, 0, 1 << 30, s);
 }
 
+// Warm start (the dense path's change of variables): x = E^-1 x0, y = A^ x
+// over the rows of A^, y~ = -(D^-1 nu0) / rho0, x~ = -A^T y~ over the rows
+// of A^T.
+template <typename T> struct EpiSpWarm {
+  T *out;
+  double sign;
+  __device__ double row(int i, double v, double) const {
+    out[i] = (T)(sign * v);
+    return 0.0;
+  }
+  __device__ void block_done(int, double) const {}
+};
+
+template <int LPR, typename T>
+__global__ __launch_bounds__(kBlock) void sp_warm_kernel(Csr<T> A, const T *v, EpiSpWarm<T> e) {
+  spmv_body<LPR, 1, false, T, T, EpiSpWarm<T>>(A, v, v, e);
+}
+
+template <typename T>
+void launch_warm_start_sparse(const IterArgs<T> &p, const double *D, const double *E, double rho0, const T *x0,
+                              const T *nu0, hipStream_t s) {
+  if (x0) {
+    hipLaunchKernelGGL(warm_scale_kernel<T>, dim3(cdiv(p.n, kBlock)), dim3(kBlock), 0, s, x0, E, true, 1.0, p.n,
+                       p.x);
+    POGS_SP_DISPATCH(p.sa.lpr, sp_warm_kernel, p.sa.grid, s, p.sa, (const T *)p.x, EpiSpWarm<T>{p.y, 1.0})
+  }
+  if (nu0) {
+    hipLaunchKernelGGL(warm_scale_kernel<T>, dim3(cdiv(p.m, kBlock)), dim3(kBlock), 0, s, nu0, D, true,
+                       -1.0 / rho0, p.m, p.yt);
+    POGS_SP_DISPATCH(p.sat.lpr, sp_warm_kernel, p.sat.grid, s, p.sat, (const T *)p.yt, EpiSpWarm<T>{p.xt, -1.0})
+  }
+}
+
 #undef POGS_SP_DISPATCH
 
 #define POGS_INST(T)                                                                                        \
   template void run_equilibrate_sparse<T>(Csr<T>, Csr<T>, int, int, int, double, double *, double *,        \
                                           double *, hipStream_t);                                           \
   template void launch_iteration_cg_sparse<T>(const IterArgs<T> &, int, hipStream_t);                       \
-  template void launch_iteration_cg_sparse_part<T>(const IterArgs<T> &, int, hipStream_t);
+  template void launch_iteration_cg_sparse_part<T>(const IterArgs<T> &, int, hipStream_t);                  \
+  template void launch_warm_start_sparse<T>(const IterArgs<T> &, const double *, const double *, double,      \
+                                            const T *, const T *, hipStream_t);
 POGS_INST(float)
 POGS_INST(double)
 #undef POGS_INST

@@ -95,10 +95,45 @@ def test_sparse_device_input_and_rejections():
         r2 = c_dev.solve(p.f, p.g)
         assert r1.converged and r2.converged
         assert r1.iters == r2.iters and abs(r1.optval - r2.optval) <= 1e-12 * max(1.0, abs(r1.optval))
-        for call in (lambda: c_host.solve(p.f, p.g, x0=np.zeros(100, np.float32)),
-                     lambda: c_host.solve(p.f, p.g, P.default_params(stop_rule="gap")),
+        for call in (lambda: c_host.solve(p.f, p.g, P.default_params(stop_rule="gap")),
                      lambda: c_host.project(np.zeros(100, np.float32), np.zeros(400, np.float32)),
                      lambda: c_host.solve_path([p.f], [p.g])):
             with pytest.raises(P.PogsError) as ei:
                 call()
             assert ei.value.code == P.POGS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+@pytest.mark.parametrize("shape,k", [((700, 160), 9), ((160, 600), 40)])
+def test_sparse_warm_start_matches_oracle(shape, k, dt):
+    """Warm start from a perturbed point (x0, nu0) on the sparse pair against
+    the oracle's warm start on the densified matrix."""
+    p = W.sparse_problem("lasso", *shape, k, seed=5 * shape[0] + k, dtype=dt)
+    m, n = shape
+    rng = np.random.default_rng(m + n)
+    x0 = (0.1 * rng.normal(size=n)).astype(dt)
+    nu0 = (0.1 * rng.normal(size=m)).astype(dt)
+    with P.SparseContext(p.A) as ctx:
+        r = ctx.solve(p.f, p.g, x0=x0, nu0=nu0)
+    ref = O.solve(_dense(p.A), p.f, p.g, O.Params(eps_cmp=EPS[dt], projection="cgls"),
+                  x0=x0.astype(np.float64), nu0=nu0.astype(np.float64))
+    assert ref.converged and r.status == P.POGS_CONVERGED, (r, ref.iters)
+    assert abs(r.optval - ref.optval) <= 1e-3 * max(abs(ref.optval), 1.0), (r.optval, ref.optval)
+    if dt == np.float64:
+        assert abs(r.iters - ref.iters) <= 1, (r.iters, ref.iters)
+
+
+def test_sparse_warm_start_from_optimum_and_device_input():
+    """From a converged solution the warm state is a fixed point up to the CG
+    tolerance; device-resident (x0, nu0) give the same solve as host ones."""
+    import torch
+    p = W.sparse_problem("lasso", 1200, 300, 12, seed=21, dtype=np.float64)
+    prm = P.default_params(eps_abs=1e-6, eps_rel=1e-6)
+    with P.SparseContext(p.A, prm) as ctx:
+        r0 = ctx.solve(p.f, p.g, prm)
+        r1 = ctx.solve(p.f, p.g, x0=r0.x, nu0=r0.nu)
+        r2 = ctx.solve(p.f, p.g, device_out=True, x0=torch.from_numpy(r0.x), nu0=torch.from_numpy(r0.nu))
+    assert r0.converged and r1.converged
+    assert r1.iters <= 3, r1.iters
+    assert abs(r1.optval - r0.optval) <= 1e-4 * max(1.0, abs(r0.optval))
+    assert r2.iters == r1.iters and abs(r2.optval - r1.optval) <= 1e-12 * max(1.0, abs(r1.optval))
