@@ -143,6 +143,13 @@ typedef struct {
                             keeps the fastest; the choice is cached per
                             (m, n, dtype) in the process and changes no result
                             bit.  0: a matrix above 192 MB streams, others cache. */
+  int32_t sparse_segment; /* pogs_init_sparse only: columns of A^T per segment
+                            of its segmented copy (the passes over A^T gather
+                            from one segment's piece of an m-vector at a time);
+                            0 (default): 1 MB of the paired vector per segment,
+                            with at least two entries per row piece on average.
+                            >= 0; results depend on it only through the
+                            summation order. */
 } pogs_params;
 
 /* Result of a solve: the half-step tuple (x, y, mu, nu) of the last iteration,

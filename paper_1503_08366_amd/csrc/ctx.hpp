@@ -168,6 +168,7 @@ struct pogs_ctx {
   int *sp_rp = nullptr, *sp_ci = nullptr, *sp_rpt = nullptr, *sp_cit = nullptr;
   void *sp_va = nullptr, *sp_vat = nullptr;
   int sp_lpr = 0, sp_grid = 0, sp_lprt = 0, sp_gridt = 0;
+  int sp_nseg = 1;  // column segments of the A^T copy
   void *sp_pair = nullptr;  // 2 m entries of T
   double *D = nullptr, *E = nullptr;
   // iteration state (T): x y xt yt xh yh mu nu cx dy rhs, outputs xo yo muo nuo
@@ -254,8 +255,8 @@ struct pogs_ctx {
     p.s_gobj = p.s_qq + n_pri;       // nbx + nby
     p.s_gconj = p.s_gobj + nbx + nby;  // nbx + nby
     if (sparse) {
-      p.sa = Csr<T>{sp_rp, sp_ci, (T *)sp_va, (int)m, sp_lpr, sp_grid};
-      p.sat = Csr<T>{sp_rpt, sp_cit, (T *)sp_vat, (int)n, sp_lprt, sp_gridt};
+      p.sa = Csr<T>{sp_rp, sp_ci, (T *)sp_va, (int)m, sp_lpr, sp_grid, 1};
+      p.sat = Csr<T>{sp_rpt, sp_cit, (T *)sp_vat, (int)n, sp_lprt, sp_gridt, sp_nseg};
       p.pair = (T *)sp_pair;
     }
     return p;

@@ -54,6 +54,7 @@ inline int check_params(const pogs_params &p) {
     return POGS_EINVAL;
   if (p.projection != POGS_PROJ_DIRECT && p.projection != POGS_PROJ_CGLS) return POGS_EINVAL;
   if (p.stop_rule != POGS_STOP_RESIDUAL && p.stop_rule != POGS_STOP_GAP) return POGS_EINVAL;
+  if (p.sparse_segment < 0) return POGS_EINVAL;
   if (p.projection == POGS_PROJ_CGLS && (p.cg_max_iter < 1 || p.cg_max_iter > 1000 || !(p.cg_tol > 0.0) ||
                                          !finite(p.cg_tol)))
     return POGS_EINVAL;

@@ -59,12 +59,24 @@ template <typename T> struct FnDev {
 // Sparse matrix in compressed rows on the device: row r holds the entries
 // ci[rp[r] .. rp[r + 1]) with values va.  The passes over it give each row lpr
 // lanes (a power of two up to 64) and launch `grid` workgroups.
+// Compressed rows.  nseg > 1 (the copy of A^T): the entries are split by
+// column into nseg segments of seg columns each and stored segment by
+// segment; the entries of row r in segment s are [rp[s rows + r],
+// rp[s rows + r + 1]), so rp has nseg rows + 1 entries.
 template <typename T> struct Csr {
   const int *rp;
   const int *ci;
   T *va;
-  int rows, lpr, grid;
+  int rows, lpr, grid, nseg;
 };
+
+// Column segments of the sparse A^T: the piece of the gathered vector one
+// segment reads (2 values of T per column) is at most kSegBytes, so it stays
+// in one XCD's L2 (4 MB) while the grid works on that segment; a workgroup
+// keeps the sums of at most kSegRows rows in LDS across the segments.
+constexpr size_t kSegBytes = (size_t)1 << 20;
+constexpr int kSegRows = 512;
+constexpr int kSegGrid = 2048;
 
 // Default load policy of the passes over A (when not tuned): a matrix larger
 // than this is streamed with non-temporal loads (the MI355X last-level cache
@@ -201,6 +213,13 @@ GemvNShape gemv_n_shape(int m, int n, int ld, int elem_size);
 // Sparse contexts (sparse.hip).  Lanes per row and grid of the passes over a
 // matrix with `rows` rows and `nnz` entries.
 void sparse_shape(int rows, int64_t nnz, int *lpr, int *grid);
+// Columns per segment of A^T (m columns, n rows, nnz entries, elem bytes per
+// value): a kSegBytes piece of the paired vector, with at least two entries
+// per row and segment on average (else fewer, wider segments).
+int sparse_segment(int m, int n, int64_t nnz, int elem);
+// Lanes per row and grid of the segmented pass over A^T (rows * nseg row
+// pieces); the grid keeps every workgroup at <= kSegRows rows.
+void sparse_seg_shape(int rows, int nseg, int64_t nnz, int *lpr, int *grid);
 // Algorithm 2 and the Frobenius normalisation on the sparse pair (A, A^T),
 // then both scaled in place to D A E: fills D (m), E (n).  ws: 2 (m + n) + 1024
 // doubles.

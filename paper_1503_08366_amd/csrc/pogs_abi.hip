@@ -60,6 +60,7 @@ int pogs_params_default(pogs_params *p) {
   p->cg_tol = 0.1;
   p->stop_rule = POGS_STOP_RESIDUAL;
   p->autotune = 1;
+  p->sparse_segment = 0;
   return POGS_OK;
 }
 
@@ -372,23 +373,31 @@ int read_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr, const int
   return POGS_OK;
 }
 
-// A^T in compressed rows, by a counting sort over the columns that keeps the
-// row order inside each column (deterministic).
-void transpose_csr(const HostCsr &a, int n, HostCsr *t) {
+// A^T in compressed rows split into column segments of seg columns (rows of
+// A): the entries of row j of A^T whose column i lies in segment s = i / seg
+// form row piece s n + j, stored in that order.  A counting sort over the
+// pieces that keeps the row order of A inside each piece (deterministic).
+void transpose_csr(const HostCsr &a, int n, int seg, HostCsr *t) {
   const size_t nnz = a.ci.size();
-  t->rp.assign((size_t)n + 1, 0);
-  for (size_t k = 0; k < nnz; ++k) ++t->rp[(size_t)a.ci[k] + 1];
-  for (int j = 0; j < n; ++j) t->rp[(size_t)j + 1] += t->rp[(size_t)j];
+  const int m = (int)a.rp.size() - 1;
+  const size_t pieces = (size_t)cdiv(m, seg) * n;
+  t->rp.assign(pieces + 1, 0);
+  for (int i = 0; i < m; ++i) {
+    const size_t base = (size_t)(i / seg) * n;
+    for (int k = a.rp[(size_t)i]; k < a.rp[(size_t)i + 1]; ++k) ++t->rp[base + a.ci[(size_t)k] + 1];
+  }
+  for (size_t b = 0; b < pieces; ++b) t->rp[b + 1] += t->rp[b];
   std::vector<int> cur(t->rp.begin(), t->rp.end() - 1);
   t->ci.resize(nnz);
   t->va.resize(nnz);
-  const int m = (int)a.rp.size() - 1;
-  for (int i = 0; i < m; ++i)
+  for (int i = 0; i < m; ++i) {
+    const size_t base = (size_t)(i / seg) * n;
     for (int k = a.rp[(size_t)i]; k < a.rp[(size_t)i + 1]; ++k) {
-      const int pos = cur[(size_t)a.ci[(size_t)k]]++;
+      const int pos = cur[base + a.ci[(size_t)k]]++;
       t->ci[(size_t)pos] = i;
       t->va[(size_t)pos] = a.va[(size_t)k];
     }
+  }
 }
 
 template <typename T> int init_sparse_impl(pogs_ctx *c, const HostCsr &a, const HostCsr &t) {
@@ -397,9 +406,9 @@ template <typename T> int init_sparse_impl(pogs_ctx *c, const HostCsr &a, const 
   hipStream_t s = c->stream;
   int rc;
   sparse_shape(m, (int64_t)nnz, &c->sp_lpr, &c->sp_grid);
-  sparse_shape(n, (int64_t)nnz, &c->sp_lprt, &c->sp_gridt);
+  sparse_seg_shape(n, c->sp_nseg, (int64_t)nnz, &c->sp_lprt, &c->sp_gridt);
   if ((rc = c->arena.alloc((void **)&c->sp_rp, ((size_t)m + 1) * 4))) return rc;
-  if ((rc = c->arena.alloc((void **)&c->sp_rpt, ((size_t)n + 1) * 4))) return rc;
+  if ((rc = c->arena.alloc((void **)&c->sp_rpt, t.rp.size() * 4))) return rc;
   if ((rc = c->arena.alloc((void **)&c->sp_ci, std::max<size_t>(nnz, 1) * 4))) return rc;
   if ((rc = c->arena.alloc((void **)&c->sp_cit, std::max<size_t>(nnz, 1) * 4))) return rc;
   if ((rc = c->arena.alloc(&c->sp_va, std::max<size_t>(nnz, 1) * sizeof(T)))) return rc;
@@ -446,7 +455,9 @@ extern "C" int pogs_init_sparse(pogs_ctx **out, int64_t m, int64_t n, int64_t nn
   HostCsr a, t;
   int rc = read_csr(m, n, nnz, rowptr, colind, val, dt, mem, &a);
   if (rc) return rc;
-  transpose_csr(a, (int)n, &t);
+  const int seg = p.sparse_segment > 0 ? (int)std::min<int64_t>(p.sparse_segment, m)
+                                       : sparse_segment((int)m, (int)n, nnz, dt == POGS_F32 ? 4 : 8);
+  transpose_csr(a, (int)n, seg, &t);
   pogs_ctx *c = new (std::nothrow) pogs_ctx();
   if (!c) return POGS_ENOMEM;
   c->m = m;
@@ -456,6 +467,7 @@ extern "C" int pogs_init_sparse(pogs_ctx **out, int64_t m, int64_t n, int64_t nn
   c->proj = POGS_PROJ_CGLS;
   c->sparse = true;
   c->nnz = nnz;
+  c->sp_nseg = (int)cdiv(m, (int64_t)seg);
   c->ld = (int)round_up(n, 64);
   c->q = (int)std::min(m, n);
   c->Q = (int)round_up(c->q, 64);

@@ -22,6 +22,20 @@ void sparse_shape(int rows, int64_t nnz, int *lpr, int *grid) {
   *grid = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(std::max(rows, 1), groups), 1024));
 }
 
+int sparse_segment(int m, int n, int64_t nnz, int elem) {
+  int64_t nseg = cdiv((int64_t)m, (int64_t)(kSegBytes / (2 * (size_t)elem)));
+  nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, nnz / (2 * (int64_t)n)));
+  return (int)cdiv((int64_t)m, nseg);
+}
+
+void sparse_seg_shape(int rows, int nseg, int64_t nnz, int *lpr, int *grid) {
+  int g;
+  sparse_shape((int)std::min<int64_t>((int64_t)rows * nseg, 1 << 30), nnz, lpr, &g);
+  const int64_t groups = kBlock / *lpr;
+  const int64_t want = std::min<int64_t>(cdiv((int64_t)rows, groups), kSegGrid);
+  *grid = (int)std::max<int64_t>(1, std::max<int64_t>(want, cdiv((int64_t)rows, (int64_t)kSegRows)));
+}
+
 __device__ inline void acc_add(double &a, double b) { a += b; }
 __device__ inline void acc_add(Sum2 &a, const Sum2 &b) {
   a.a += b.a;
@@ -70,6 +84,66 @@ __device__ __forceinline__ void spmv_body(const Csr<T> &A, const TV *__restrict_
   }
 }
 
+// The same pass over the rows of a segmented copy (A^T): every workgroup
+// walks the segments in order for its own rows and keeps their sums in LDS,
+// so at any moment the grid gathers from one segment's piece of the vector,
+// which stays in L2, instead of from the whole m-long vector.  The lane that
+// owns a row (sub == 0) is the only one to touch its LDS slot, so the slots
+// need no barrier.  Requires ceil(rows / (gridDim.x G)) G <= kSegRows (the
+// host's grid does this).
+template <int LPR, int NRHS, bool SQUARE, typename T, typename TV, class Epi, bool PAIRED = false>
+__device__ __forceinline__ void spmv_seg_body(const Csr<T> &A, const TV *__restrict__ v0, const TV *__restrict__ v1,
+                                              const Epi &epi) {
+  typedef TV TV2 __attribute__((ext_vector_type(2)));
+  constexpr int G = kBlock / LPR;
+  __shared__ double acc[NRHS][kSegRows];
+  __shared__ double bs[kBlock / kWave];
+  const int grp = threadIdx.x / LPR, sub = threadIdx.x % LPR;
+  const int first = blockIdx.x * G + grp, stride = gridDim.x * G;
+  if (sub == 0)
+    for (int row = first, slot = grp; row < A.rows; row += stride, slot += G)
+      for (int r = 0; r < NRHS; ++r) acc[r][slot] = 0.0;
+  for (int sg = 0; sg < A.nseg; ++sg) {
+    const int *__restrict__ rp = A.rp + (size_t)sg * A.rows;
+    for (int row = first, slot = grp; row < A.rows; row += stride, slot += G) {
+      const int k1 = rp[row + 1];
+      double s0 = 0.0, s1 = 0.0;
+      for (int k = rp[row] + sub; k < k1; k += LPR) {
+        double a = (double)A.va[k];
+        if constexpr (SQUARE) a *= a;
+        const int j = A.ci[k];
+        if constexpr (PAIRED) {
+          const TV2 v = reinterpret_cast<const TV2 *>(v0)[j];
+          s0 = fma(a, (double)v.x, s0);
+          s1 = fma(a, (double)v.y, s1);
+        } else {
+          s0 = fma(a, (double)v0[j], s0);
+          if constexpr (NRHS > 1) s1 = fma(a, (double)v1[j], s1);
+        }
+      }
+      s0 = group_sum<LPR>(s0);
+      if constexpr (NRHS > 1) s1 = group_sum<LPR>(s1);
+      if (sub == 0) {
+        acc[0][slot] += s0;
+        if constexpr (NRHS > 1) acc[1][slot] += s1;
+      }
+    }
+  }
+  using R = decltype(epi.row(0, 0.0, 0.0));
+  R contrib{};
+  if (sub == 0)
+    for (int row = first, slot = grp; row < A.rows; row += stride, slot += G)
+      acc_add(contrib, epi.row(row, acc[0][slot], NRHS > 1 ? acc[NRHS - 1][slot] : 0.0));
+  if constexpr (std::is_same<R, Sum2>::value) {
+    const double a = block_sum(contrib.a, bs);
+    const double b = block_sum(contrib.b, bs);
+    if (threadIdx.x == 0) epi.block_done(blockIdx.x, Sum2{a, b});
+  } else {
+    const double t = block_sum(contrib, bs);
+    if (threadIdx.x == 0) epi.block_done(blockIdx.x, t);
+  }
+}
+
 // A column epilogue of the dense path used on the rows of A^T.
 template <class E> struct ColRows {
   E e;
@@ -96,19 +170,22 @@ struct EpiSpFro {  // sum_i d_i ((A o A) e)_i = ||sqrt(d) A sqrt(e)||_F^2
   __device__ void block_done(int b, double v) const { slots[b] = v; }
 };
 
-template <int LPR, typename T, class Epi>
+template <int LPR, typename T, class Epi, bool SEG>
 __global__ __launch_bounds__(kBlock) void sp_square_kernel(Csr<T> A, const double *v, Epi e) {
-  spmv_body<LPR, 1, true, T, double, Epi>(A, v, v, e);
+  if constexpr (SEG) spmv_seg_body<LPR, 1, true, T, double, Epi>(A, v, v, e);
+  else spmv_body<LPR, 1, true, T, double, Epi>(A, v, v, e);
 }
 
-template <typename T, class Epi> static void launch_square(const Csr<T> &A, const double *v, const Epi &e, hipStream_t s) {
+// SEG: A is the segmented copy of A^T
+template <typename T, class Epi, bool SEG>
+static void launch_square(const Csr<T> &A, const double *v, const Epi &e, hipStream_t s) {
   const dim3 g(A.grid), b(kBlock);
   switch (A.lpr) {
-    case 4: hipLaunchKernelGGL((sp_square_kernel<4, T, Epi>), g, b, 0, s, A, v, e); break;
-    case 8: hipLaunchKernelGGL((sp_square_kernel<8, T, Epi>), g, b, 0, s, A, v, e); break;
-    case 16: hipLaunchKernelGGL((sp_square_kernel<16, T, Epi>), g, b, 0, s, A, v, e); break;
-    case 32: hipLaunchKernelGGL((sp_square_kernel<32, T, Epi>), g, b, 0, s, A, v, e); break;
-    default: hipLaunchKernelGGL((sp_square_kernel<64, T, Epi>), g, b, 0, s, A, v, e); break;
+    case 4: hipLaunchKernelGGL((sp_square_kernel<4, T, Epi, SEG>), g, b, 0, s, A, v, e); break;
+    case 8: hipLaunchKernelGGL((sp_square_kernel<8, T, Epi, SEG>), g, b, 0, s, A, v, e); break;
+    case 16: hipLaunchKernelGGL((sp_square_kernel<16, T, Epi, SEG>), g, b, 0, s, A, v, e); break;
+    case 32: hipLaunchKernelGGL((sp_square_kernel<32, T, Epi, SEG>), g, b, 0, s, A, v, e); break;
+    default: hipLaunchKernelGGL((sp_square_kernel<64, T, Epi, SEG>), g, b, 0, s, A, v, e); break;
   }
 }
 
@@ -130,13 +207,15 @@ __global__ __launch_bounds__(kBlock) void sp_eq_finish_kernel(const double *d, c
 }
 
 // A^_ij = D_i A_ij E_j on the rows of A (transposed = false: row r is i) or
-// of A^T (transposed = true: row r is j), the same expression in both.
+// of A^T (transposed = true: row r is j), the same expression in both; one
+// wave per row piece (row r % rows of segment r / rows).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void sp_scale_kernel(Csr<T> A, const double *D, const double *E, bool transposed) {
-  const int r = blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
-  if (r >= A.rows) return;
+  const int64_t b = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+  if (b >= (int64_t)A.rows * A.nseg) return;
+  const int r = (int)(b % A.rows);
   const int lane = threadIdx.x & (kWave - 1);
-  for (int k = A.rp[r] + lane; k < A.rp[r + 1]; k += kWave) {
+  for (int k = A.rp[b] + lane; k < A.rp[b + 1]; k += kWave) {
     const int c = A.ci[k];
     const double di = transposed ? D[c] : D[r], ej = transposed ? E[r] : E[c];
     A.va[k] = (T)(di * (double)A.va[k] * ej);
@@ -155,14 +234,15 @@ void run_equilibrate_sparse(Csr<T> A, Csr<T> At, int m, int n, int iters, double
   const double gamma = (double)(m + n) * sqrt(eps_cmp);
   hipLaunchKernelGGL(sp_fill_kernel, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, e, n, 1.0);
   for (int it = 0; it < iters; ++it) {
-    launch_square<T>(A, e, EpiSpEqRow{d, (double)n, gamma / m}, s);
-    launch_square<T>(At, d, EpiSpEqRow{e, (double)m, gamma / n}, s);
+    launch_square<T, EpiSpEqRow, false>(A, e, EpiSpEqRow{d, (double)n, gamma / m}, s);
+    launch_square<T, EpiSpEqRow, true>(At, d, EpiSpEqRow{e, (double)m, gamma / n}, s);
   }
-  launch_square<T>(A, e, EpiSpFro{d, slots}, s);
+  launch_square<T, EpiSpFro, false>(A, e, EpiSpFro{d, slots}, s);
   hipLaunchKernelGGL(sp_eq_finish_kernel, dim3(cdiv(m + n, kBlock)), dim3(kBlock), 0, s, d, e, slots, A.grid, m, n,
                      D, E);
   hipLaunchKernelGGL(sp_scale_kernel<T>, dim3(cdiv(m, kBlock / kWave)), dim3(kBlock), 0, s, A, D, E, false);
-  hipLaunchKernelGGL(sp_scale_kernel<T>, dim3(cdiv(n, kBlock / kWave)), dim3(kBlock), 0, s, At, D, E, true);
+  hipLaunchKernelGGL(sp_scale_kernel<T>, dim3(cdiv((int64_t)n * At.nseg, (int64_t)(kBlock / kWave))), dim3(kBlock), 0,
+                     s, At, D, E, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -217,7 +297,7 @@ template <int LPR, typename T>
 __global__ __launch_bounds__(kBlock) void sp_first_kernel(IterArgs<T> p) {
   if (!cg_first_enter<T>(p)) return;
   ColRows<EpiCgFirst<T>> e{EpiCgFirst<T>{p}};
-  spmv_body<LPR, 2, false, T, T, ColRows<EpiCgFirst<T>>, true>(p.sat, p.pair, p.pair, e);
+  spmv_seg_body<LPR, 2, false, T, T, ColRows<EpiCgFirst<T>>, true>(p.sat, p.pair, p.pair, e);
 }
 
 // KA: q_j = A^ s_j + beta q_{j-1}, pending r1 update
@@ -234,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void sp_step_kernel(IterArgs<T> p, int j) {
   EpiCgStep<T> e;
   if (!cg_step_enter<T>(p, j, &e)) return;
   ColRows<EpiCgStep<T>> c{e};
-  spmv_body<LPR, 2, false, T, T, ColRows<EpiCgStep<T>>, true>(p.sat, p.pair, p.pair, c);
+  spmv_seg_body<LPR, 2, false, T, T, ColRows<EpiCgStep<T>>, true>(p.sat, p.pair, p.pair, c);
 }
 
 #define POGS_SP_DISPATCH(lpr, KERNEL, grid, s, ...)                                                        \
@@ -290,6 +370,10 @@ template <int LPR, typename T>
 __global__ __launch_bounds__(kBlock) void sp_warm_kernel(Csr<T> A, const T *v, EpiSpWarm<T> e) {
   spmv_body<LPR, 1, false, T, T, EpiSpWarm<T>>(A, v, v, e);
 }
+template <int LPR, typename T>
+__global__ __launch_bounds__(kBlock) void sp_warm_seg_kernel(Csr<T> A, const T *v, EpiSpWarm<T> e) {
+  spmv_seg_body<LPR, 1, false, T, T, EpiSpWarm<T>>(A, v, v, e);
+}
 
 template <typename T>
 void launch_warm_start_sparse(const IterArgs<T> &p, const double *D, const double *E, double rho0, const T *x0,
@@ -302,7 +386,7 @@ void launch_warm_start_sparse(const IterArgs<T> &p, const double *D, const doubl
   if (nu0) {
     hipLaunchKernelGGL(warm_scale_kernel<T>, dim3(cdiv(p.m, kBlock)), dim3(kBlock), 0, s, nu0, D, true,
                        -1.0 / rho0, p.m, p.yt);
-    POGS_SP_DISPATCH(p.sat.lpr, sp_warm_kernel, p.sat.grid, s, p.sat, (const T *)p.yt, EpiSpWarm<T>{p.xt, -1.0})
+    POGS_SP_DISPATCH(p.sat.lpr, sp_warm_seg_kernel, p.sat.grid, s, p.sat, (const T *)p.yt, EpiSpWarm<T>{p.xt, -1.0})
   }
 }
 

@@ -52,7 +52,7 @@ class pogs_params(C.Structure):
                 ("tau", C.c_double), ("adaptive_rho", C.c_int32), ("equil_iters", C.c_int32),
                 ("eps_cmp", C.c_double), ("chunk_iters", C.c_int32), ("verbose", C.c_int32),
                 ("projection", C.c_int32), ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
-                ("stop_rule", C.c_int32), ("autotune", C.c_int32)]
+                ("stop_rule", C.c_int32), ("autotune", C.c_int32), ("sparse_segment", C.c_int32)]
 
 
 class pogs_result(C.Structure):

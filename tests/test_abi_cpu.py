@@ -74,7 +74,11 @@ def test_init_rejects_bad_arguments_without_device(lib):
     assert lib.pogs_init(C.byref(h), 4, 3, ptr, 0, 0, 3, 0, C.byref(bad), None) == E
     bad = pogs.default_params(max_iter=0)
     assert lib.pogs_init(C.byref(h), 4, 3, ptr, 0, 0, 3, 0, C.byref(bad), None) == E
+    bad = pogs.default_params(sparse_segment=-1)
+    assert lib.pogs_init(C.byref(h), 4, 3, ptr, 0, 0, 3, 0, C.byref(bad), None) == E
     assert h.value is None
+    p = pogs.default_params()
+    assert p.sparse_segment == 0 and p.autotune == 1
 
 
 def test_solve_and_free_reject_null(lib):

@@ -24,10 +24,12 @@ def _dense(A):
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
-@pytest.mark.parametrize("shape,k", [((500, 120), 6), ((120, 400), 30), ((3000, 700), 40)])
-def test_sparse_equilibration_parity(shape, k, dt):
+@pytest.mark.parametrize("shape,k,seg", [((500, 120), 6, 0), ((120, 400), 30, 0), ((3000, 700), 40, 0),
+                                         ((500, 120), 6, 37), ((3000, 700), 40, 256)])
+def test_sparse_equilibration_parity(shape, k, seg, dt):
+    """seg > 0: A^T stored in column segments of seg columns (ragged last one)."""
     p = W.sparse_problem("lasso", *shape, k, seed=shape[0] + k, dtype=dt)
-    with P.SparseContext(p.A) as ctx:
+    with P.SparseContext(p.A, P.default_params(sparse_segment=seg)) as ctx:
         D, E = ctx.scaling()
     Dr, Er = O.equilibrate(_dense(p.A), EPS[dt], 10)
     np.testing.assert_allclose(D, Dr, rtol=1e-10)
@@ -53,8 +55,10 @@ def test_sparse_solve_matches_oracle(kind, shape, k, dt):
           f"CG steps {r.cg_steps} (oracle {ref.cg_steps})")
 
 
-def test_sparse_with_empty_rows_and_columns():
-    """Rows and columns without entries (a zero row of A, an unused variable)."""
+@pytest.mark.parametrize("seg", [0, 50])
+def test_sparse_with_empty_rows_and_columns(seg):
+    """Rows and columns without entries (a zero row of A, an unused variable);
+    with seg = 50 whole segments of some rows of A^T are empty."""
     rng = np.random.default_rng(3)
     A = W.sparse_matrix(300, 90, 5, rng, np.float64).tolil()
     A[17, :] = 0.0
@@ -65,7 +69,7 @@ def test_sparse_with_empty_rows_and_columns():
     b = rng.normal(size=300)
     f = W.Fn("square", 300, b=b)
     g = W.Fn("abs", 90, c=0.05)
-    with P.SparseContext(A) as ctx:
+    with P.SparseContext(A, P.default_params(sparse_segment=seg)) as ctx:
         r = ctx.solve(f, g)
     ref = O.solve(_dense(A), f, g, O.Params(eps_cmp=EPS[np.float64], projection="cgls"))
     assert r.converged and ref.converged
@@ -137,3 +141,55 @@ def test_sparse_warm_start_from_optimum_and_device_input():
     assert r1.iters <= 3, r1.iters
     assert abs(r1.optval - r0.optval) <= 1e-4 * max(1.0, abs(r0.optval))
     assert r2.iters == r1.iters and abs(r2.optval - r1.optval) <= 1e-12 * max(1.0, abs(r1.optval))
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+@pytest.mark.parametrize("kind,shape,k,seg", [
+    ("lasso", (600, 150), 10, 64), ("lasso", (150, 500), 40, 16), ("logistic", (800, 120), 12, 100),
+    ("lp", (200, 60), 10, 7),
+])
+def test_sparse_segmented_matches_oracle(kind, shape, k, seg, dt):
+    """The passes over A^T in column segments (many, ragged last one) follow
+    the oracle as the single-segment copy does."""
+    p = W.sparse_problem(kind, *shape, k, seed=11 * shape[0] + k, dtype=dt)
+    with P.SparseContext(p.A, P.default_params(sparse_segment=seg)) as ctx:
+        r = ctx.solve(p.f, p.g)
+    ref = O.solve(_dense(p.A), p.f, p.g, O.Params(eps_cmp=EPS[dt], projection="cgls"))
+    assert ref.converged and r.status == P.POGS_CONVERGED, (r, ref.iters)
+    assert abs(r.optval - ref.optval) <= 1e-3 * max(abs(ref.optval), 1.0), (r.optval, ref.optval)
+    if dt == np.float64:
+        assert abs(r.iters - ref.iters) <= 1, (r.iters, ref.iters)
+
+
+def test_sparse_segments_change_only_the_summation_order():
+    """float64: one segment against 9 segments on the same matrix: the scaling
+    agrees to rounding, the solve takes the same path."""
+    p = W.sparse_problem("lasso", 2000, 300, 12, seed=17, dtype=np.float64)
+    out = []
+    for seg in (2000, 223):
+        prm = P.default_params(sparse_segment=seg)
+        with P.SparseContext(p.A, prm) as ctx:
+            D, E = ctx.scaling()
+            r = ctx.solve(p.f, p.g)
+            w = ctx.solve(p.f, p.g, x0=r.x, nu0=r.nu)
+        out.append((D, E, r, w))
+    (D1, E1, r1, w1), (D9, E9, r9, w9) = out
+    np.testing.assert_allclose(D9, D1, rtol=1e-13)
+    np.testing.assert_allclose(E9, E1, rtol=1e-13)
+    assert abs(r9.iters - r1.iters) <= 1 and r9.cg_steps > 0
+    assert abs(r9.optval - r1.optval) <= 1e-8 * max(1.0, abs(r1.optval))
+    assert w1.iters <= 3 and w9.iters <= 3
+
+
+def test_sparse_automatic_segments_at_size_match_dense_cgls():
+    """float32, m = 300000 (three automatic segments of 131072 columns of A^T)
+    against the dense CGLS path on the same matrix."""
+    p = W.sparse_problem("lasso", 300_000, 1000, 8, seed=23)
+    with P.SparseContext(p.A) as ctx:
+        rs = ctx.solve(p.f, p.g)
+    prm = P.default_params(projection="cgls")
+    with P.Context(np.ascontiguousarray(p.A.toarray()), prm) as ctx:
+        rd = ctx.solve(p.f, p.g, prm)
+    assert rs.converged and rd.converged
+    assert abs(rs.optval - rd.optval) <= 1e-3 * max(1.0, abs(rd.optval))
+    assert abs(rs.iters - rd.iters) <= max(2, rd.iters // 20), (rs.iters, rd.iters)
