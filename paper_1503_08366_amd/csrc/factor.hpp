@@ -7,6 +7,8 @@
 // solver calls the same functions in loops inside one workgroup per problem.
 #pragma once
 
+#include <utility>
+
 #include "common.hpp"
 #include "mfma.hpp"
 
@@ -285,6 +287,75 @@ template <class Fn> __device__ inline void acc_store(const F64Acc acc[2][2], Fn 
   f64_tile_store(acc, (w >> 1) * 32, (w & 1) * 32, fn);
 }
 
+// 1 / sqrt(p) for p > 0: the hardware estimate refined by two Newton steps
+// for f(y) = 1 / y^2 - p, y <- y (3 - p y^2) / 2 (each step squares the
+// relative error, so the estimate's ~2^-22 becomes the float64 rounding
+// level).  Cheaper on the factor's critical path than sqrt() followed by a
+// division, which are both correctly rounded expansions.
+__device__ inline double rsqrt_newton(double p) {
+  double y = __builtin_amdgcn_rsq(p);
+  const double h = 0.5 * p;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// Value of v in lane K of each row of 16 lanes, for every lane of that row
+// (DPP row_newbcast: a VGPR-to-VGPR move at ALU rate, no scalar registers).
+template <int K> __device__ inline double row_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + K, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + K, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// 16 x 16 leaf, one copy per row of 16 lanes: lane r holds row r of the
+// block in a[0..15].  Column J of the Cholesky factor: the pivot's
+// reciprocal square root rd gives L_JJ = piv rd (lane J) and L_rJ = a_J rd,
+// then the right-looking update a_k -= L_rJ L_kJ of the later columns.
+template <int J, int... K>
+__device__ inline void leaf_update(double (&a)[16], double lj, std::integer_sequence<int, K...>) {
+  ((a[J + 1 + K] = fma(-lj, row_bcast<J + 1 + K>(lj), a[J + 1 + K])), ...);
+}
+template <int J> __device__ inline void leaf_column(double (&a)[16], double &rdiag, unsigned &nbad, int r) {
+  double piv = row_bcast<J>(a[J]);
+  if (!(piv > 0.0) || !isfinite(piv)) {
+    ++nbad;
+    piv = 1.0;
+  }
+  const double rd = rsqrt_newton(piv);
+  if (r == J) rdiag = rd;
+  const double lj = (r == J ? piv : a[J]) * rd;
+  a[J] = lj;
+  leaf_update<J>(a, lj, std::make_integer_sequence<int, 15 - J>{});
+  __builtin_amdgcn_sched_barrier(0);  // keep each column's broadcasts in its column (register pressure)
+}
+template <int... J>
+__device__ inline void leaf_factor(double (&a)[16], double &rdiag, unsigned &nbad, int r,
+                                   std::integer_sequence<int, J...>) {
+  (leaf_column<J>(a, rdiag, nbad, r), ...);
+}
+
+// W = L^{-1} of the leaf, column r of W in lane r (x[0..15]), by forward
+// substitution swept by columns of L: once W_K is known every later row
+// takes its term, so the dependent chain is one product and one fma per K.
+template <int K, int... R>
+__device__ inline void inv_update(double (&acc)[16], const double (&a)[16], double xk,
+                                  std::integer_sequence<int, R...>) {
+  ((acc[K + 1 + R] = fma(-row_bcast<K + 1 + R>(a[K]), xk, acc[K + 1 + R])), ...);
+}
+template <int K>
+__device__ inline void inv_column(double (&acc)[16], double (&x)[16], const double (&a)[16], double rdiag) {
+  x[K] = acc[K] * row_bcast<K>(rdiag);
+  inv_update<K>(acc, a, x[K], std::make_integer_sequence<int, 15 - K>{});
+  __builtin_amdgcn_sched_barrier(0);
+}
+template <int... K>
+__device__ inline void leaf_inverse(double (&acc)[16], double (&x)[16], const double (&a)[16], double rdiag,
+                                    std::integer_sequence<int, K...>) {
+  (inv_column<K>(acc, x, a, rdiag), ...);
+}
+
 // Value of v in lane l (l uniform), as two 32-bit lane reads.
 __device__ inline double lane_bcast(double v, int l) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -306,52 +377,47 @@ template <class FA, class FB> __device__ inline F64Acc mfma_block16(F64Acc acc, 
 // invert the factor, in LDS with the whole workgroup (4 waves).  The 64 x 64
 // block is factored recursively over 16 x 16 sub-blocks s = 0..3:
 //   leaf:   L_ss = chol(B_ss) and W_s = L_ss^{-1}, in the registers of every
-//           wave (row r of L_ss and column r of W_s in lane r % 16; the values
-//           other rows need are read from their lanes), no LDS round trips
-//           inside the 16-step chains;
+//           row of 16 lanes (row r of L_ss and column r of W_s in lane r % 16;
+//           the values other rows need are DPP row broadcasts), no LDS round
+//           trips inside the 16-step chains;
 //   panel:  L_rs = B_rs W_s^T for the row blocks r > s (f64 MFMA, one wave per block);
 //   update: B_IJ -= L_Is L_Js^T for s < J <= I (f64 MFMA).
 // Then X = L^{-1} by block diagonals: X_ii = W_i, and for i > j
 // X_ij = -W_i sum_{j <= k < i} L_ik X_kj, the partial sums parked in the
 // (unused) upper blocks of X.  Writes L_kk (upper part zeroed) back into K and
 // L_kk^{-1} into Dinv block kb.  A non-positive pivot counts in *bad and is
-// replaced by 1.
+// replaced by 1.  Launched with 256 threads.
 __device__ __forceinline__ void potrf_diag(double *K, int Q, int kb, double *Dinv, unsigned *bad, CholLds &s) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
   double *blk = K + (size_t)kb * NB * Q + (size_t)kb * NB;
-  for (int e = t; e < NB * NB; e += blockDim.x) s.L[e / NB][e % NB] = blk[(size_t)(e / NB) * Q + e % NB];
+  // every load in flight before the first LDS store (256 threads)
+  constexpr int kPer = NB * NB / 256;
+  double v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = t + 256 * u;
+    v[u] = blk[(size_t)(e / NB) * Q + e % NB];
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = t + 256 * u;
+    s.L[e / NB][e % NB] = v[u];
+  }
   __syncthreads();
   unsigned nbad = 0;
+#pragma unroll
   for (int sb = 0; sb < 4; ++sb) {
     const int s0 = sb * 16;
-    // leaf (every wave computes the same values)
-    double a[16], x[16];
+    // leaf (every row of 16 lanes of every wave computes the same values)
+    double a[16], x[16], acc[16];
     double rdiag = 0.0;  // 1 / L_jj, kept in lane j
 #pragma unroll
     for (int k = 0; k < 16; ++k) a[k] = s.L[s0 + r16][s0 + k];
+    leaf_factor(a, rdiag, nbad, r16, std::make_integer_sequence<int, 16>{});
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      double piv = lane_bcast(a[j], j);
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        ++nbad;
-        piv = 1.0;
-      }
-      const double d = sqrt(piv);
-      const double rd = 1.0 / d;
-      if (r16 == j) rdiag = rd;
-      const double lj = r16 == j ? d : a[j] * rd;
-      a[j] = lj;
-#pragma unroll
-      for (int k = j + 1; k < 16; ++k) a[k] = fma(-lj, lane_bcast(lj, k), a[k]);
-    }
-#pragma unroll
-    for (int rr = 0; rr < 16; ++rr) {
-      double acc = r16 == rr ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < rr; ++k) acc = fma(-lane_bcast(a[k], rr), x[k], acc);
-      x[rr] = acc * lane_bcast(rdiag, rr);
-    }
+    for (int rr = 0; rr < 16; ++rr) acc[rr] = r16 == rr ? 1.0 : 0.0;
+    leaf_inverse(acc, x, a, rdiag, std::make_integer_sequence<int, 16>{});
     if (w == 0 && lane < 16) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) s.L[s0 + lane][s0 + k] = a[k];
@@ -408,7 +474,9 @@ __device__ __forceinline__ void potrf_diag(double *K, int Q, int kb, double *Din
   }
   if (nbad && t == 0) atomicAdd(bad, nbad);
   double *dv = Dinv + (size_t)kb * NB * NB;
-  for (int e = t; e < NB * NB; e += blockDim.x) {
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = t + 256 * u;
     const int r = e / NB, c = e % NB;
     blk[(size_t)r * Q + c] = c <= r ? s.L[r][c] : 0.0;
     dv[e] = (c >> 4) > (r >> 4) ? 0.0 : s.X[r][c];
