@@ -27,6 +27,7 @@
 #include "ctx.hpp"
 #include "group_engine.hpp"
 #include "hostutil.hpp"
+#include "upload.hpp"
 
 using namespace pogs;
 
@@ -177,6 +178,7 @@ extern "C" int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_r
     if ((rc = blocks.alloc((void **)&blk_a, tot_a))) return rc;
     if ((rc = blocks.alloc((void **)&blk_w, tot_w))) return rc;
     POGS_HIP_TRY(hipMemsetAsync(blk_a, 0, tot_a, s));
+    POGS_HIP_TRY(host_uploader().order(s));  // the matrix uploads below go into blk_w
     size_t k = 0;
     for (int i : grouped) {
       const pogs_problem &p = probs[i];

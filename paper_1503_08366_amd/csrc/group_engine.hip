@@ -12,6 +12,7 @@
 
 #include "ctx.hpp"
 #include "factor.hpp"
+#include "upload.hpp"
 
 namespace pogs {
 
@@ -179,15 +180,14 @@ int GroupEngine::add(const Input &in, int *handle) {
     POGS_HIP_TRY(hipMemsetAsync(M.arena, 0, g.arena, s_));
   }
   used_[h] = 1;
-  // input matrix, compacted (row-major: lda = n; column-major: lda = m): one
-  // copy when the rows (columns) are contiguous, a strided copy otherwise
+  // input matrix, compacted (row-major: lda = n; column-major: lda = m),
+  // through the pinned-ring uploader (rows packed on the host side)
   float *raw = at<float>(M.ws, g.w_raw);
   const int64_t inner = in.colmajor ? m : n, outer = in.colmajor ? n : m;
-  if (in.lda == inner)
-    POGS_HIP_TRY(hipMemcpyAsync(raw, in.A, (size_t)m * n * 4, hipMemcpyHostToDevice, s_));
-  else
-    POGS_HIP_TRY(hipMemcpy2DAsync(raw, (size_t)inner * 4, in.A, (size_t)in.lda * 4, (size_t)inner * 4, outer,
-                                  hipMemcpyHostToDevice, s_));
+  // caller-provided memory was ordered for the uploader by the caller
+  POGS_HIP_TRY(host_uploader().upload_rows(raw, in.A, (size_t)inner * 4, (size_t)in.lda * 4, (size_t)outer, s_,
+                                           false, M.owned));
+  upload_pending_ = true;  // fenced before the next launch on s_ or the next free
   // functions: codes and a..e, packed into a pinned ring and copied in one
   // transfer; the ring is reused from the start once the last copy out of it
   // has completed
@@ -318,6 +318,10 @@ int GroupEngine::add(const Input &in, int *handle) {
 // Copy the descriptors added since the last upload to the device in one
 // transfer (through a pinned mirror of the descriptor array).
 int GroupEngine::flush_descriptors() {
+  if (upload_pending_) {
+    POGS_HIP_TRY(host_uploader().fence(s_));
+    upload_pending_ = false;
+  }
   int lo = cap_, hi = -1;
   for (int h = 0; h < cap_; ++h)
     if (dirty_[h]) {
@@ -341,6 +345,10 @@ int GroupEngine::flush_descriptors() {
 void GroupEngine::remove(int h) {
   if (h < 0 || h >= cap_ || !used_[h]) return;
   dirty_[h] = 0;
+  if (upload_pending_) {  // a copy into this problem's memory may still run
+    (void)host_uploader().fence(s_);
+    upload_pending_ = false;
+  }
   if (mem_[h].owned) {
     if (mem_[h].arena) (void)hipFreeAsync(mem_[h].arena, s_);
     if (mem_[h].ws) (void)hipFreeAsync(mem_[h].ws, s_);

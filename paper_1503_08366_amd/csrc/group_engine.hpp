@@ -22,7 +22,9 @@ class GroupEngine {
     const HostFn *f = nullptr, *g = nullptr;
     pogs_params params{};
     // optional caller-owned device memory (split_bytes sizes; arena zeroed);
-    // NULL: the engine allocates and frees its own
+    // NULL: the engine allocates and frees its own.  Caller-provided
+    // memory must be ready for the host uploader (host_uploader().order()
+    // on the engine's stream after it was allocated and cleared).
     void *arena = nullptr, *ws = nullptr;
   };
 
@@ -78,6 +80,7 @@ class GroupEngine {
   std::vector<char> dirty_;         // descriptors not yet on the device
   GProb *probs_host_ = nullptr;     // pinned mirror of the descriptors
   hipEvent_t desc_copied_ = nullptr;  // the last copy out of probs_host_
+  bool upload_pending_ = false;       // matrices uploaded without a fence on s_
   GProb *probs_dev_ = nullptr;
   GStatus *status_dev_ = nullptr;
   GStatus *status_host_ = nullptr;  // pinned

@@ -15,6 +15,7 @@
 #include "prox.hpp"
 #include "hostutil.hpp"
 #include "ctx.hpp"
+#include "upload.hpp"
 
 using namespace pogs;
 
@@ -89,7 +90,7 @@ template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, 
   if (mem == POGS_HOST) {
     void *stage;
     if ((rc = tmp.alloc(&stage, src_elems * selem))) return rc;
-    POGS_HIP_TRY(hipMemcpyAsync(stage, A, src_elems * selem, hipMemcpyHostToDevice, s));
+    POGS_HIP_TRY(host_uploader().upload(stage, A, src_elems * selem, s));
     src = stage;
   }
   unsigned *flags;  // [0] non-finite A, [1] factorisation failures
@@ -415,13 +416,14 @@ template <typename T> int init_sparse_impl(pogs_ctx *c, const HostCsr &a, const 
   if ((rc = c->arena.alloc(&c->sp_vat, std::max<size_t>(nnz, 1) * sizeof(T)))) return rc;
   if ((rc = c->arena.alloc(&c->sp_pair, (size_t)2 * m * sizeof(T)))) return rc;
   std::vector<T> va(a.va.begin(), a.va.end()), vat(t.va.begin(), t.va.end());
-  POGS_HIP_TRY(hipMemcpyAsync(c->sp_rp, a.rp.data(), a.rp.size() * 4, hipMemcpyHostToDevice, s));
-  POGS_HIP_TRY(hipMemcpyAsync(c->sp_rpt, t.rp.data(), t.rp.size() * 4, hipMemcpyHostToDevice, s));
+  HostUploader &up = host_uploader();
+  POGS_HIP_TRY(up.upload(c->sp_rp, a.rp.data(), a.rp.size() * 4, s));
+  POGS_HIP_TRY(up.upload(c->sp_rpt, t.rp.data(), t.rp.size() * 4, s));
   if (nnz) {
-    POGS_HIP_TRY(hipMemcpyAsync(c->sp_ci, a.ci.data(), nnz * 4, hipMemcpyHostToDevice, s));
-    POGS_HIP_TRY(hipMemcpyAsync(c->sp_cit, t.ci.data(), nnz * 4, hipMemcpyHostToDevice, s));
-    POGS_HIP_TRY(hipMemcpyAsync(c->sp_va, va.data(), nnz * sizeof(T), hipMemcpyHostToDevice, s));
-    POGS_HIP_TRY(hipMemcpyAsync(c->sp_vat, vat.data(), nnz * sizeof(T), hipMemcpyHostToDevice, s));
+    POGS_HIP_TRY(up.upload(c->sp_ci, a.ci.data(), nnz * 4, s));
+    POGS_HIP_TRY(up.upload(c->sp_cit, t.ci.data(), nnz * 4, s));
+    POGS_HIP_TRY(up.upload(c->sp_va, va.data(), nnz * sizeof(T), s));
+    POGS_HIP_TRY(up.upload(c->sp_vat, vat.data(), nnz * sizeof(T), s));
   }
   if ((rc = c->arena.alloc((void **)&c->D, (size_t)m * 8))) return rc;
   if ((rc = c->arena.alloc((void **)&c->E, (size_t)n * 8))) return rc;

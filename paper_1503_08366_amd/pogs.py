@@ -296,13 +296,7 @@ class Context:
                 import torch
                 stream = torch.cuda.current_stream()
         else:
-            if A.flags.c_contiguous:
-                order, lda = POGS_ROW_MAJOR, n
-            elif A.flags.f_contiguous:
-                order, lda = POGS_COL_MAJOR, m
-            else:
-                A = np.ascontiguousarray(A)
-                order, lda = POGS_ROW_MAJOR, n
+            A, order, lda = _host_layout(A)
             ptr, mem = A.ctypes.data, POGS_HOST
         self.stream = stream
         self.projection = int(params.projection) if params is not None else 0
@@ -488,16 +482,30 @@ class SparseContext(Context):
         self.handle = handle
 
 
+def _host_layout(A):
+    """(array, order, lda) of a host matrix: row-major or column-major with a
+    padded leading dimension goes as it is (the library packs it on upload),
+    any other layout is copied to row-major first."""
+    it = A.itemsize
+    m, n = A.shape
+    s0, s1 = A.strides
+    if s1 == it and s0 > 0 and s0 % it == 0 and s0 // it >= n:
+        return A, POGS_ROW_MAJOR, s0 // it
+    if s0 == it and s1 > 0 and s1 % it == 0 and s1 // it >= m:
+        return A, POGS_COL_MAJOR, s1 // it
+    return np.ascontiguousarray(A), POGS_ROW_MAJOR, n
+
+
 def _problem_struct(p, params: Optional[pogs_params], keep: list) -> pogs_problem:
-    A = np.ascontiguousarray(p.A)
+    A = np.asarray(p.A)
     if A.dtype != np.float32:
         raise TypeError("batched problems take float32 matrices")
+    A, order, lda = _host_layout(A)
     fh, gh = _FnHolder(p.f, A.shape[0]), _FnHolder(p.g, A.shape[1])
     keep.extend([A, fh, gh])
     prm = params if params is not None else default_params(eps_abs=p.eps_abs, eps_rel=p.eps_rel,
                                                            max_iter=p.max_iter)
-    return pogs_problem(A.shape[0], A.shape[1], A.ctypes.data, POGS_F32, POGS_ROW_MAJOR, A.shape[1],
-                        fh.s, gh.s, prm)
+    return pogs_problem(A.shape[0], A.shape[1], A.ctypes.data, POGS_F32, order, lda, fh.s, gh.s, prm)
 
 
 def _host_outputs(m: int, n: int, r: pogs_result, keep: list):

@@ -150,3 +150,26 @@ def test_serving_large_request_overlaps():
             assert eng.poll(t).converged
     finally:
         eng.close()
+
+
+def test_uploads_after_a_serving_engine_is_gone():
+    """Host uploads of 64 KB and more go through a pinned ring shared by the
+    whole process; after a serving engine that ran grouped and whole-GPU
+    requests (its threads and streams now destroyed), new contexts and batches
+    from host matrices still upload correctly."""
+    big = W.lasso(5000, 4000, 43)  # m n > 16 Mi: the whole-GPU path
+    small = _mix(6, seed=44)
+    eng = P.BatchEngine(chunk_iters=20)
+    try:
+        ts = [eng.submit(big)] + [eng.submit(p) for p in small]
+        eng.wait_all()
+        served = [eng.poll(t) for t in ts]
+    finally:
+        eng.close()
+    assert all(r.converged for r in served)
+    with P.Context(big.A) as ctx:
+        r = ctx.solve(big.f, big.g)
+    assert r.converged and r.iters == served[0].iters and r.optval == served[0].optval
+    again = P.pogs_solve_batch(small)
+    for a, b in zip(again, served[1:]):
+        assert a.iters == b.iters and a.optval == b.optval
