@@ -11,6 +11,7 @@
 // large for the grouped path, or large enough to slow every chunk, run on the
 // whole-GPU path on a second thread and stream, overlapping the chunks.
 #include <algorithm>
+#include <atomic>
 #include <cfloat>
 #include <cmath>
 #include <chrono>
@@ -40,7 +41,7 @@ double now_ms() {
 // A validated, self-contained copy of one problem (host memory).
 struct HostProblem {
   int m = 0, n = 0;
-  std::vector<float> A;  // row-major m x n
+  std::unique_ptr<float[]> A;  // row-major m x n
   HostFn f, g;
   pogs_params params{};
 };
@@ -69,17 +70,44 @@ int make_host_problem(const pogs_problem *p, HostProblem *hp) {
   hp->m = (int)p->m;
   hp->n = (int)p->n;
   hp->params = p->params;
-  hp->A.resize((size_t)p->m * p->n);
+  const int64_t m = p->m, n = p->n, lda = p->lda;
+  hp->A.reset(new (std::nothrow) float[(size_t)m * n]);  // not zero-filled: every entry is written below
+  if (!hp->A) return POGS_ENOMEM;
   const float *src = (const float *)p->A;
-  bool bad = false;
-  for (int64_t i = 0; i < p->m; ++i) {
-    float *dst = &hp->A[(size_t)i * p->n];
-    for (int64_t j = 0; j < p->n; ++j) {
-      const float v = p->ord == POGS_ROW_MAJOR ? src[i * p->lda + j] : src[j * p->lda + i];
-      bad |= !std::isfinite(v);
-      dst[j] = v;
+  float *dst = hp->A.get();
+  const bool rowmajor = p->ord == POGS_ROW_MAJOR;
+  // copy and check in one pass over row ranges, on the host pool's threads
+  // for large matrices; a non-finite float has all exponent bits set
+  const int parts = (size_t)m * n >= ((size_t)1 << 20) ? 16 : 1;
+  std::atomic<unsigned> bad{0};
+  auto body = [&](int part) {
+    const int64_t i0 = m * part / parts, i1 = m * (part + 1) / parts;
+    unsigned nb = 0;
+    for (int64_t i = i0; i < i1; ++i) {
+      float *d = dst + i * n;
+      if (rowmajor) {
+        const float *r = src + i * lda;
+        for (int64_t j = 0; j < n; ++j) {
+          const float v = r[j];
+          d[j] = v;
+          uint32_t b;
+          std::memcpy(&b, &v, 4);
+          nb |= (b & 0x7f800000u) == 0x7f800000u;
+        }
+      } else {
+        for (int64_t j = 0; j < n; ++j) {
+          const float v = src[j * lda + i];
+          d[j] = v;
+          uint32_t b;
+          std::memcpy(&b, &v, 4);
+          nb |= (b & 0x7f800000u) == 0x7f800000u;
+        }
+      }
     }
-  }
+    if (nb) bad = 1;
+  };
+  if (parts > 1) host_pool().run(parts, body);
+  else body(0);
   return bad ? POGS_EINVAL : POGS_OK;
 }
 
@@ -109,7 +137,7 @@ void fill_result(const GStatus &st, pogs_result *out, double ms_solve) {
 // Whole-GPU path for one problem (used for problems too large for a workgroup).
 int solve_large(const HostProblem &hp, pogs_result *out, hipStream_t s) {
   pogs_ctx *ctx = nullptr;
-  int rc = pogs_init(&ctx, hp.m, hp.n, hp.A.data(), POGS_F32, POGS_ROW_MAJOR, hp.n, POGS_HOST, &hp.params, s);
+  int rc = pogs_init(&ctx, hp.m, hp.n, hp.A.get(), POGS_F32, POGS_ROW_MAJOR, hp.n, POGS_HOST, &hp.params, s);
   if (rc) return rc;
   std::vector<uint8_t> fh(hp.f.h), gh(hp.g.h);
   pogs_fn f{hp.m, 1, fh.data(), hp.f.a.data(), hp.f.b.data(), hp.f.c.data(), hp.f.d.data(), hp.f.e.data()};
@@ -329,7 +357,7 @@ void pogs_batch::run() {
       GroupEngine::Input in;
       in.m = r->hp.m;
       in.n = r->hp.n;
-      in.A = r->hp.A.data();
+      in.A = r->hp.A.get();
       in.lda = r->hp.n;
       in.f = &r->hp.f;
       in.g = &r->hp.g;

@@ -26,13 +26,15 @@
 namespace pogs {
 
 // fn(p) for p in [0, parts), spread over the pool's threads and the caller;
-// returns when every part has finished.  One run at a time.
+// returns when every part has finished.  Runs from several threads take
+// turns.
 class CopyPool {
  public:
   explicit CopyPool(int workers) {
     for (int i = 0; i < workers; ++i) std::thread([this] { worker(); }).detach();
   }
   void run(int parts, const std::function<void(int)> &fn) {
+    std::lock_guard<std::mutex> one(run_mu_);  // callers on several threads take turns
     std::unique_lock<std::mutex> lk(mu_);
     fn_ = &fn;
     parts_ = parts;
@@ -63,7 +65,7 @@ class CopyPool {
       if (--left_ == 0) done_.notify_all();
     }
   }
-  std::mutex mu_;
+  std::mutex run_mu_, mu_;
   std::condition_variable cv_, done_;
   const std::function<void(int)> *fn_ = nullptr;
   int parts_ = 0, next_ = 0, left_ = 0;
@@ -196,6 +198,13 @@ class HostUploader {
   hipEvent_t start_ = nullptr, done_ = nullptr;
   CopyPool *pool_ = nullptr;
 };
+
+// A pool for other host-side copies (the serving engine's private copy of
+// each request), separate from the uploader's so the two run side by side.
+inline CopyPool &host_pool() {
+  static CopyPool *p = new CopyPool(3);
+  return *p;
+}
 
 // One uploader per process (never destroyed: its threads and pinned ring
 // outlive every context).

@@ -173,3 +173,45 @@ def test_uploads_after_a_serving_engine_is_gone():
     again = P.pogs_solve_batch(small)
     for a, b in zip(again, served[1:]):
         assert a.iters == b.iters and a.optval == b.optval
+
+
+def _pad_rows(A, pad):
+    big = np.zeros((A.shape[0], A.shape[1] + pad), dtype=A.dtype)
+    big[:, :A.shape[1]] = A
+    return big[:, :A.shape[1]]
+
+
+def _pad_cols(A, pad):
+    big = np.zeros((A.shape[0] + pad, A.shape[1]), dtype=A.dtype, order="F")
+    big[:A.shape[0]] = A
+    return big[:A.shape[0]]
+
+
+def test_serving_submit_copies_layouts_and_rejects_non_finite():
+    """pogs_batch_submit keeps its own row-major copy of the request (from
+    row-major or column-major input, padded or not; 1.35 M entries take the
+    threaded copy) and rejects non-finite entries anywhere."""
+    import dataclasses
+    p = W.lasso(1500, 900, 45)
+    variants = [p, dataclasses.replace(p, A=_pad_rows(p.A, 13)), dataclasses.replace(p, A=np.asfortranarray(p.A)),
+                dataclasses.replace(p, A=_pad_cols(p.A, 7))]
+    small = W.lasso(50, 20, 46)
+    eng = P.BatchEngine(chunk_iters=20)
+    try:
+        ts = [eng.submit(v) for v in variants]
+        eng.wait_all()
+        rs = [eng.poll(t) for t in ts]
+        for q, at, val in ((p, (0, 0), np.nan), (p, (1499, 899), np.inf), (p, (700, 3), -np.inf),
+                           (small, (3, 4), np.nan)):
+            for layout in (np.ascontiguousarray, np.asfortranarray):
+                A = layout(q.A.copy())
+                A[at] = val
+                with pytest.raises(P.PogsError) as ei:
+                    eng.submit(dataclasses.replace(q, A=A))
+                assert ei.value.code == P.POGS_EINVAL
+    finally:
+        eng.close()
+    assert rs[0].converged
+    for r in rs[1:]:
+        assert r.iters == rs[0].iters and r.optval == rs[0].optval
+        np.testing.assert_array_equal(r.x, rs[0].x)
