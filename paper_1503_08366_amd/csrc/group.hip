@@ -315,12 +315,12 @@ void launch_group(int phase, const GProb *probs, const GItem *items, int count, 
     case G_KINV: hipLaunchKernelGGL(g_kinv, grid, blk, 0, s, probs, items); break;
     case G_PROX: hipLaunchKernelGGL(g_prox, grid, blk, 0, s, probs, items, arg); break;
     case G_PASS1_T: hipLaunchKernelGGL(g_pass1_t, grid, blk, 0, s, probs, items, arg); break;
-    case G_PASS1_W64: hipLaunchKernelGGL((g_pass1_w<64, 2>), grid, blk, 0, s, probs, items, arg); break;
+    case G_PASS1_W64: hipLaunchKernelGGL((g_pass1_w<64, 4>), grid, blk, 0, s, probs, items, arg); break;
     case G_PASS1_W16: hipLaunchKernelGGL((g_pass1_w<16, 4>), grid, blk, 0, s, probs, items, arg); break;
     case G_FINISH1: hipLaunchKernelGGL(g_finish1, grid, blk, 0, s, probs, items, arg); break;
-    case G_SOLVE64: hipLaunchKernelGGL((g_solve<64, 2>), grid, blk, 0, s, probs, items, arg); break;
+    case G_SOLVE64: hipLaunchKernelGGL((g_solve<64, 4>), grid, blk, 0, s, probs, items, arg); break;
     case G_SOLVE16: hipLaunchKernelGGL((g_solve<16, 4>), grid, blk, 0, s, probs, items, arg); break;
-    case G_PASS2_T64: hipLaunchKernelGGL((g_pass2_t<64, 2>), grid, blk, 0, s, probs, items, arg); break;
+    case G_PASS2_T64: hipLaunchKernelGGL((g_pass2_t<64, 4>), grid, blk, 0, s, probs, items, arg); break;
     case G_PASS2_T16: hipLaunchKernelGGL((g_pass2_t<16, 4>), grid, blk, 0, s, probs, items, arg); break;
     case G_PASS2_W: hipLaunchKernelGGL(g_pass2_w, grid, blk, 0, s, probs, items, arg); break;
     case G_FINISH2: hipLaunchKernelGGL(g_finish2, grid, blk, 0, s, probs, items, arg); break;

@@ -89,7 +89,7 @@ enum GPhase : int {
 };
 
 // Rows per workgroup of the row-dot passes in each variant.
-constexpr int kGRows64 = 8;   // 64 lanes per row, 2 rows per wave
+constexpr int kGRows64 = 16;  // 64 lanes per row, 4 rows per wave
 constexpr int kGRows16 = 64;  // 16 lanes per row, 4 rows per lane group
 
 void launch_group(int phase, const GProb *probs, const GItem *items, int count, int arg, hipStream_t s);

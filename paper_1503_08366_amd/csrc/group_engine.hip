@@ -51,7 +51,7 @@ Geo geo(int m, int n) {
   g.lpr16 = g.ld < 512;
   g.lpr16k = g.ldk < 512;
   g.tiles = (int)cdiv(n, 256);
-  g.rps = (int)std::max<int64_t>(32, round_up(cdiv(m, 128), 4));
+  g.rps = (int)std::max<int64_t>(128, round_up(cdiv(m, 64), 4));  // 32+ rows per wave: the 8-deep load loop runs
   g.splits = (int)cdiv(m, g.rps);
   g.ncolp = g.tiles * 256;
   g.nbx = (int)cdiv(n, kBlock);
