@@ -37,8 +37,11 @@ struct DevArena {
       ptrs.erase(it);
     }
   }
+  // Last allocated first: freeing a large block ahead of smaller ones made
+  // the next free take 0.3-1.2 ms in the stream-ordered pool (measured on
+  // MI355X); in reverse order every free takes tens of microseconds.
   void free_all() {
-    for (void *p : ptrs) (void)hipFreeAsync(p, stream);
+    for (auto it = ptrs.rbegin(); it != ptrs.rend(); ++it) (void)hipFreeAsync(*it, stream);
     ptrs.clear();
   }
   ~DevArena() { free_all(); }

@@ -620,14 +620,19 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   *c->ctrl_host = h;
   POGS_HIP_TRY(hipMemcpyAsync(c->ctrl, c->ctrl_host, sizeof(Ctrl), hipMemcpyHostToDevice, s));
   const int chunk = even_chunk(p.chunk_iters);
-  // Without a graph for this chunk size yet, the first chunk is launched
-  // directly and the graph is captured while the GPU runs it.
-  bool eager = !(c->graph && c->graph_chunk == chunk && c->graph_cg_cap == cg_cap && c->graph_gap == gap);
+  // Large problems launch every chunk directly: an iteration keeps the GPU
+  // busy longer than the host takes to issue it, and a graph would only add
+  // its capture and, at pogs_free, its destruction (about 1 ms for a chunk of
+  // 20 iterations).  Smaller ones replay a graph; without one for this chunk
+  // size yet, the first chunk is launched directly and the graph is captured
+  // while the GPU runs it.
+  const bool direct = c->sparse ? c->nnz >= ((int64_t)1 << 22) : (double)c->m * (double)c->n >= 16.0 * (1 << 20);
+  bool eager = direct || !(c->graph && c->graph_chunk == chunk && c->graph_cg_cap == cg_cap && c->graph_gap == gap);
   for (;;) {
     if (eager) launch_chunk<T>(c, chunk, cg_cap, gap, s);
     else POGS_HIP_TRY(hipGraphLaunch(c->graph, s));
     POGS_HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-    if (eager) {
+    if (eager && !direct) {
       if ((rc = ensure_graph<T>(c, chunk, cg_cap, gap))) return rc;
       eager = false;
     }
