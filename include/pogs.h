@@ -317,8 +317,8 @@ typedef struct pogs_batch pogs_batch;
  * slot count allow, set up together, and advanced in chunks of chunk_iters
  * iterations as one group; finished ones leave after each chunk and queued
  * ones join.  Requests too large for the group (see pogs_solve_batch) or with
- * m n > 16 Mi or min(m, n) > 2048 run on the whole-GPU path on a second
- * thread and stream.  cfg may be NULL.  POGS_EAGAIN if the engine's own
+ * m n > 16 Mi or min(m, n) > 2048 run on the whole-GPU path on two more
+ * threads, each with its own stream.  cfg may be NULL.  POGS_EAGAIN if the engine's own
  * arrays do not fit the budget. */
 int pogs_batch_create(pogs_batch **out, const pogs_batch_cfg *cfg);
 

@@ -9,7 +9,7 @@
 // returned and their memory released after each chunk, so requests that
 // arrive while others are on the GPU join at the next chunk.  Problems too
 // large for the grouped path, or large enough to slow every chunk, run on the
-// whole-GPU path on a second thread and stream, overlapping the chunks.
+// whole-GPU path on two more threads (one stream each), overlapping the chunks.
 #include <algorithm>
 #include <atomic>
 #include <cfloat>
@@ -293,7 +293,10 @@ struct Request {
 
 struct pogs_batch {
   pogs_batch_cfg cfg{};
-  hipStream_t stream = nullptr, solo_stream = nullptr;
+  // requests for the whole-GPU path run on kSolo threads, each with its own
+  // stream, so a short one does not wait behind a long one
+  static constexpr int kSolo = 2;
+  hipStream_t stream = nullptr, solo_stream[kSolo] = {};
   bool own_stream = false;
   std::mutex mu;
   std::condition_variable cv, cv_done;
@@ -305,11 +308,11 @@ struct pogs_batch {
   size_t budget = 0, used = 0, fixed = 0;
   int pending = 0;
   std::unique_ptr<GroupEngine> eng;
-  std::thread worker, solo;
+  std::thread worker, solo[kSolo];
   int error = 0;
 
   void run();
-  void run_solo();
+  void run_solo(int w);
   void finish(const std::shared_ptr<Request> &r, int status_override);
 };
 
@@ -432,7 +435,7 @@ void pogs_batch::run() {
   }
 }
 
-void pogs_batch::run_solo() {
+void pogs_batch::run_solo(int w) {
   for (;;) {
     std::shared_ptr<Request> r;
     {
@@ -460,7 +463,7 @@ void pogs_batch::run_solo() {
     r->res.y = r->yo.data();
     r->res.mu = r->muo.data();
     r->res.nu = r->nuo.data();
-    const int rc = solve_large(r->hp, &r->res, solo_stream);
+    const int rc = solve_large(r->hp, &r->res, solo_stream[w]);
     r->res.ms_solve = now_ms() - r->t_submit;
     finish(r, rc ? POGS_NUMERICAL : -1);
   }
@@ -480,7 +483,8 @@ extern "C" int pogs_batch_create(pogs_batch **out, const pogs_batch_cfg *cfg) {
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) return POGS_EDEVICE;
     b->own_stream = true;
   }
-  if (hipStreamCreateWithFlags(&b->solo_stream, hipStreamNonBlocking) != hipSuccess) return POGS_EDEVICE;
+  for (int w = 0; w < pogs_batch::kSolo; ++w)
+    if (hipStreamCreateWithFlags(&b->solo_stream[w], hipStreamNonBlocking) != hipSuccess) return POGS_EDEVICE;
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return POGS_EDEVICE;
   b->budget = b->cfg.hbm_budget_bytes ? b->cfg.hbm_budget_bytes : (size_t)(0.8 * (double)fr);
@@ -493,7 +497,7 @@ extern "C" int pogs_batch_create(pogs_batch **out, const pogs_batch_cfg *cfg) {
   int rc;
   if ((rc = b->eng->init())) return rc;
   b->worker = std::thread([p = b.get()] { p->run(); });
-  b->solo = std::thread([p = b.get()] { p->run_solo(); });
+  for (int w = 0; w < pogs_batch::kSolo; ++w) b->solo[w] = std::thread([p = b.get(), w] { p->run_solo(w); });
   *out = b.release();
   return POGS_OK;
 }
@@ -583,12 +587,14 @@ extern "C" int pogs_batch_destroy(pogs_batch *b) {
     b->cv.notify_all();
   }
   if (b->worker.joinable()) b->worker.join();
-  if (b->solo.joinable()) b->solo.join();
+  for (auto &t : b->solo)
+    if (t.joinable()) t.join();
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  if (b->solo_stream) {
-    (void)hipStreamSynchronize(b->solo_stream);
-    (void)hipStreamDestroy(b->solo_stream);
-  }
+  for (hipStream_t &ss : b->solo_stream)
+    if (ss) {
+      (void)hipStreamSynchronize(ss);
+      (void)hipStreamDestroy(ss);
+    }
   b->eng.reset();
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
