@@ -171,60 +171,71 @@ struct EpiPass2 {  // [Y | T] = A [X | Xh]
   }
 };
 
-// One thread per problem: stopping test and Algorithm 3 on its own residuals.
-__global__ void path_control_kernel(PathArgs p) {
+// One workgroup per problem r: its four residual sums over the block slots
+// (a strided share per thread, then a fixed-order tree), then thread 0 runs
+// the stopping test and Algorithm 3 on its own residuals.
+__global__ __launch_bounds__(256) void path_control_kernel(PathArgs p) {
+  __shared__ double scratch[256 / kWave];
+  const int r = blockIdx.x;
+  if (*p.all_done || p.done[r]) return;  // the same for the whole workgroup
+  double mu2 = 0.0, yh2 = 0.0, pri2 = 0.0, dual2 = 0.0;
+  for (int b = threadIdx.x; b < p.nbx; b += blockDim.x) mu2 += p.s_mu[(size_t)b * p.Rp + r];
+  for (int b = threadIdx.x; b < p.nby; b += blockDim.x) yh2 += p.s_yh[(size_t)b * p.Rp + r];
+  for (int b = threadIdx.x; b < p.nb_pri; b += blockDim.x) pri2 += p.s_pri[(size_t)b * p.Rp + r];
+  for (int b = threadIdx.x; b < p.nb_dual; b += blockDim.x) dual2 += p.s_dual[(size_t)b * p.Rp + r];
+  mu2 = block_sum(mu2, scratch);
+  yh2 = block_sum(yh2, scratch);
+  pri2 = block_sum(pri2, scratch);
+  dual2 = block_sum(dual2, scratch);
+  if (threadIdx.x != 0) return;
+  const double r_pri = sqrt(pri2), r_dual = sqrt(dual2);
+  const double eps_pri = p.eps_abs + p.eps_rel * sqrt(yh2);
+  const double eps_dual = p.eps_abs + p.eps_rel * sqrt(mu2);
+  p.r_pri[r] = r_pri;
+  p.r_dual[r] = r_dual;
+  p.eps_pri[r] = eps_pri;
+  p.eps_dual[r] = eps_dual;
+  const int k = p.iters[r];
+  double rescale = 1.0;
+  int status = -1;
+  if (!isfinite(r_pri) || !isfinite(r_dual)) {
+    status = POGS_NUMERICAL;
+  } else if (r_pri < eps_pri && r_dual < eps_dual) {
+    status = POGS_CONVERGED;
+  } else {
+    if (p.adaptive) {
+      const double r0 = p.rho[r];
+      double r1 = r0;
+      if (r_dual < eps_dual && p.tau * k > p.l[r]) {
+        r1 = p.delta * r0;
+        p.u[r] = k;
+      } else if (r_pri < eps_pri && p.tau * k > p.u[r]) {
+        r1 = r0 / p.delta;
+        p.l[r] = k;
+      }
+      if (r1 != r0) {
+        rescale = r0 / r1;
+        p.rho[r] = r1;
+      }
+    }
+    if (k + 1 >= p.max_iter) status = POGS_MAXITER;
+  }
+  p.rescale[r] = rescale;
+  p.iters[r] = k + 1;
+  if (status >= 0) {
+    p.status[r] = status;
+    p.done[r] = 1;
+  }
+}
+
+// Sets all_done once every problem has stopped (after the control step).
+__global__ void path_alldone_kernel(PathArgs p) {
   __shared__ int live;
   if (*p.all_done) return;
   if (threadIdx.x == 0) live = 0;
   __syncthreads();
-  for (int r = threadIdx.x; r < p.R; r += blockDim.x) {
-    if (p.done[r]) continue;
-    double mu2 = 0.0, yh2 = 0.0, pri2 = 0.0, dual2 = 0.0;
-    for (int b = 0; b < p.nbx; ++b) mu2 += p.s_mu[(size_t)b * p.Rp + r];
-    for (int b = 0; b < p.nby; ++b) yh2 += p.s_yh[(size_t)b * p.Rp + r];
-    for (int b = 0; b < p.nb_pri; ++b) pri2 += p.s_pri[(size_t)b * p.Rp + r];
-    for (int b = 0; b < p.nb_dual; ++b) dual2 += p.s_dual[(size_t)b * p.Rp + r];
-    const double r_pri = sqrt(pri2), r_dual = sqrt(dual2);
-    const double eps_pri = p.eps_abs + p.eps_rel * sqrt(yh2);
-    const double eps_dual = p.eps_abs + p.eps_rel * sqrt(mu2);
-    p.r_pri[r] = r_pri;
-    p.r_dual[r] = r_dual;
-    p.eps_pri[r] = eps_pri;
-    p.eps_dual[r] = eps_dual;
-    const int k = p.iters[r];
-    double rescale = 1.0;
-    int status = -1;
-    if (!isfinite(r_pri) || !isfinite(r_dual)) {
-      status = POGS_NUMERICAL;
-    } else if (r_pri < eps_pri && r_dual < eps_dual) {
-      status = POGS_CONVERGED;
-    } else {
-      if (p.adaptive) {
-        const double r0 = p.rho[r];
-        double r1 = r0;
-        if (r_dual < eps_dual && p.tau * k > p.l[r]) {
-          r1 = p.delta * r0;
-          p.u[r] = k;
-        } else if (r_pri < eps_pri && p.tau * k > p.u[r]) {
-          r1 = r0 / p.delta;
-          p.l[r] = k;
-        }
-        if (r1 != r0) {
-          rescale = r0 / r1;
-          p.rho[r] = r1;
-        }
-      }
-      if (k + 1 >= p.max_iter) status = POGS_MAXITER;
-    }
-    p.rescale[r] = rescale;
-    p.iters[r] = k + 1;
-    if (status >= 0) {
-      p.status[r] = status;
-      p.done[r] = 1;
-    } else {
-      atomicAdd(&live, 1);
-    }
-  }
+  for (int r = threadIdx.x; r < p.R; r += blockDim.x)
+    if (!p.done[r]) atomicAdd(&live, 1);
   __syncthreads();
   if (threadIdx.x == 0 && live == 0) *p.all_done = 1;
 }
@@ -328,7 +339,8 @@ void launch_path_iteration(const PathArgs &p, float *part, hipStream_t s) {
   gemm<false>(p.A, p.ld, m, p.XX, N2, N2, n, part, s3, p.all_done, s);
   hipLaunchKernelGGL(path_reduce_kernel<EpiPass2>, dim3(cols.x, p.nb_pri), dim3(256), 0, s, p, (const float *)part,
                      actual_splits(n, s3), m, N2, p.rows_per_block, EpiPass2{});
-  hipLaunchKernelGGL(path_control_kernel, dim3(1), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(path_control_kernel, dim3(p.R), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(path_alldone_kernel, dim3(1), dim3(256), 0, s, p);
 }
 
 void launch_path_unscale(const PathArgs &p, const double *D, const double *E, const double *f0, const uint8_t *fh0,

@@ -3,6 +3,7 @@
 // stopped.  Host side: packing the per-problem functions column-interleaved,
 // state allocation, graph-captured iteration chunks, results.
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <cmath>
 #include <vector>
@@ -10,6 +11,7 @@
 #include "ctx.hpp"
 #include "hostutil.hpp"
 #include "path.hpp"
+#include "upload.hpp"
 
 using namespace pogs;
 
@@ -20,20 +22,30 @@ double now_ms() {
 }
 
 // Per-problem functions packed as [len][Rp] (problem index fastest), float64
-// a, b, c, d, e planes followed by the h codes.
+// a, b, c, d, e planes followed by the h codes; element ranges on the host
+// pool's threads, writes contiguous over the problems.
 void pack_fns(const std::vector<HostFn> &fs, int len, int Rp, std::vector<double> *prm, std::vector<uint8_t> *h) {
   const size_t tot = (size_t)len * Rp;
   prm->assign(5 * tot, 0.0);
   h->assign(tot, 0);
-  for (size_t r = 0; r < fs.size(); ++r) {
-    const HostFn &F = fs[r];
-    const std::vector<double> *arr[5] = {&F.a, &F.b, &F.c, &F.d, &F.e};
-    for (int i = 0; i < len; ++i) {
-      const size_t e = (size_t)i * Rp + r;
-      for (int k = 0; k < 5; ++k) (*prm)[k * tot + e] = (*arr[k])[i];
-      (*h)[e] = F.h[i];
+  const int R = (int)fs.size(), parts = len >= 4096 ? 16 : 1;
+  auto body = [&](int part) {
+    const int i0 = (int)((int64_t)len * part / parts), i1 = (int)((int64_t)len * (part + 1) / parts);
+    for (int i = i0; i < i1; ++i) {
+      const size_t e0 = (size_t)i * Rp;
+      for (int r = 0; r < R; ++r) {
+        const HostFn &F = fs[r];
+        (*prm)[e0 + r] = F.a[i];
+        (*prm)[tot + e0 + r] = F.b[i];
+        (*prm)[2 * tot + e0 + r] = F.c[i];
+        (*prm)[3 * tot + e0 + r] = F.d[i];
+        (*prm)[4 * tot + e0 + r] = F.e[i];
+        (*h)[e0 + r] = F.h[i];
+      }
     }
-  }
+  };
+  if (parts > 1) host_pool().run(parts, body);
+  else body(0);
 }
 
 }  // namespace
@@ -59,8 +71,10 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
   const int Rp = (int)round_up(R, 64);
   std::vector<double> fprm, gprm;
   std::vector<uint8_t> fhh, ghh;
+  const double t_expand = now_ms();
   pack_fns(hf, m, Rp, &fprm, &fhh);
   pack_fns(hg, n, Rp, &gprm, &ghh);
+  const double t_pack = now_ms();
 
   PathArgs p{};
   p.m = m;
@@ -70,7 +84,7 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
   p.ldk = ctx->ldk;
   p.R = R;
   p.Rp = Rp;
-  p.rows_per_block = 64;
+  p.rows_per_block = 8;  // many small blocks: the split-K sums run in parallel
   p.nbx = (int)cdiv(n, p.rows_per_block);
   p.nby = (int)cdiv(m, p.rows_per_block);
   p.nb_pri = p.nby;
@@ -161,6 +175,7 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
     POGS_HIP_TRY(hipStreamSynchronize(s));
   }
   // iterate in captured chunks until every problem has stopped
+  const double t_upload = now_ms();
   const int chunk = std::max(1, prm.chunk_iters > 0 ? prm.chunk_iters : 20);
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -172,6 +187,7 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
     return POGS_EDEVICE;
   }
   (void)hipGraphDestroy(graph);
+  const double t_capture = now_ms();
   int all_done = 0;
   int guard = 0;
   const int max_launches = (int)cdiv(prm.max_iter, chunk) + 1;
@@ -180,25 +196,62 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
     if (hipMemcpyAsync(&all_done, p.all_done, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) break;
     if (hipStreamSynchronize(s) != hipSuccess) break;
   }
+  const double t_iter = now_ms();
   (void)hipGraphExecDestroy(exec);
   POGS_HIP_TRY(hipGetLastError());
+  const double t_destroy = now_ms();
   launch_path_unscale(p, ctx->D, ctx->E, f0, fh0, g0, gh0, outs, obj, s);
   std::vector<double> hc(6 * (size_t)Rp), hobj(Rp);
   std::vector<int> hi(5 * (size_t)Rp);
   POGS_HIP_TRY(hipMemcpyAsync(hc.data(), percol, hc.size() * 8, hipMemcpyDeviceToHost, s));
   POGS_HIP_TRY(hipMemcpyAsync(hi.data(), ints, hi.size() * 4, hipMemcpyDeviceToHost, s));
   POGS_HIP_TRY(hipMemcpyAsync(hobj.data(), obj, (size_t)Rp * 8, hipMemcpyDeviceToHost, s));
+  // host outputs: the R result blocks in one copy to pinned memory, then
+  // scattered on the host; device outputs: copies on the device
+  const size_t blk = 2 * (size_t)(m + n);
+  bool any_host = false;
+  for (int r = 0; r < R; ++r) any_host |= out[r].mem == POGS_HOST;
+  float *staged = nullptr;
+  if (any_host) {
+    staged = (float *)pinned_stage().acquire((size_t)R * blk * 4);
+    if (!staged) return POGS_ENOMEM;
+    const hipError_t e = hipMemcpyAsync(staged, outs, (size_t)R * blk * 4, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) {
+      pinned_stage().release(s);
+      return POGS_EDEVICE;
+    }
+  }
   for (int r = 0; r < R; ++r) {
-    const float *o = outs + (size_t)r * 2 * (m + n);
-    const hipMemcpyKind k = out[r].mem == POGS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (out[r].mem != POGS_DEVICE) continue;
+    const float *o = outs + (size_t)r * blk;
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
     if (out[r].x) POGS_HIP_TRY(hipMemcpyAsync(out[r].x, o, (size_t)n * 4, k, s));
     if (out[r].y) POGS_HIP_TRY(hipMemcpyAsync(out[r].y, o + n, (size_t)m * 4, k, s));
     if (out[r].mu) POGS_HIP_TRY(hipMemcpyAsync(out[r].mu, o + n + m, (size_t)n * 4, k, s));
     if (out[r].nu) POGS_HIP_TRY(hipMemcpyAsync(out[r].nu, o + 2 * n + m, (size_t)m * 4, k, s));
   }
-  POGS_HIP_TRY(hipStreamSynchronize(s));
+  const hipError_t se = hipStreamSynchronize(s);
+  if (any_host) {
+    if (se == hipSuccess)
+      for (int r = 0; r < R; ++r) {
+        if (out[r].mem != POGS_HOST) continue;
+        const float *o = staged + (size_t)r * blk;
+        if (out[r].x) std::memcpy(out[r].x, o, (size_t)n * 4);
+        if (out[r].y) std::memcpy(out[r].y, o + n, (size_t)m * 4);
+        if (out[r].mu) std::memcpy(out[r].mu, o + n + m, (size_t)n * 4);
+        if (out[r].nu) std::memcpy(out[r].nu, o + 2 * n + m, (size_t)m * 4);
+      }
+    pinned_stage().release(s);
+  }
+  POGS_HIP_TRY(se);
   POGS_HIP_TRY(hipGetLastError());
   const double ms = now_ms() - t0;
+  if (prm.verbose)
+    fprintf(stderr,
+            "pogs path: %d problems: expand %.1f ms, pack %.1f ms, upload and scale %.1f ms, capture %.1f ms, "
+            "iterations %.1f ms, graph destroy %.1f ms, results %.1f ms\n",
+            R, t_expand - t0, t_pack - t_expand, t_upload - t_pack, t_capture - t_upload, t_iter - t_capture,
+            t_destroy - t_iter, now_ms() - t_destroy);
   for (int r = 0; r < R; ++r) {
     out[r].optval = hobj[r];
     out[r].rho = hc[r];
