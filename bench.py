@@ -107,7 +107,7 @@ def bench_batch(args):
     from paper_1503_08366_amd import pogs as P
     from paper_1503_08366_amd import workloads as W
     probs = W.batch_mix(count=args.count)
-    P.pogs_solve_batch(probs[:8])  # warm
+    P.pogs_solve_batch(probs)  # warm at full size (device memory pool, pinned ring)
     t = time.perf_counter()
     res = P.pogs_solve_batch(probs)
     tb = time.perf_counter() - t
