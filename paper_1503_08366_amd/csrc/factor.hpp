@@ -151,7 +151,7 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
 template <bool A_T, class Out>
 __device__ void gemm_tile_f32(const float *__restrict__ A, int lda, int M, const float *__restrict__ B, int ldb,
                               int N, int i0, int j0, int k0, int k1, GramStage &st, Out out) {
-  constexpr int TB = kGramTB, KC = 16;
+  constexpr int KC = 16;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = w >> 1, wj = w & 1;
   typedef float f4 __attribute__((ext_vector_type(4)));
