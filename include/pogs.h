@@ -139,8 +139,10 @@ typedef struct {
   int32_t autotune;      /* 1 (default): pogs_init times the load policy of the
                             passes over A (cached or non-temporal loads, for the
                             row passes and the column passes) on the projection
-                            (pass 1, solve, pass 2) of the context's shape and
-                            keeps the fastest; the choice is cached per
+                            (pass 1, solve, pass 2) of the context's shape,
+                            interleaved over four rounds, and keeps the fastest
+                            if it beats the size rule's policy (that of
+                            autotune = 0) by 2 %; the choice is cached per
                             (m, n, dtype) in the process and changes no result
                             bit.  0: a matrix above 192 MB streams, others cache. */
   int32_t sparse_segment; /* pogs_init_sparse only: columns of A^T per segment

@@ -94,6 +94,10 @@ void gemv_t_geometry(int m, int ncols, int elem_size, int *splits, int *rows_per
   const int tile = gemv_t_tile(elem_size);
   const int tiles = (int)cdiv(ncols, tile);
   int s = std::max(1, std::min((int)cdiv(m, 16), 1024 / std::max(tiles, 1)));
+  // splits shorter than 256 rows cost more in partials and their finish than
+  // they gain in parallelism while more than 512 workgroups remain (measured on
+  // gfx950: 20000 x 2000 pass 1 29.9 -> 28.7 us; 100000 x 1000 keeps 256 splits)
+  while (s > 1 && m / s < 256 && s * tiles > 512) s = (s + 1) / 2;
   int rps = (int)cdiv(m, s);
   rps = (int)round_up(rps, 4);
   s = (int)cdiv(m, rps);
