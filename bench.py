@@ -307,8 +307,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": 4 * n, "copies": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU sharding "
+              "of the path is designed but not built", file=sys.stderr)
         sys.exit(2)
     if args.workload in ("batch", "path", "serve", "sparse"):
         import torch
@@ -378,7 +378,7 @@ def main():
         kern_desc = "CG step (A p, A^T [r1, q]: three launches)"
         iter_bytes = None
     else:
-        vec_bytes = {  # float32 vectors read + written per launch (see DESIGN.md)
+        vec_bytes = {  # float32 vectors read + written per launch
             "pass1": (2 * m + 3 * n) * 4 if tall else (2 * n + 3 * m) * 4,
             "pass2": (2 * n + 4 * m) * 4 if tall else (2 * m + 4 * n) * 4,
         }
