@@ -124,18 +124,16 @@ template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, 
   const int Q = c->Q;
   double *K;
   if ((rc = tmp.alloc((void **)&K, (size_t)Q * Q * 8))) return rc;
-  {
-    const size_t gb = gram_workspace_bytes(m, n, sizeof(T));
-    void *gws;
-    if ((rc = tmp.alloc(&gws, gb))) return rc;
-    if ((rc = run_gram<T>((const T *)c->A, m, n, c->ld, K, Q, (float *)gws, (double *)gws, gb, s))) return rc;
-    tmp.release(gws);
-  }
   if ((rc = c->arena.alloc(&c->Kinv, (size_t)c->q * c->ldk * sizeof(T)))) return rc;
   {
-    double *fws;
-    if ((rc = tmp.alloc((void **)&fws, ((size_t)Q * Q + (size_t)Q * 64) * 8))) return rc;
-    if ((rc = run_factor_inverse<T>(K, c->q, Q, (T *)c->Kinv, c->ldk, fws, flags + 1, s))) return rc;
+    // one block serves the Gram partials, then the factor's workspace
+    // (stream order separates the two uses)
+    const size_t gb = gram_workspace_bytes(m, n, sizeof(T));
+    const size_t fb = ((size_t)Q * Q + (size_t)Q * 64) * 8;
+    void *ws;
+    if ((rc = tmp.alloc(&ws, std::max(gb, fb)))) return rc;
+    if ((rc = run_gram<T>((const T *)c->A, m, n, c->ld, K, Q, (float *)ws, (double *)ws, gb, s))) return rc;
+    if ((rc = run_factor_inverse<T>(K, c->q, Q, (T *)c->Kinv, c->ldk, (double *)ws, flags + 1, s))) return rc;
   }
   unsigned hflags[2] = {0, 0};
   POGS_HIP_TRY(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));

@@ -191,7 +191,7 @@ int run_equilibrate(T *A, int m, int n, int ld, int iters, double eps_cmp, doubl
 // ---------------------------------------------------------------------------
 // G tile (ti, tj) partial over the K range of split blockIdx.y (f32 MFMA).
 template <bool TALL>
-__global__ __launch_bounds__(256) void gram_f32_kernel(const float *__restrict__ A, int m, int n, int ld,
+__global__ __launch_bounds__(256, 4) void gram_f32_kernel(const float *__restrict__ A, int m, int n, int ld,
                                                        int kchunk, int ntp, float *__restrict__ part) {
   __shared__ GramStage st;
   int ti, tj;
@@ -255,20 +255,39 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
 }
 
 // K = I + sum_splits partials, full symmetric Q x Q (identity in the padding).
+// One workgroup per 64 x 64 sub-block of a lower tile: its sums are staged
+// in LDS and written twice, as they are (lower half) and transposed (upper
+// half), so every write runs along a row of K and both halves hold the same
+// bits (those of the lower element).  Sub-blocks wholly above the diagonal
+// of a diagonal tile are written by their mirror.
 template <typename P>
-__global__ void gram_reduce_kernel(const P *part, int splits, int ntp, int TB, int q, int Q, double *K) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j >= Q) return;
-  double v = (i == j) ? 1.0 : 0.0;
-  if (i < q && j < q) {
-    const int a = max(i, j), b = min(i, j);
-    const int ti = a / TB, tj = b / TB;
-    const int tp = ti * (ti + 1) / 2 + tj;
-    const int ri = a % TB, cj = b % TB;
-    for (int s = 0; s < splits; ++s) v += (double)part[((size_t)s * ntp + tp) * TB * TB + ri * TB + cj];
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const P *part, int splits, int ntp, int TB, int q, int Q,
+                                                          double *K) {
+  __shared__ double tile[64][65];
+  const int per = TB / 64, subs = per * per;
+  const int tp = blockIdx.x / subs, sub = blockIdx.x % subs;
+  int ti, tj;
+  tri_index(tp, &ti, &tj);
+  const int si = sub / per, sj = sub % per;
+  const int i0 = ti * TB + si * 64, j0 = tj * TB + sj * 64;
+  if ((ti == tj && si < sj) || i0 >= Q) return;  // uniform over the workgroup
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const P *src = part + (size_t)tp * TB * TB + (size_t)si * 64 * TB + sj * 64;
+  const size_t sstride = (size_t)ntp * TB * TB;
+  for (int r = ty; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + tx;
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < q && j < q)
+      for (int s = 0; s < splits; ++s) v += (double)src[s * sstride + (size_t)r * TB + tx];
+    tile[r][tx] = v;
   }
-  K[(size_t)i * Q + j] = v;
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + tx;
+    if (i < Q && j < Q && i >= j) K[(size_t)i * Q + j] = tile[r][tx];
+    const int it = i0 + tx, jt = j0 + r;  // element (it, jt) of the lower half, stored at (jt, it)
+    if (it < Q && jt < Q && it > jt) K[(size_t)jt * Q + it] = tile[tx][r];
+  }
 }
 
 static void gram_geometry(int m, int n, int elem_size, int *TB, int *ntp, int *splits, int *kchunk) {
@@ -312,14 +331,14 @@ int run_gram(const T *A, int m, int n, int ld, double *K, int Q, float *ws32, do
       hipLaunchKernelGGL(gram_f32_kernel<true>, grid, dim3(256), 0, s, (const float *)A, m, n, ld, kchunk, ntp, ws32);
     else
       hipLaunchKernelGGL(gram_f32_kernel<false>, grid, dim3(256), 0, s, (const float *)A, m, n, ld, kchunk, ntp, ws32);
-    hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3(cdiv(Q, 256), Q), dim3(256), 0, s, ws32, splits, ntp, TB, q,
+    hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3(ntp * (TB / 64) * (TB / 64)), dim3(256), 0, s, ws32, splits, ntp, TB, q,
                        Q, K);
   } else {
     if (tall)
       hipLaunchKernelGGL(gram_f64_kernel<true>, grid, dim3(256), 0, s, (const double *)A, m, n, ld, kchunk, ntp, ws64);
     else
       hipLaunchKernelGGL(gram_f64_kernel<false>, grid, dim3(256), 0, s, (const double *)A, m, n, ld, kchunk, ntp, ws64);
-    hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3(cdiv(Q, 256), Q), dim3(256), 0, s, ws64, splits, ntp, TB, q,
+    hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3(ntp * (TB / 64) * (TB / 64)), dim3(256), 0, s, ws64, splits, ntp, TB, q,
                        Q, K);
   }
   return POGS_OK;
