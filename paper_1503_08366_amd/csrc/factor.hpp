@@ -28,9 +28,9 @@ struct CholLds {              // 66.6 KB
 };
 constexpr int kGramTB = 128;  // f32 Gram tile
 constexpr int kGramKC = 16;   // k depth of one f32 stage
-struct GramStage {            // 16.9 KB
-  float a[kGramKC][kGramTB + 4];
-  float b[kGramKC][kGramTB + 4];
+struct GramStage {            // 18.4 KB (row stride 144: the 16-lane row groups of an MFMA operand read land on disjoint banks)
+  float a[kGramKC][kGramTB + 16];
+  float b[kGramKC][kGramTB + 16];
 };
 
 // Tile pair t of a lower triangle (ti >= tj), row by row.
@@ -48,11 +48,13 @@ typedef float GramAcc __attribute__((ext_vector_type(4)));
 // else sum_k A[i][k] A[j][k] (A A^T).  Each wave owns a 64 x 64 quarter as
 // 4 x 4 f32 MFMA 16x16x4 blocks; out(row, col, value) visits the tile's
 // elements (tile-local indices).  Reads beyond m / n are zero.  k0 is a
-// multiple of kGramKC.  Stages of kGramKC k; the next stage is loaded into
-// registers while the MFMAs of the current one run.  Ends with a barrier.
+// multiple of kGramKC.  Stages of kGramKC k in two LDS buffers: the next
+// stage is loaded into registers while the MFMAs of the current one run and
+// stored into the other buffer after them (one barrier per stage).  Ends
+// with a barrier.
 template <bool TALL, class Out>
 __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld, int ti, int tj, int k0, int k1,
-                              GramStage &st, Out out) {
+                              GramStage (&st)[2], Out out) {
   constexpr int TB = kGramTB, KC = kGramKC;
   constexpr int NL = KC * TB / 4 / 256;  // float4 loads per thread per panel
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -88,40 +90,42 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
       }
     }
   };
-  auto store = [&](int kk0) {
+  auto store = [&](GramStage &sd, int kk0) {
 #pragma unroll
     for (int h = 0; h < NL; ++h) {
       const int f = t + h * 256;
       if (TALL) {
         const int k = f >> 5, c = (f & 31) * 4;
-        *reinterpret_cast<f4 *>(&st.a[k][c]) = ra[h];
-        if (!diag) *reinterpret_cast<f4 *>(&st.b[k][c]) = rb[h];
+        *reinterpret_cast<f4 *>(&sd.a[k][c]) = ra[h];
+        if (!diag) *reinterpret_cast<f4 *>(&sd.b[k][c]) = rb[h];
       } else {
         const int r = f & 127, kq = (f >> 7) * 4;
         const int kc = kk0 + kq;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const bool ok = kc + u < k1;
-          st.a[kq + u][r] = ok ? ra[h][u] : 0.f;
-          if (!diag) st.b[kq + u][r] = ok ? rb[h][u] : 0.f;
+          sd.a[kq + u][r] = ok ? ra[h][u] : 0.f;
+          if (!diag) sd.b[kq + u][r] = ok ? rb[h][u] : 0.f;
         }
       }
     }
   };
   load(k0);
+  store(st[0], k0);
+  __syncthreads();
+  int cur = 0;
   for (int kk0 = k0; kk0 < k1; kk0 += KC) {
-    if (kk0 != k0) __syncthreads();
-    store(kk0);
-    __syncthreads();
-    if (kk0 + KC < k1) load(kk0 + KC);
-    const float(*pb)[TB + 4] = diag ? st.a : st.b;
+    const bool more = kk0 + KC < k1;
+    if (more) load(kk0 + KC);
+    const GramStage &sc = st[cur];
+    const float(*pb)[TB + 16] = diag ? sc.a : sc.b;
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
       float av[4], bv[4];
       const int kr = k4 + (lane >> 4), cl = lane & 15;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        av[b] = st.a[kr][wi * 64 + b * 16 + cl];
+        av[b] = sc.a[kr][wi * 64 + b * 16 + cl];
         bv[b] = pb[kr][wj * 64 + b * 16 + cl];
       }
 #pragma unroll
@@ -129,8 +133,11 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) store(st[cur ^ 1], kk0 + KC);
+    __syncthreads();
+    cur ^= 1;
   }
-  __syncthreads();
   // f32 16x16x4 result layout: lane l, element r -> row 4 (l / 16) + r, column l % 16
 #pragma unroll
   for (int i = 0; i < 4; ++i)

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void g_scale_fn(const GProb *probs, const G
 // triangle of K; the identity fills the padding up to Q.
 __global__ __launch_bounds__(256) void g_gram(const GProb *probs, const GItem *items) {
   GROUP_ITEM();
-  __shared__ GramStage st;
+  __shared__ GramStage st[2];
   int ti, tj;
   tri_index(b.x, &ti, &tj);
   const int m = P.it.m, n = P.it.n, Q = P.Q;

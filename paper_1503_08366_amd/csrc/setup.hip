@@ -193,7 +193,7 @@ int run_equilibrate(T *A, int m, int n, int ld, int iters, double eps_cmp, doubl
 template <bool TALL>
 __global__ __launch_bounds__(256, 4) void gram_f32_kernel(const float *__restrict__ A, int m, int n, int ld,
                                                        int kchunk, int ntp, float *__restrict__ part) {
-  __shared__ GramStage st;
+  __shared__ GramStage st[2];
   int ti, tj;
   tri_index(blockIdx.x, &ti, &tj);
   const int kdim = TALL ? m : n;
