@@ -157,7 +157,7 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
 // indices.  128 x 128 tile, 4 waves in 2 x 2, f32 MFMA 16x16x4.
 template <bool A_T, class Out>
 __device__ void gemm_tile_f32(const float *__restrict__ A, int lda, int M, const float *__restrict__ B, int ldb,
-                              int N, int i0, int j0, int k0, int k1, GramStage &st, Out out) {
+                              int N, int i0, int j0, int k0, int k1, GramStage (&st)[2], Out out) {
   constexpr int KC = 16;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = w >> 1, wj = w & 1;
@@ -167,49 +167,77 @@ __device__ void gemm_tile_f32(const float *__restrict__ A, int lda, int M, const
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = GramAcc{0.f, 0.f, 0.f, 0.f};
-  for (int kk0 = k0; kk0 < k1; kk0 += KC) {
+  // stage k range [kk0, kk0 + 16) into registers (two float4 of A and of B
+  // per thread), then into an LDS buffer; as in gram_tile_f32, the next
+  // stage's loads are in flight while the MFMAs of the current one run
+  f4 ra[2], rb[2];
+  auto load = [&](int kk0) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int f = t + h * 256;  // float4 index in a 16 x 128 stage
-      // B: rows kk0 + k, columns j0 + c .. c + 3
-      {
+      {  // B: rows kk0 + k, columns j0 + c .. c + 3
         const int k = f >> 5, c = (f & 31) * 4;
         const int row = kk0 + k, col = j0 + c;
-        f4 vb = f4{0.f, 0.f, 0.f, 0.f};
-        if (row < k1 && col < N) vb = *reinterpret_cast<const f4 *>(B + (size_t)row * ldb + col);
-        *reinterpret_cast<f4 *>(&st.b[k][c]) = vb;
+        rb[h] = f4{0.f, 0.f, 0.f, 0.f};
+        if (row < k1 && col < N) rb[h] = *reinterpret_cast<const f4 *>(B + (size_t)row * ldb + col);
       }
+      ra[h] = f4{0.f, 0.f, 0.f, 0.f};
       if (A_T) {
         const int k = f >> 5, c = (f & 31) * 4;
         const int row = kk0 + k, col = i0 + c;
-        f4 va = f4{0.f, 0.f, 0.f, 0.f};
-        if (row < k1 && col < M) va = *reinterpret_cast<const f4 *>(A + (size_t)row * lda + col);
-        *reinterpret_cast<f4 *>(&st.a[k][c]) = va;
+        if (row < k1 && col < M) ra[h] = *reinterpret_cast<const f4 *>(A + (size_t)row * lda + col);
       } else {
         const int r = f & 127, kq = (f >> 7) * 4;
         const int row = i0 + r, kc = kk0 + kq;
-        f4 va = f4{0.f, 0.f, 0.f, 0.f};
-        if (row < M && kc < k1) va = *reinterpret_cast<const f4 *>(A + (size_t)row * lda + kc);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) st.a[kq + u][r] = kc + u < k1 ? va[u] : 0.f;
+        if (row < M && kc < k1) ra[h] = *reinterpret_cast<const f4 *>(A + (size_t)row * lda + kc);
       }
     }
-    __syncthreads();
+  };
+  auto store = [&](GramStage &sd, int kk0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int f = t + h * 256;
+      {
+        const int k = f >> 5, c = (f & 31) * 4;
+        *reinterpret_cast<f4 *>(&sd.b[k][c]) = rb[h];
+      }
+      if (A_T) {
+        const int k = f >> 5, c = (f & 31) * 4;
+        *reinterpret_cast<f4 *>(&sd.a[k][c]) = ra[h];
+      } else {
+        const int r = f & 127, kq = (f >> 7) * 4;
+        const int kc = kk0 + kq;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sd.a[kq + u][r] = kc + u < k1 ? ra[h][u] : 0.f;
+      }
+    }
+  };
+  load(k0);
+  store(st[0], k0);
+  __syncthreads();
+  int cur = 0;
+  for (int kk0 = k0; kk0 < k1; kk0 += KC) {
+    const bool more = kk0 + KC < k1;
+    if (more) load(kk0 + KC);
+    const GramStage &sc = st[cur];
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
       float av[4], bv[4];
       const int kr = k4 + (lane >> 4), cl = lane & 15;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        av[b] = st.a[kr][wi * 64 + b * 16 + cl];
-        bv[b] = st.b[kr][wj * 64 + b * 16 + cl];
+        av[b] = sc.a[kr][wi * 64 + b * 16 + cl];
+        bv[b] = sc.b[kr][wj * 64 + b * 16 + cl];
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) store(st[cur ^ 1], kk0 + KC);
     __syncthreads();
+    cur ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)

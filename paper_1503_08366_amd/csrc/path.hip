@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void path_prox_kernel(PathArgs p) {
 template <bool A_T>
 __global__ __launch_bounds__(256) void path_gemm_kernel(const float *A, int lda, int M, const float *B, int ldb, int N,
                                                         int K, int kchunk, float *part, const int *all_done) {
-  __shared__ GramStage st;
+  __shared__ GramStage st[2];
   if (*all_done) return;
   const int i0 = blockIdx.x * kGramTB, j0 = blockIdx.y * kGramTB;
   const int k0 = blockIdx.z * kchunk, k1 = min(K, k0 + kchunk);
