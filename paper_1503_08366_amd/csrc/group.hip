@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void g_scale_fn(const GProb *probs, const G
 // K = I + G over the whole K range in one tile (float32 accumulation, as the
 // single-problem path does inside a split), written as float64 into the lower
 // triangle of K; the identity fills the padding up to Q.
-__global__ __launch_bounds__(256) void g_gram(const GProb *probs, const GItem *items) {
+__global__ __launch_bounds__(256, 4) void g_gram(const GProb *probs, const GItem *items) {
   GROUP_ITEM();
   __shared__ GramStage st[2];
   int ti, tj;
