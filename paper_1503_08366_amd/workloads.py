@@ -397,18 +397,26 @@ def batch_mix(count: int = 512, seed: int = 3, m_range=(64, 4096), n_range=(32, 
     child seed.
     """
     ss = np.random.SeedSequence(seed)
-    out = []
-    for i, child in enumerate(ss.spawn(count)):
-        rng = np.random.default_rng(child)
-        m = int(rng.integers(m_range[0], m_range[1] + 1))
-        n = int(rng.integers(n_range[0], n_range[1] + 1))
-        if i % 2 == 0:
-            p = lasso(m, n, 0, dtype=dtype, rng=rng)
-        else:
-            p = logistic(m, n, 0, dtype=dtype, rng=rng)
-        p.meta["index"] = i
-        out.append(p)
-    return out
+    return [_batch_member(child, i, m_range, n_range, dtype) for i, child in enumerate(ss.spawn(count))]
+
+
+def batch_member(index: int, count: int = 512, seed: int = 3, m_range=(64, 4096), n_range=(32, 1024),
+                 dtype=np.float32) -> Problem:
+    """Problem ``index`` of ``batch_mix(count, seed, ...)`` drawn alone (the same data)."""
+    child = np.random.SeedSequence(seed).spawn(count)[index]
+    return _batch_member(child, index, m_range, n_range, dtype)
+
+
+def _batch_member(child, i, m_range, n_range, dtype) -> Problem:
+    rng = np.random.default_rng(child)
+    m = int(rng.integers(m_range[0], m_range[1] + 1))
+    n = int(rng.integers(n_range[0], n_range[1] + 1))
+    if i % 2 == 0:
+        p = lasso(m, n, 0, dtype=dtype, rng=rng)
+    else:
+        p = logistic(m, n, 0, dtype=dtype, rng=rng)
+    p.meta["index"] = i
+    return p
 
 
 def lambda_path(m: int = 8000, n: int = 1000, R: int = 64, seed: int = 33,
@@ -457,3 +465,20 @@ def serving_stream(count: int, qps: float, seed: int = 4, **kw) -> Iterator[tupl
     for _ in range(count):
         t += float(rng.exponential(1.0 / qps))
         yield t, serving_request(rng, **kw)
+
+
+def fingerprint(p: Problem) -> str:
+    """Digest of a problem's inputs (shape, storage type, column sums of A in
+    float64, every function parameter): a stored result is used only for the
+    inputs it was computed on."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(f"{p.m}x{p.n}:{p.A.dtype.str}:{p.eps_abs}:{p.eps_rel}:{p.max_iter}".encode())
+    h.update(np.ascontiguousarray(p.A.sum(axis=0, dtype=np.float64)).tobytes())
+    h.update(np.ascontiguousarray(p.A[:, 0], dtype=np.float64).tobytes())
+    for fn in (p.f, p.g):
+        names = [fn.h] if isinstance(fn.h, str) else list(fn.h)
+        h.update(",".join(names).encode())
+        for k in "abcde":
+            h.update(fn.field(k).tobytes())
+    return h.hexdigest()[:24]
