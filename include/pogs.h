@@ -55,6 +55,10 @@ extern "C" {
 #define POGS_MAXITER    1      /* iteration cap reached */
 #define POGS_NUMERICAL  2      /* a residual became non-finite */
 #define POGS_CANCELLED  3      /* batch: cancelled before completion */
+#define POGS_FAILED     4      /* batch: the request could not be set up on the
+                                  device; pogs_result.error holds the code
+                                  (POGS_ENOMEM, POGS_EDEVICE, or POGS_EINVAL for
+                                  non-finite entries found on the device) */
 
 typedef enum { POGS_F32 = 0, POGS_F64 = 1 } pogs_dtype;
 typedef enum { POGS_ROW_MAJOR = 0, POGS_COL_MAJOR = 1 } pogs_order;
@@ -166,11 +170,12 @@ typedef struct {
   double r_pri, r_dual, eps_pri, eps_dual;  /* last residuals (scaled space) */
   double rho;        /* final penalty */
   int32_t iters;     /* iterations run */
-  int32_t status;    /* POGS_CONVERGED / POGS_MAXITER / POGS_NUMERICAL / POGS_CANCELLED */
+  int32_t status;    /* POGS_CONVERGED / POGS_MAXITER / POGS_NUMERICAL / POGS_CANCELLED /
+                        POGS_FAILED */
   double ms_setup;   /* setup time of the context this solve used (ms) */
   double ms_solve;   /* wall time of this solve (ms) */
   int32_t cg_steps;  /* CGLS steps over all projections (0 for DIRECT) */
-  int32_t reserved;
+  int32_t error;     /* status POGS_FAILED: the POGS_E* code of the failure, else 0 */
   double gap;        /* stop_rule GAP: eta of the last tuple tested (NaN otherwise) */
   double eps_gap;    /* its tolerance eps_abs + eps_rel |f + g| (NaN otherwise) */
 } pogs_result;
@@ -320,7 +325,13 @@ typedef struct pogs_batch pogs_batch;
  * iterations as one group; finished ones leave after each chunk and queued
  * ones join.  Requests too large for the group (see pogs_solve_batch) or with
  * m n > 16 Mi or min(m, n) > 2048 run on the whole-GPU path on two more
- * threads, each with its own stream.  cfg may be NULL.  POGS_EAGAIN if the engine's own
+ * threads, each with its own stream.  Admission counts every resident request
+ * against hbm_budget_bytes, grouped and whole-GPU alike (a whole-GPU request
+ * is charged its matrix, the float64 Gram/factor workspace, K^-1 and its
+ * vectors while it runs); the head of the whole-GPU queue waits for memory,
+ * and the grouped admission then leaves that memory free for it.  A request
+ * whose device setup fails finishes with status POGS_FAILED (code in
+ * pogs_result.error).  cfg may be NULL.  POGS_EAGAIN if the engine's own
  * arrays do not fit the budget. */
 int pogs_batch_create(pogs_batch **out, const pogs_batch_cfg *cfg);
 

@@ -111,8 +111,9 @@ int make_host_problem(const pogs_problem *p, HostProblem *hp) {
   return bad ? POGS_EINVAL : POGS_OK;
 }
 
-// Problems the serving engine runs on the whole-GPU path: those the grouped
-// path does not take, and those large enough to slow every chunk of the group.
+// Problems the batch call and the serving engine run on the whole-GPU path:
+// those the grouped path does not take, and those large enough to slow every
+// chunk of the group (their passes and Gram tiles would run on a few CUs).
 bool serve_solo(int m, int n) {
   return !GroupEngine::fits(m, n) || (double)m * n > 16.0 * (1 << 20) || std::min(m, n) > 2048;
 }
@@ -178,7 +179,7 @@ extern "C" int pogs_solve_batch(int32_t nprob, const pogs_problem *probs, pogs_r
   } guard{s, own};
   std::vector<int> grouped, large;
   for (int i = 0; i < nprob; ++i)
-    (GroupEngine::fits((int)probs[i].m, (int)probs[i].n) ? grouped : large).push_back(i);
+    (serve_solo((int)probs[i].m, (int)probs[i].n) ? large : grouped).push_back(i);
   int rc;
   if (!grouped.empty()) {
     GroupEngine eng(s, (int)grouped.size());
@@ -313,12 +314,21 @@ struct pogs_batch {
 
   void run();
   void run_solo(int w);
-  void finish(const std::shared_ptr<Request> &r, int status_override);
+  // status_override >= 0 replaces the result's status; err != 0 marks a
+  // request whose setup failed (status POGS_FAILED, the code in res.error)
+  void finish(const std::shared_ptr<Request> &r, int status_override, int err = 0);
+  // bytes the request at the head of the whole-GPU queue waits for (the
+  // grouped admission leaves them free so that request is not starved)
+  size_t solo_wait = 0;
 };
 
-void pogs_batch::finish(const std::shared_ptr<Request> &r, int status_override) {
+void pogs_batch::finish(const std::shared_ptr<Request> &r, int status_override, int err) {
   std::lock_guard<std::mutex> g(mu);
   if (status_override >= 0) r->res.status = status_override;
+  if (err) {
+    r->res.status = POGS_FAILED;
+    r->res.error = err;
+  }
   r->state = 2;
   if (r->bytes) used -= r->bytes;
   --pending;
@@ -332,7 +342,14 @@ void pogs_batch::run() {
     std::vector<std::shared_ptr<Request>> admitted;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv.wait(lk, [&] { return stop || !queue.empty() || !resident.empty(); });
+      // wake for resident work, or for a queued request that can be admitted
+      // now (memory held by whole-GPU requests is released by finish())
+      cv.wait(lk, [&] {
+        if (stop || !resident.empty()) return true;
+        if (queue.empty() || free_slots <= 0) return false;
+        const auto &h = queue.front();
+        return h->cancel || used + h->bytes + solo_wait <= budget;
+      });
       if (stop) return;
       // admit while memory and slots allow (first come, first served)
       while (!queue.empty() && free_slots > 0) {
@@ -345,7 +362,7 @@ void pogs_batch::run() {
           cv_done.notify_all();
           continue;
         }
-        if (used + r->bytes > budget) break;
+        if (used + r->bytes + solo_wait > budget) break;
         queue.pop_front();
         used += r->bytes;
         --free_slots;
@@ -369,7 +386,7 @@ void pogs_batch::run() {
       if (rc) {
         ++free_slots;
         r->handle = -1;
-        finish(r, POGS_NUMERICAL);
+        finish(r, -1, rc);
         continue;
       }
       fresh.push_back(r->handle);
@@ -380,7 +397,7 @@ void pogs_batch::run() {
       if (rc || eng->status(r->handle).flags[0]) {
         eng->remove(r->handle);
         ++free_slots;
-        finish(r, POGS_NUMERICAL);
+        finish(r, -1, rc ? rc : POGS_EINVAL);  // flags[0]: non-finite entries found on the device
         continue;
       }
       std::lock_guard<std::mutex> g(mu);
@@ -430,7 +447,7 @@ void pogs_batch::run() {
         std::lock_guard<std::mutex> g(mu);
         resident.erase(std::find(resident.begin(), resident.end(), r));
       }
-      finish(r, rc ? POGS_NUMERICAL : (r->cancel ? POGS_CANCELLED : -1));
+      finish(r, r->cancel ? POGS_CANCELLED : -1, rc);
     }
   }
 }
@@ -439,19 +456,32 @@ void pogs_batch::run_solo(int w) {
   for (;;) {
     std::shared_ptr<Request> r;
     {
+      // the head of the queue starts once its estimated device memory fits
+      // the budget next to everything resident (grouped and whole-GPU)
       std::unique_lock<std::mutex> lk(mu);
-      cv.wait(lk, [&] { return stop || !solo_queue.empty(); });
-      if (stop) return;
-      r = solo_queue.front();
-      solo_queue.pop_front();
-      if (r->cancel) {
-        r->state = 2;
-        r->res.status = POGS_CANCELLED;
-        --pending;
-        cv_done.notify_all();
-        continue;
+      for (;;) {
+        cv.wait(lk, [&] { return stop || !solo_queue.empty(); });
+        if (stop) return;
+        r = solo_queue.front();
+        if (r->cancel) {
+          solo_queue.pop_front();
+          if (solo_wait && solo_queue.empty()) solo_wait = 0;
+          r->state = 2;
+          r->res.status = POGS_CANCELLED;
+          --pending;
+          cv_done.notify_all();
+          cv.notify_all();
+          continue;
+        }
+        if (used + r->bytes <= budget) break;
+        solo_wait = r->bytes;
+        cv.wait(lk);
       }
+      solo_queue.pop_front();
+      solo_wait = 0;
+      used += r->bytes;
       r->state = 1;
+      cv.notify_all();
     }
     const int m = r->hp.m, n = r->hp.n;
     r->xo.resize(n);
@@ -465,7 +495,7 @@ void pogs_batch::run_solo(int w) {
     r->res.nu = r->nuo.data();
     const int rc = solve_large(r->hp, &r->res, solo_stream[w]);
     r->res.ms_solve = now_ms() - r->t_submit;
-    finish(r, rc ? POGS_NUMERICAL : -1);
+    finish(r, -1, rc);
   }
 }
 
@@ -512,9 +542,12 @@ extern "C" int pogs_batch_submit(pogs_batch *b, const pogs_problem *p, uint64_t 
     r->bytes = GroupEngine::bytes_for(r->hp.m, r->hp.n);
     if (r->bytes > b->budget) return POGS_EAGAIN;
   } else {
+    // the whole-GPU path's device memory: the matrix, the float64 Gram and
+    // factor workspace and K^-1, plus the vectors (charged while it runs)
     const size_t q = std::min(r->hp.m, r->hp.n);
-    const size_t est = (size_t)r->hp.m * round_up(r->hp.n, 64) * 4 + 3 * q * q * 8;
-    if (est > b->budget) return POGS_EAGAIN;
+    r->bytes = (size_t)r->hp.m * round_up(r->hp.n, 64) * 4 + 3 * q * q * 8 +
+               (size_t)64 * (r->hp.m + r->hp.n) * 8;
+    if (r->bytes > b->budget) return POGS_EAGAIN;
   }
   r->t_submit = now_ms();
   std::lock_guard<std::mutex> g(b->mu);

@@ -108,22 +108,33 @@ __global__ __launch_bounds__(kBlock) void g_scale_fn(const GProb *probs, const G
   }
 }
 
-// K = I + G over the whole K range in one tile (float32 accumulation, as the
-// single-problem path does inside a split), written as float64 into the lower
-// triangle of K; the identity fills the padding up to Q.
+// K = I + G, one tile per workgroup, written as float64 into the lower
+// triangle of K; the identity fills the padding up to Q.  The K range is
+// summed in chunks of kGChunk in float32 (as the single-problem path does
+// inside a split) and the chunks are added in float64 in order, so a long
+// K range (m rows of a tall problem) does not accumulate in float32.
+constexpr int kGChunk = 4096;
 __global__ __launch_bounds__(256, 4) void g_gram(const GProb *probs, const GItem *items) {
   GROUP_ITEM();
   __shared__ GramStage st[2];
   int ti, tj;
   tri_index(b.x, &ti, &tj);
   const int m = P.it.m, n = P.it.n, Q = P.Q;
+  const int kdim = P.tall ? m : n;
   double *K = P.K;
-  auto out = [&](int r, int c, float v) {
-    const int gi = ti * kGramTB + r, gj = tj * kGramTB + c;
-    if (gi < Q && gj <= gi) K[(size_t)gi * Q + gj] = (gi == gj ? 1.0 : 0.0) + (double)v;
-  };
-  if (P.tall) gram_tile_f32<true>(P.it.A, m, n, P.it.ld, ti, tj, 0, m, st, out);
-  else gram_tile_f32<false>(P.it.A, m, n, P.it.ld, ti, tj, 0, n, st, out);
+  for (int k0 = 0; k0 < kdim; k0 += kGChunk) {
+    const int k1 = min(kdim, k0 + kGChunk);
+    const bool first = k0 == 0;
+    auto out = [&](int r, int c, float v) {
+      const int gi = ti * kGramTB + r, gj = tj * kGramTB + c;
+      if (gi < Q && gj <= gi) {
+        double &dst = K[(size_t)gi * Q + gj];
+        dst = (first ? (gi == gj ? 1.0 : 0.0) : dst) + (double)v;
+      }
+    };
+    if (P.tall) gram_tile_f32<true>(P.it.A, m, n, P.it.ld, ti, tj, k0, k1, st, out);
+    else gram_tile_f32<false>(P.it.A, m, n, P.it.ld, ti, tj, k0, k1, st, out);
+  }
 }
 
 __global__ __launch_bounds__(256) void g_trtri_init(const GProb *probs, const GItem *items) {

@@ -23,14 +23,14 @@ LIB_PATH = os.path.join(_HERE, "libpogs.so")
 # --- constants of include/pogs.h ------------------------------------------
 POGS_OK, POGS_EINVAL, POGS_ENOMEM, POGS_EDEVICE, POGS_EAGAIN, POGS_ENOTFOUND, POGS_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-POGS_CONVERGED, POGS_MAXITER, POGS_NUMERICAL, POGS_CANCELLED = 0, 1, 2, 3
+POGS_CONVERGED, POGS_MAXITER, POGS_NUMERICAL, POGS_CANCELLED, POGS_FAILED = 0, 1, 2, 3, 4
 POGS_F32, POGS_F64 = 0, 1
 POGS_ROW_MAJOR, POGS_COL_MAJOR = 0, 1
 POGS_HOST, POGS_DEVICE = 0, 1
 H_CODES = {"zero": 0, "identity": 1, "abs": 2, "square": 3, "huber": 4, "hinge": 5,
            "logistic": 6, "ind_ge0": 7, "ind_le0": 8, "ind_eq0": 9, "ind_box01": 10,
            "exp": 11, "neg_entr": 12, "neg_log": 13, "recipr": 14, "max_neg0": 15}
-STATUS_NAMES = {0: "converged", 1: "maxiter", 2: "numerical", 3: "cancelled"}
+STATUS_NAMES = {0: "converged", 1: "maxiter", 2: "numerical", 3: "cancelled", 4: "failed"}
 
 
 class PogsError(RuntimeError):
@@ -61,7 +61,7 @@ class pogs_result(C.Structure):
                 ("r_dual", C.c_double), ("eps_pri", C.c_double), ("eps_dual", C.c_double),
                 ("rho", C.c_double), ("iters", C.c_int32), ("status", C.c_int32),
                 ("ms_setup", C.c_double), ("ms_solve", C.c_double), ("cg_steps", C.c_int32),
-                ("reserved", C.c_int32), ("gap", C.c_double), ("eps_gap", C.c_double)]
+                ("error", C.c_int32), ("gap", C.c_double), ("eps_gap", C.c_double)]
 
 
 class pogs_problem(C.Structure):
@@ -226,6 +226,7 @@ class Result:
         self.ms_setup, self.ms_solve = r.ms_setup, r.ms_solve
         self.cg_steps = r.cg_steps
         self.gap, self.eps_gap = r.gap, r.eps_gap
+        self.error = r.error
 
     @property
     def converged(self) -> bool:

@@ -215,3 +215,29 @@ def test_serving_submit_copies_layouts_and_rejects_non_finite():
     for r in rs[1:]:
         assert r.iters == rs[0].iters and r.optval == rs[0].optval
         np.testing.assert_array_equal(r.x, rs[0].x)
+
+
+def test_serving_budget_counts_whole_gpu_requests():
+    """Whole-GPU requests are charged their device memory while they run: with
+    a budget that holds one of them at a time, two such requests (and small
+    grouped ones) still all finish, each with the result it has alone."""
+    big = [W.lasso(5000, 4000, 71), W.nnls_from(W.lasso(4500, 4000, 72))]  # m n > 16 Mi: whole-GPU path
+    small = _mix(3, seed=73)
+    alone = []
+    for p in big:
+        with P.Context(p.A) as ctx:
+            alone.append(ctx.solve(p.f, p.g))
+    eng = P.BatchEngine(hbm_budget_bytes=600 << 20, chunk_iters=20)
+    try:
+        ts = [eng.submit(p) for p in big]
+        tsmall = [eng.submit(p) for p in small]
+        eng.wait_all()
+        served = [eng.poll(t) for t in ts]
+        rsmall = [eng.poll(t) for t in tsmall]
+    finally:
+        eng.close()
+    for s, a in zip(served, alone):
+        assert s.status == a.status == P.POGS_CONVERGED and s.error == 0
+        assert s.iters == a.iters and s.optval == a.optval
+        np.testing.assert_array_equal(s.x, a.x)
+    assert all(r.converged for r in rsmall)
