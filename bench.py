@@ -1,17 +1,23 @@
-"""Benchmark: plain single-problem graph-form ADMM on one MI355X.
+"""Benchmark: graph-form ADMM on one MI355X.
 
-One step = one whole solve of the workload with A already resident in HBM:
-pogs_init (layout, Sinkhorn-Knopp equilibration, Frobenius normalisation,
-MFMA Gram, float64 Cholesky and inverse) + pogs_solve (prox, two passes over
-A, solve, dual update and residual/stopping reductions per iteration, until
-the stopping test passes at eps_abs = 1e-4, eps_rel = 1e-3) + pogs_free.
+Default line (``python bench.py``): one step = one whole solve of the Lasso
+20000 x 2000 workload with A already resident in HBM: pogs_init (layout,
+Sinkhorn-Knopp equilibration, Frobenius normalisation, MFMA Gram, float64
+Cholesky and inverse) + pogs_solve (the ADMM iterations until the stopping
+test passes at eps_abs = 1e-4, eps_rel = 1e-3) + pogs_free.  value = solves/s
+(converged solves only), with ADMM iter/s, p50/p99 step latency, the roofline
+of the dominant per-iteration kernel (HIP events on the library's stream),
+the FP64 CPU oracle's rate on the host cores and the objective's error
+against that oracle.  Beside it, each against its plain one-problem path on
+the same GPU and with its objective error against the oracle:
+  dose     the dose-shaped 100000 x 1000 problem (whole solves, roofline);
+  batched  512 uneven Lasso/logistic problems in one batch call;
+  path     a 64-point lambda path on one 8000 x 1000 matrix;
+  serving  mixed requests through the serving engine (closed loop, then
+           Poisson arrivals at 80 % of it: p50/p99 latency).
 
-Prints one JSON line: value = solves/s (converged solves only), plus ADMM
-iter/s, p50/p99 step latency, the roofline of the dominant per-iteration
-kernel (HIP events on the library's stream) and the FP64 CPU oracle's rate on
-the host cores.
-
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lasso|nnls|dose]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-blocks]
+                    [--workload lasso|nnls|dose|lasso-cgls|batch|path|serve|sparse]
 """
 from __future__ import annotations
 
@@ -99,41 +105,97 @@ def cpu_baseline(prob, budget_s: float = 30.0, projection: str = "direct"):
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "solves/s", "cores": _cpu_threads(), "kind": "oracle",
             "sample": f"{done} whole solve(s) of the same workload in FP64 ({iters} ADMM iterations, "
-                      f"{dt:.1f} s)", "iter_per_s": iters / dt}
+                      f"{dt:.1f} s)", "iter_per_s": iters / dt, "optval": float(r.optval),
+            "converged": bool(r.converged)}
+
+
+def rel_err(got: float, ref: float) -> float:
+    """Objective error against the oracle: |p - p_oracle| / max(|p_oracle|, 1)."""
+    return abs(got - ref) / max(abs(ref), 1.0)
+
+
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def stored_oracle(name: str, probs):
+    """Oracle objectives stored by tests/golden/make_golden.py (FP64 oracle
+    only), or None unless every record was computed on exactly these inputs."""
+    from paper_1503_08366_amd import workloads as W
+    try:
+        with open(os.path.join(GOLDEN_DIR, name)) as fh:
+            recs = json.load(fh)["results"]
+    except (OSError, ValueError, KeyError):
+        return None
+    if len(recs) != len(probs) or any(r["fingerprint"] != W.fingerprint(p) for r, p in zip(recs, probs)):
+        return None
+    return recs
+
+
+def err_summary(res, recs):
+    if recs is None:
+        return None
+    e = np.array([rel_err(r.optval, g["optval"]) for r, g in zip(res, recs)])
+    return {"max": float(e.max()), "median": float(np.median(e)), "count": int(e.size),
+            "oracle": "stored FP64-oracle objectives (tests/golden/)"}
 
 
 def bench_batch(args):
     """512 uneven Lasso/logistic problems: one batched call vs one problem per launch sequence."""
     from paper_1503_08366_amd import pogs as P
     from paper_1503_08366_amd import workloads as W
-    probs = W.batch_mix(count=args.count)
+    block = batch_block(P, W.batch_mix(count=args.count), args.plain_count)
+    return {"metric": "solves/s at rel tol 1e-3, batched (grouped launches per phase) vs plain",
+            "value": block["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "config": {"workload": block["workload"]}, **block}
+
+
+def batch_block(P, probs, plain_count, reps=2):
+    """The batch call over all problems (grouped launches: one launch per phase
+    for every problem) against the plain path, one pogs_init + pogs_solve per
+    problem; both from host inputs, the plain leg without the load-policy
+    tuner (the batched leg has none)."""
+    recs = stored_oracle("batch_mix_512.json", probs) if len(probs) == 512 else None
     P.pogs_solve_batch(probs)  # warm at full size (device memory pool, pinned ring)
-    t = time.perf_counter()
-    res = P.pogs_solve_batch(probs)
-    tb = time.perf_counter() - t
+    tb = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        res = P.pogs_solve_batch(probs)
+        tb.append(time.perf_counter() - t)
+    tb = float(np.mean(tb))
     conv = sum(r.converged for r in res)
-    nplain = min(len(probs), args.plain_count)
+    nplain = min(len(probs), plain_count)
+    prm = P.default_params(autotune=0)
     t = time.perf_counter()
     plain_conv = 0
     for p in probs[:nplain]:
-        with P.Context(p.A) as ctx:
-            plain_conv += ctx.solve(p.f, p.g).converged
+        with P.Context(p.A, prm) as ctx:
+            plain_conv += ctx.solve(p.f, p.g, prm).converged
     tp = time.perf_counter() - t
-    return {"metric": "solves/s at rel tol 1e-3, batched (one persistent launch) vs plain",
-            "value": conv / tb, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
-            "config": {"workload": f"{len(probs)} problems, even Lasso / odd logistic, m~U[64,4096], n~U[32,1024], "
-                                   "float32, host inputs (PCIe copy inside the timed region for both legs)"},
-            "batched": {"solves_per_s": conv / tb, "seconds": tb, "converged": f"{conv}/{len(res)}",
-                        "iters_mean": float(np.mean([r.iters for r in res]))},
-            "plain": {"solves_per_s": plain_conv / tp, "seconds": tp, "problems": nplain},
-            "speedup": (conv / tb) / max(plain_conv / tp, 1e-30)}
+    return {"workload": f"{len(probs)} problems, even Lasso / odd logistic, m~U[64,4096], n~U[32,1024], "
+                        "float32, host inputs (PCIe copy inside the timed region for both legs)",
+            "solves_per_s": conv / tb, "seconds": tb, "converged": f"{conv}/{len(res)}",
+            "iters_mean": float(np.mean([r.iters for r in res])),
+            "plain": {"solves_per_s": plain_conv / tp, "seconds": tp, "problems": nplain,
+                      "converged": f"{plain_conv}/{nplain}", "autotune": 0},
+            "speedup": (conv / tb) / max(plain_conv / tp, 1e-30),
+            "oracle_rel_err": err_summary(res, recs)}
 
 
 def bench_path(args):
     """64-point lambda path on one 8000x1000 A: stacked right-hand sides on MFMA vs one solve per lambda."""
     from paper_1503_08366_amd import pogs as P
     from paper_1503_08366_amd import workloads as W
-    probs = W.lambda_path(R=args.R)
+    block = path_block(P, W.lambda_path(R=args.R))
+    return {"metric": "solves/s at rel tol 1e-3, lambda path (stacked RHS, MFMA) vs plain",
+            "value": block["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "config": {"workload": block["workload"]}, **block}
+
+
+def path_block(P, probs):
+    """All lambdas of one path in one call (shared A, K^-1; the passes are
+    MFMA products over the stacked right-hand sides) against one solve per
+    lambda on the same context; shared setup excluded from both legs."""
+    recs = stored_oracle("lambda_path_8000x1000.json", probs)
     with P.Context(probs[0].A) as ctx:
         # warm both legs at full size (device memory pool, captured graphs)
         ctx.solve_path([p.f for p in probs], [p.g for p in probs])
@@ -146,14 +208,13 @@ def bench_path(args):
         tplain = time.perf_counter() - t
         setup_ms = alone[0].ms_setup
     conv = sum(r.converged for r in res)
-    return {"metric": "solves/s at rel tol 1e-3, lambda path (stacked RHS, MFMA) vs plain",
-            "value": conv / tpath, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
-            "config": {"workload": f"{len(probs)} Lasso lambdas log-spaced over [1e-3, 1] lam_max, A 8000x1000 float32, "
-                                   "shared setup excluded from both legs", "setup_ms": setup_ms},
-            "path": {"seconds": tpath, "converged": f"{conv}/{len(res)}", "iters_max": max(r.iters for r in res)},
+    return {"workload": f"{len(probs)} Lasso lambdas log-spaced over [1e-3, 1] lam_max, A 8000x1000 float32, "
+                        "shared setup excluded from both legs", "setup_ms": setup_ms,
+            "solves_per_s": conv / tpath, "seconds": tpath, "converged": f"{conv}/{len(res)}",
+            "iters_max": max(r.iters for r in res),
             "plain": {"seconds": tplain, "solves_per_s": sum(r.converged for r in alone) / tplain,
                       "iters_sum": sum(r.iters for r in alone)},
-            "speedup": tplain / tpath}
+            "speedup": tplain / tpath, "oracle_rel_err": err_summary(res, recs)}
 
 
 def bench_sparse(args):
@@ -245,37 +306,43 @@ def bench_serve(args):
     rate."""
     from paper_1503_08366_amd import pogs as P
     from paper_1503_08366_amd import workloads as W
-    stream = list(W.serving_stream(args.count, 1.0))  # unit-rate arrivals; the problems do not depend on the rate
+    block = serve_block(P, W, args.count, args.window, [0.5, 0.8], args.qps)
+    return {"metric": "served solves/s at rel tol 1e-3 (continuous batching, closed loop) with p50/p99 latency "
+                      "at 50%/80% of it (open loop)",
+            "value": block["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "config": {"workload": block["workload"], "window": args.window}, **block}
+
+
+def serve_block(P, W, count, window, loads, qps=0.0):
+    stream = list(W.serving_stream(count, 1.0))  # unit-rate arrivals; the problems do not depend on the rate
     unit = [t for t, _ in stream]
     probs = [p for _, p in stream]
     say = lambda msg: print(msg, file=sys.stderr, flush=True)
     _serve_leg(P, probs[:16], window=16)  # warm
-    closed = _serve_leg(P, probs, window=args.window)
+    closed = _serve_leg(P, probs, window=window)
     say(f"serve closed loop: {closed}")
     t = time.perf_counter()
     plain_conv = 0
+    prm = P.default_params(autotune=0)
     for p in probs:
-        with P.Context(p.A) as ctx:
-            plain_conv += ctx.solve(p.f, p.g).converged
+        with P.Context(p.A, prm) as ctx:
+            plain_conv += ctx.solve(p.f, p.g, prm).converged
     tp = time.perf_counter() - t
     say(f"serve plain: {plain_conv / tp:.1f} solves/s")
-    rates = [0.5 * closed["solves_per_s"], 0.8 * closed["solves_per_s"]] + ([args.qps] if args.qps > 0 else [])
+    rates = [f * closed["solves_per_s"] for f in loads] + ([qps] if qps > 0 else [])
     open_loop = []
     for q in rates:
         r = _serve_leg(P, probs, arrivals=[u / q for u in unit])
         r["offered_qps"] = q
         open_loop.append(r)
         say(f"serve open loop at {q:.1f}/s: {r}")
-    return {"metric": "served solves/s at rel tol 1e-3 (continuous batching, closed loop) with p50/p99 latency "
-                      "at 50%/80% of it (open loop)",
-            "value": closed["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
-            "config": {"workload": f"{args.count} requests, Lasso/NNLS/SVM/LP, m~logU[100,50000], "
-                                   "n~logU[50,5000], float32 host inputs (PCIe copy inside), HBM budget 80% of free",
-                       "window": args.window},
-            "closed_loop": closed, "open_loop": open_loop,
-            "latency_ms": {"p50": open_loop[0]["p50_ms"], "p99": open_loop[0]["p99_ms"],
-                           "at_qps": open_loop[0]["offered_qps"]},
-            "plain": {"solves_per_s": plain_conv / tp, "seconds": tp, "converged": f"{plain_conv}/{len(probs)}"},
+    last = open_loop[-1] if not qps else open_loop[len(loads) - 1]
+    return {"workload": f"{count} requests, Lasso/NNLS/SVM/LP, m~logU[100,50000], n~logU[50,5000], "
+                        "float32 host inputs (PCIe copy inside), HBM budget 80% of free",
+            "solves_per_s": closed["solves_per_s"], "closed_loop": closed, "open_loop": open_loop,
+            "latency_ms": {"p50": last["p50_ms"], "p99": last["p99_ms"], "at_qps": last["offered_qps"]},
+            "plain": {"solves_per_s": plain_conv / tp, "seconds": tp, "converged": f"{plain_conv}/{len(probs)}",
+                      "autotune": 0},
             "speedup": closed["solves_per_s"] / max(plain_conv / tp, 1e-30)}
 
 
@@ -286,6 +353,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lasso", choices=sorted(WORKLOADS) + ["batch", "path", "serve", "sparse"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-blocks", action="store_true",
+                    help="lasso: only the single-problem line (no dose, batched, path, serving blocks)")
+    ap.add_argument("--serve-count", type=int, default=128, help="requests in the default line's serving block")
     ap.add_argument("--profile-reps", type=int, default=100)
     ap.add_argument("--count", type=int, default=512, help="batch / serve: number of problems")
     ap.add_argument("--plain-count", type=int, default=512, help="batch: problems in the plain leg")
@@ -321,11 +391,51 @@ def main():
     import torch
     from paper_1503_08366_amd import pogs as P
     from paper_1503_08366_amd import workloads as W
+    torch.cuda.set_device(0)
+    say = lambda msg: print(msg, file=sys.stderr, flush=True)
 
-    gen_name, desc, projection = WORKLOADS[args.workload]
+    line = single_problem(P, W, args.workload, args.steps, args.warmup, args.profile_reps, host_leg=True)
+    prob_desc = line.pop("_prob")
+    line = {
+        "metric": "solves/s at rel tol 1e-3 (plain, one problem per launch sequence; batched, lambda-path and "
+                  "served blocks beside it); ADMM iter/s; p50/p99 latency",
+        **line}
+    if not args.no_cpu:
+        cb = cpu_baseline(prob_desc, projection=WORKLOADS[args.workload][2])
+        line["cpu_baseline"] = cb
+        line["oracle_rel_err"] = {args.workload: rel_err(line.pop("_optval"), cb["optval"])}
+    else:
+        line.pop("_optval")
+    say(f"{args.workload}: {line['value']:.1f} solves/s")
+    if args.workload == "lasso" and not args.no_blocks:
+        # the metric's other workloads, each against its plain one-problem path
+        dose = single_problem(P, W, "dose", 2, 1, 20, host_leg=False)
+        dprob = dose.pop("_prob")
+        drec = stored_oracle("dose_100000x1000.json", [dprob])
+        dose["oracle_rel_err"] = None if drec is None else rel_err(dose.pop("_optval"), drec[0]["optval"])
+        dose.pop("_optval", None)
+        for k in ("metric", "n_gpus", "scaling", "vs_baseline", "data", "higher_is_better"):
+            dose.pop(k, None)
+        line["dose"] = dose
+        say(f"dose: {dose['value']:.2f} solves/s")
+        line["batched"] = batch_block(P, W.batch_mix(512), 512)
+        say(f"batched: {line['batched']['solves_per_s']:.0f} solves/s, {line['batched']['speedup']:.2f}x plain")
+        line["path"] = path_block(P, W.lambda_path())
+        say(f"path: {line['path']['solves_per_s']:.0f} solves/s, {line['path']['speedup']:.2f}x plain")
+        line["serving"] = serve_block(P, W, args.serve_count, min(args.window, args.serve_count), [0.8])
+        say(f"serving: {line['serving']['solves_per_s']:.0f} solves/s")
+    print(json.dumps(line), flush=True)
+
+
+def single_problem(P, W, workload, steps, warmup, profile_reps, host_leg):
+    """Whole solves of one problem with A resident in HBM (pogs_init + pogs_solve
+    + pogs_free per step), the roofline of the dominant per-iteration kernel
+    from HIP-event timings on the library's stream, and optionally the same
+    solves from a host matrix (PCIe copy inside the timed region)."""
+    import torch
+    gen_name, desc, projection = WORKLOADS[workload]
     prob = getattr(W, gen_name)()
     m, n = prob.m, prob.n
-    torch.cuda.set_device(0)
     A = torch.from_numpy(prob.A).cuda()
     stream = torch.cuda.current_stream()
     prm = P.default_params(eps_abs=prob.eps_abs, eps_rel=prob.eps_rel, max_iter=prob.max_iter,
@@ -338,12 +448,12 @@ def main():
             r = ctx.solve(prob.f, prob.g, prm, device_out=True)
         return time.perf_counter() - t, r
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     lat, res = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         dt, r = step()
         lat.append(dt)
         res.append(r)
@@ -354,21 +464,26 @@ def main():
     solve_ms = sum(r.ms_solve for r in res)
     setup_ms = sum(r.ms_setup for r in res)
 
-    # the same whole solves with A handed over in (pageable) host memory: the
-    # PCIe copy is inside the timed region
-    host_steps = max(1, min(args.steps, 5))
-    t = time.perf_counter()
-    host_conv = 0
-    for _ in range(host_steps):
-        with P.Context(prob.A, prm, stream) as ctx:
-            host_conv += ctx.solve(prob.f, prob.g, prm, device_out=True).converged
-    torch.cuda.synchronize()
-    host_s = time.perf_counter() - t
+    host = None
+    if host_leg:
+        # the same whole solves with A handed over in (pageable) host memory: the
+        # PCIe copy is inside the timed region
+        host_steps = max(1, min(steps, 5))
+        t = time.perf_counter()
+        host_conv = 0
+        for _ in range(host_steps):
+            with P.Context(prob.A, prm, stream) as ctx:
+                host_conv += ctx.solve(prob.f, prob.g, prm, device_out=True).converged
+        torch.cuda.synchronize()
+        host_s = time.perf_counter() - t
+        host = {"solves_per_s": host_conv / host_s, "steps": host_steps,
+                "input": "A in pageable host memory, PCIe copy inside the timed region"}
 
     # dominant kernel: the passes over A, timed with HIP events on the library's stream
     with P.Context(A, prm, stream) as ctx:
         ctx.solve(prob.f, prob.g, prm, device_out=True)
-        prof = ctx.profile_iteration(args.profile_reps)
+        prof = ctx.profile_iteration(profile_reps)
+    del A
     tall = m >= n
     q = min(m, n)
     if cgls:
@@ -387,16 +502,14 @@ def main():
         kern_desc = f"{kern} ({'A^T v' if (kern == 'pass1') == tall else 'A v'})"
         iter_bytes = 8.0 * m * n + 4.0 * q * q + 4.0 * 24 * (m + n)
     achieved = alg_bytes / (prof[kern] * 1e-3) / 1e9
-    traffic = None if cgls else recorded_traffic(args.workload, kern)
-
+    traffic = None if cgls else recorded_traffic(workload, kern)
     line = {
-        "metric": "solves/s at rel tol 1e-3 (plain, one problem per launch sequence); ADMM iter/s; p50/p99 latency",
         "value": converged / total,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * total / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * total / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -411,20 +524,21 @@ def main():
         "solve_ms_mean": solve_ms / len(res),
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
         "kernel_ms": prof,
-        "host_input": {"solves_per_s": host_conv / host_s, "steps": host_steps,
-                       "input": "A in pageable host memory, PCIe copy inside the timed region"},
         "roofline": {"bound": "hbm", "kernel": kern_desc,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes},
+        "_optval": float(res[-1].optval),
+        "_prob": prob,
     }
+    if host is not None:
+        line["host_input"] = host
     if iter_bytes is not None:
         line["iteration_GBps"] = iter_bytes / (prof["iteration"] * 1e-3) / 1e9
+        line["iteration_frac"] = line["iteration_GBps"] / HBM_PEAK_GBS
     if cgls:
         line["cg_steps_per_iteration"] = sum(r.cg_steps for r in res) / max(iters, 1)
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(prob, projection=projection)
-    print(json.dumps(line), flush=True)
+    return line
 
 
 if __name__ == "__main__":
