@@ -105,6 +105,29 @@ class Problem:
         return self.A.shape[1]
 
 
+_ROW_BLOCK = 2048
+
+
+def _matvec(A: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """A x in float64 from elementwise products and NumPy's own fixed-order
+    sums over row blocks, so that the drawn inputs do not depend on the host's
+    BLAS library or its thread count."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.empty(A.shape[0])
+    for i in range(0, A.shape[0], _ROW_BLOCK):
+        out[i:i + _ROW_BLOCK] = (A[i:i + _ROW_BLOCK].astype(np.float64) * x).sum(axis=1)
+    return out
+
+
+def _rmatvec(A: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """A^T v in float64, row blocks accumulated in index order (see _matvec)."""
+    v = np.asarray(v, dtype=np.float64)
+    acc = np.zeros(A.shape[1])
+    for i in range(0, A.shape[0], _ROW_BLOCK):
+        acc += (A[i:i + _ROW_BLOCK].astype(np.float64) * v[i:i + _ROW_BLOCK, None]).sum(axis=0)
+    return acc
+
+
 def _sparse_truth(rng: np.random.Generator, n: int, frac: float) -> np.ndarray:
     """x_true with exactly round(frac*n) (at least 1) N(0,1) entries at random positions."""
     k = max(1, int(round(frac * n)))
@@ -127,9 +150,8 @@ def lasso(m: int, n: int, seed: int, dtype=np.float32, lam_frac: float = 0.1,
     rng = rng if rng is not None else np.random.default_rng(seed)
     A = (rng.standard_normal((m, n)) / math.sqrt(n)).astype(dtype)
     x_true = _sparse_truth(rng, n, nnz_frac)
-    A64 = A.astype(np.float64)
-    b = A64 @ x_true + noise * rng.standard_normal(m)
-    lam = lam_frac * float(np.max(np.abs(A64.T @ b)))
+    b = _matvec(A, x_true) + noise * rng.standard_normal(m)
+    lam = lam_frac * float(np.max(np.abs(_rmatvec(A, b))))
     f = Fn("square", m, a=1.0, b=b, c=1.0)
     g = Fn("abs", n, c=lam)
     return Problem("lasso", np.ascontiguousarray(A), f, g, max_iter=max_iter,
@@ -179,11 +201,10 @@ def logistic(m: int, n: int, seed: int, dtype=np.float32, lam_frac: float = 0.1,
     rng = rng if rng is not None else np.random.default_rng(seed)
     A = (rng.standard_normal((m, n)) / math.sqrt(n)).astype(dtype)
     x_true = _sparse_truth(rng, n, nnz_frac)
-    A64 = A.astype(np.float64)
-    s = np.sign(A64 @ x_true + noise * rng.standard_normal(m))
+    s = np.sign(_matvec(A, x_true) + noise * rng.standard_normal(m))
     s[s == 0] = 1.0
     b01 = 0.5 * (1.0 + s)
-    lam = lam_frac * float(np.max(np.abs(A64.T @ (0.5 - b01))))
+    lam = lam_frac * float(np.max(np.abs(_rmatvec(A, 0.5 - b01))))
     f = Fn("logistic", m, a=1.0, b=0.0, c=1.0, d=-b01)
     g = Fn("abs", n, c=lam)
     return Problem("logistic", np.ascontiguousarray(A), f, g, max_iter=max_iter,
@@ -221,7 +242,7 @@ def lp(m: int, n: int, seed: int, dtype=np.float32, max_iter: int = 10000,
     rng = rng if rng is not None else np.random.default_rng(seed)
     A = rng.standard_normal((m, n)).astype(dtype)
     v = rng.random(n)
-    b = A.astype(np.float64) @ v + rng.uniform(0.0, 0.1, m)
+    b = _matvec(A, v) + rng.uniform(0.0, 0.1, m)
     cost = rng.random(n)
     f = Fn("ind_le0", m, a=1.0, b=b)
     g = Fn("ind_box01", n, d=cost)
@@ -241,7 +262,7 @@ def basis_pursuit(m: int, n: int, seed: int, dtype=np.float32, max_iter: int = 1
     rng = rng if rng is not None else np.random.default_rng(seed)
     A = rng.standard_normal((m, n)).astype(dtype)
     v = np.where(rng.random(n) < 0.5, 0.0, rng.standard_normal(n) / math.sqrt(n))
-    b = A.astype(np.float64) @ v
+    b = _matvec(A, v)
     f = Fn("ind_eq0", m, a=1.0, b=b)
     g = Fn("abs", n)
     return Problem("basis_pursuit", np.ascontiguousarray(A), f, g, max_iter=max_iter,
@@ -262,7 +283,7 @@ def entropy_max(m: int, n: int, seed: int, dtype=np.float32, max_iter: int = 100
     F = rng.standard_normal((m, n)) * math.sqrt(n)
     v = rng.random(n)
     A = np.vstack([F, np.ones((1, n))]).astype(dtype)
-    b = A[:m].astype(np.float64) @ v / v.sum()
+    b = _matvec(A[:m], v) / v.sum()
     h = ["ind_le0"] * m + ["ind_eq0"]
     f = Fn(h, m + 1, a=1.0, b=np.append(b, 1.0))
     g = Fn("neg_entr", n)
@@ -284,7 +305,7 @@ def huber_fit(m: int, n: int, seed: int, dtype=np.float32, max_iter: int = 10000
     v = rng.standard_normal(n) / math.sqrt(n)
     outlier = rng.random(m) >= 0.95
     eps = np.where(outlier, rng.uniform(0.0, 10.0, m), 0.5 * rng.standard_normal(m))
-    b = A.astype(np.float64) @ v + eps
+    b = _matvec(A, v) + eps
     f = Fn("huber", m, a=-1.0, b=-b)
     g = Fn("zero", n)
     return Problem("huber_fit", np.ascontiguousarray(A), f, g, max_iter=max_iter,
@@ -426,7 +447,7 @@ def lambda_path(m: int = 8000, n: int = 1000, R: int = 64, seed: int = 33,
     lam_max = ||A^T b||_inf, so the last point (lam = lam_max) has x* = 0.
     """
     base = lasso(m, n, seed, dtype=dtype)
-    lam_max = float(np.max(np.abs(base.A.astype(np.float64).T @ base.meta["b"])))
+    lam_max = float(np.max(np.abs(_rmatvec(base.A, base.meta["b"]))))
     if R == 1:
         lams = np.array([lo * lam_max])
     else:
