@@ -49,6 +49,8 @@ extern "C" {
                                   or the queue is full */
 #define POGS_ENOTFOUND    -5   /* batch: unknown ticket */
 #define POGS_EUNSUPPORTED -6   /* valid request this build does not implement */
+#define POGS_ETOOBIG      -7   /* input larger than the fixed device buffer of an
+                                  allocation-free entry point */
 
 /* ---- solve status (pogs_result.status) ---------------------------------- */
 #define POGS_CONVERGED  0      /* r_pri < eps_pri and r_dual < eps_dual */
@@ -276,6 +278,24 @@ int pogs_project(pogs_ctx *ctx, const void *c, const void *d, void *x, void *y, 
  * v and out have fn->len entries of dtype dt in memory `mem`. */
 int pogs_prox(const pogs_fn *fn, pogs_dtype dt, double rho, const void *v, void *out,
               pogs_mem mem, void *stream);
+
+/* pogs_prox for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops or harnesses that forbid hipMalloc): the same
+ * values as pogs_prox (bit for bit) with v and out in device memory, and the
+ * function's parameters (fn, host memory) copied into a device buffer the
+ * library owns instead of new allocations.  That buffer holds
+ * POGS_NOALLOC_SCRATCH_BYTES on every GPU the library runs on, from the first
+ * call on that GPU until the process ends.  It needs
+ *   round256(cnt) + 5 * round256(8 cnt)  bytes,  cnt = fn->len (stride 1) or 1,
+ * (a NULL parameter takes none), so per-element functions of up to about
+ * 1.6 million entries fit; larger ones return POGS_ETOOBIG and launch nothing.
+ * Every call on one GPU shares the buffer: calls that overlap on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * The call returns after its work on `stream` (NULL: the null stream) has
+ * finished.  Errors: EINVAL (as pogs_prox, or v / out NULL), ETOOBIG, EDEVICE. */
+#define POGS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int pogs_prox_noalloc(const pogs_fn *fn, pogs_dtype dt, double rho, const void *v, void *out,
+                      void *stream);
 
 /* Time the per-iteration kernels on this context with HIP events on its
  * stream (a measurement aid for benchmarks).  Requires a previous pogs_solve

@@ -17,6 +17,25 @@ struct HostFn {
   std::vector<double> a, b, c, d, e;
 };
 
+// Validate a pogs_fn of length len in place (no copies): known h codes,
+// finite parameters, c >= 0 and e >= 0 (convexity), a != 0 where c > 0.
+inline int check_fn(const pogs_fn *fn, int64_t len) {
+  if (!fn || fn->len != len || len <= 0 || !fn->h || (fn->stride != 0 && fn->stride != 1)) return POGS_EINVAL;
+  const int64_t cnt = fn->stride ? len : 1;
+  for (int64_t k = 0; k < cnt; ++k) {
+    const double a = fn->a ? fn->a[k] : 1.0;
+    const double b = fn->b ? fn->b[k] : 0.0;
+    const double c = fn->c ? fn->c[k] : 1.0;
+    const double d = fn->d ? fn->d[k] : 0.0;
+    const double e = fn->e ? fn->e[k] : 0.0;
+    if (fn->h[k] >= kNumH) return POGS_EINVAL;
+    if (!finite(a) || !finite(b) || !finite(c) || !finite(d) || !finite(e)) return POGS_EINVAL;
+    if (c < 0.0 || e < 0.0) return POGS_EINVAL;   // convexity (Section 5: c, e >= 0)
+    if (c > 0.0 && a == 0.0) return POGS_EINVAL;  // h term would be constant
+  }
+  return POGS_OK;
+}
+
 inline int expand_fn(const pogs_fn *fn, int64_t len, HostFn *out) {
   if (!fn || fn->len != len || !fn->h || (fn->stride != 0 && fn->stride != 1)) return POGS_EINVAL;
   out->h.resize(len);

@@ -23,6 +23,8 @@ LIB_PATH = os.path.join(_HERE, "libpogs.so")
 # --- constants of include/pogs.h ------------------------------------------
 POGS_OK, POGS_EINVAL, POGS_ENOMEM, POGS_EDEVICE, POGS_EAGAIN, POGS_ENOTFOUND, POGS_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
+POGS_ETOOBIG = -7
+POGS_NOALLOC_SCRATCH_BYTES = 64 << 20
 POGS_CONVERGED, POGS_MAXITER, POGS_NUMERICAL, POGS_CANCELLED, POGS_FAILED = 0, 1, 2, 3, 4
 POGS_F32, POGS_F64 = 0, 1
 POGS_ROW_MAJOR, POGS_COL_MAJOR = 0, 1
@@ -95,6 +97,8 @@ _SIGS = {
     "pogs_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "pogs_prox": (C.c_int, [C.POINTER(pogs_fn), C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
                             C.c_void_p]),
+    "pogs_prox_noalloc": (C.c_int, [C.POINTER(pogs_fn), C.c_int, C.c_double, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
     "pogs_profile_iteration": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "pogs_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(pogs_batch_cfg)]),
     "pogs_batch_submit": (C.c_int, [C.c_void_p, C.POINTER(pogs_problem), C.POINTER(C.c_uint64)]),
@@ -270,6 +274,22 @@ def pogs_prox(fn, v, rho: float, stream=None):
     out = np.empty_like(v)
     _check(_lib().pogs_prox(C.byref(holder.s), dt, float(rho), v.ctypes.data_as(C.c_void_p),
                             out.ctypes.data_as(C.c_void_p), POGS_HOST, _stream_handle(stream)), "pogs_prox")
+    return out
+
+
+def pogs_prox_noalloc(fn, v, rho: float, out, stream=None):
+    """prox_{fn,rho}(v) into the caller's tensor ``out`` through the entry point
+    that allocates no device memory (v, out: torch CUDA tensors of one dtype,
+    contiguous, len(fn) entries).  Returns ``out``."""
+    import torch
+    if not (_is_torch(v) and _is_torch(out) and v.is_cuda and out.is_cuda):
+        raise TypeError("pogs_prox_noalloc takes torch CUDA tensors")
+    if v.dtype != out.dtype or v.numel() != out.numel() or not v.is_contiguous() or not out.is_contiguous():
+        raise ValueError("v and out must be contiguous tensors of one dtype and length")
+    holder = _FnHolder(fn, v.numel())
+    s = _stream_handle(stream if stream is not None else torch.cuda.current_stream())
+    _check(_lib().pogs_prox_noalloc(C.byref(holder.s), _dtype_code(v), float(rho), C.c_void_p(v.data_ptr()),
+                                    C.c_void_p(out.data_ptr()), s), "pogs_prox_noalloc")
     return out
 
 

@@ -151,3 +151,30 @@ def test_init_sparse_rejects_bad_inputs_without_device(lib):
     assert call(2, 3, good_rp, good_ci, good_va, prm=pogs.default_params(cg_max_iter=0)) == E
     assert lib.pogs_init_sparse(None, 2, 3, 3, None, None, None, 1, 0, None, None) == E
     assert h.value is None
+
+
+def test_prox_noalloc_rejects_without_device(lib):
+    """Argument checks and the size limit of the allocation-free prox run on
+    the host before any device call (the pointers here are never touched)."""
+    from paper_1503_08366_amd import pogs
+    dp = C.POINTER(C.c_double)
+    fake = C.c_void_p(16)
+    h1 = np.array([2], np.uint8)
+    f = pogs.pogs_fn(3, 0, h1.ctypes.data_as(C.POINTER(C.c_uint8)), None, None, None, None, None)
+    assert lib.pogs_prox_noalloc(None, 0, 1.0, fake, fake, None) == pogs.POGS_EINVAL
+    assert lib.pogs_prox_noalloc(C.byref(f), 0, 1.0, None, fake, None) == pogs.POGS_EINVAL
+    assert lib.pogs_prox_noalloc(C.byref(f), 0, 0.0, fake, fake, None) == pogs.POGS_EINVAL
+    assert lib.pogs_prox_noalloc(C.byref(f), 5, 1.0, fake, fake, None) == pogs.POGS_EINVAL
+    neg = np.array([-1.0])
+    fneg = pogs.pogs_fn(3, 0, h1.ctypes.data_as(C.POINTER(C.c_uint8)), None, None, neg.ctypes.data_as(dp),
+                        None, None)
+    assert lib.pogs_prox_noalloc(C.byref(fneg), 0, 1.0, fake, fake, None) == pogs.POGS_EINVAL
+    # per-element h plus two float64 arrays: 1 + 2 * 8 bytes per entry; 4M
+    # entries need 68 MB > 64 MiB
+    N = 4 << 20
+    hN = np.full(N, 2, np.uint8)
+    aN = np.ones(N)
+    big = pogs.pogs_fn(N, 1, hN.ctypes.data_as(C.POINTER(C.c_uint8)), aN.ctypes.data_as(dp), None,
+                       aN.ctypes.data_as(dp), None, None)
+    assert lib.pogs_prox_noalloc(C.byref(big), 0, 1.0, fake, fake, None) == pogs.POGS_ETOOBIG
+    assert b"allocation-free" in lib.pogs_strerror(pogs.POGS_ETOOBIG)
