@@ -16,6 +16,7 @@
 // per lane) and widened to float64 before accumulation.
 #pragma once
 
+#include <cstdint>
 #include <utility>
 
 #include "common.hpp"
@@ -295,54 +296,88 @@ __global__ __launch_bounds__(kBlock) void gemv_n_kernel(const TA *__restrict__ A
 // ---------------------------------------------------------------------------
 // gemv_n, whole rows per wave (float32 A, rows of at most 256 NC elements)
 // ---------------------------------------------------------------------------
-// An epilogue may also provide `Pre pre(int i) const` and
-// `double row(int i, double s0, double s1, const Pre &) const`: pre() runs in
-// lane 0 when the row's loads are issued, so the per-row vector loads the
-// epilogue needs are in flight together with the row instead of after its
-// reduction.
-template <class E, class = void> struct EpiPre {
-  static constexpr bool value = false;
-  struct type {};
-};
-template <class E> struct EpiPre<E, std::void_t<decltype(std::declval<const E &>().pre(0))>> {
-  static constexpr bool value = true;
-  using type = decltype(std::declval<const E &>().pre(0));
-};
 // Each wave takes rows gw, gw + W, gw + 2W, ... (W = waves in the grid, gw
 // its global index).  A wave loads a whole row with NC 16-byte loads per lane
 // (lane l holds columns 4 l + 256 u), multiplies it by the vectors, which the
-// workgroup staged once in LDS (float32, the same columns for every row),
-// reduces across the wave and hands the row to the epilogue.  Two rows are in
-// flight per wave: the loads of row r + W are issued before row r is reduced.
+// workgroup staged once in LDS (float32, the same columns for every row), and
+// reduces across the wave.  Two rows are in flight per wave: the loads of
+// row r + W are issued before row r is reduced.
+//
+// Latency is what this pass has to hide, so:
+//  - every thread issues its loads of the vectors (16 bytes each where the
+//    vector is aligned) before anything else, then the loads of the wave's
+//    first row, and only then writes the vectors to LDS and waits at the
+//    barrier: the three memory round trips overlap instead of following one
+//    another;
+//  - the loads of a row are unconditional (a lane whose columns lie past ld
+//    reads the row's last 16 bytes again and multiplies them by the zeros
+//    staged there), and the row loop branches only on wave-uniform counts,
+//    so the compiler waits for exactly the row it is about to use;
+//  - the epilogue runs once per 64 rows for all of them: lane t keeps the
+//    sums of the batch's row t, and after the batch every lane finishes its
+//    row (with the epilogue's own loads issued by all lanes at once) instead
+//    of lane 0 finishing each row between two loads.
+// Rows of a batch are summed per lane and the block's sum follows the fixed
+// order of block_sum, so results do not depend on timing.
 template <int NRHS, int NC, class Epi, bool NT = false>
 __device__ __forceinline__ void gemv_n_rows_body(const Blk &b, const float *__restrict__ A, int m, int n, int ld,
                                                  const float *__restrict__ v0, const float *__restrict__ v1,
                                                  const Epi &epi) {
   typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int CH = 64 * NC;                       // 16-byte pieces of each staged vector
+  constexpr int CPT = (CH + kBlock - 1) / kBlock;   // pieces per thread
   __shared__ float xs[NRHS][256 * NC];
   __shared__ double bs[kBlock / kWave];
   if (epi.skip()) return;
-  for (int t = threadIdx.x; t < 256 * NC; t += kBlock) {
-    xs[0][t] = t < n ? v0[t] : 0.f;
-    if constexpr (NRHS > 1) xs[1][t] = t < n ? v1[t] : 0.f;
-  }
-  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
   const int W = b.nx * (kBlock / kWave);
   const int gw = b.x * (kBlock / kWave) + w;
-  double contrib = 0.0;
-  using Pre = typename EpiPre<Epi>::type;
-  auto load = [&](f4 *dst, Pre &pre, int r) {
+
+  f4 st[NRHS][CPT];
+  const bool aligned = (((uintptr_t)v0 | (uintptr_t)v1) & 15) == 0;
 #pragma unroll
-    for (int u = 0; u < NC; ++u) {
-      const int c = 4 * lane + 256 * u;
-      dst[u] = c < ld ? mat_load<NT>(reinterpret_cast<const f4 *>(A + (size_t)r * ld + c)) : f4{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < CPT; ++j) {
+    const int q = threadIdx.x + kBlock * j;
+    const int idx = 4 * q;
+    if (q < CH) {
+      if (aligned && idx + 3 < n) {
+        st[0][j] = *reinterpret_cast<const f4 *>(v0 + idx);
+        if constexpr (NRHS > 1) st[1][j] = *reinterpret_cast<const f4 *>(v1 + idx);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          st[0][j][k] = idx + k < n ? v0[idx + k] : 0.f;
+          if constexpr (NRHS > 1) st[1][j][k] = idx + k < n ? v1[idx + k] : 0.f;
+        }
+      }
     }
-    if constexpr (EpiPre<Epi>::value) {
-      if (lane == 0) pre = epi.pre(r);
-    }
+  }
+
+  const int nrows = gw < m ? (m - 1 - gw) / W + 1 : 0;
+  int cofs[NC];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) cofs[u] = min(4 * lane + 256 * u, ld - 4);
+  auto load = [&](f4 *dst, int r) {
+    const float *rp = A + (size_t)r * ld;
+#pragma unroll
+    for (int u = 0; u < NC; ++u) dst[u] = mat_load<NT>(reinterpret_cast<const f4 *>(rp + cofs[u]));
   };
-  auto compute = [&](const f4 *a, const Pre &pre, int r) {
+  f4 a0[NC], a1[NC];
+  if (nrows > 0) load(a0, gw);
+
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int q = threadIdx.x + kBlock * j;
+    if (q < CH) {
+      *reinterpret_cast<f4 *>(&xs[0][4 * q]) = st[0][j];
+      if constexpr (NRHS > 1) *reinterpret_cast<f4 *>(&xs[1][4 * q]) = st[1][j];
+    }
+  }
+  __syncthreads();
+
+  double contrib = 0.0;
+  double k0 = 0.0, k1 = 0.0;
+  auto compute = [&](const f4 *a, int slot) {
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int u = 0; u < NC; ++u) {
@@ -358,24 +393,24 @@ __device__ __forceinline__ void gemv_n_rows_body(const Blk &b, const float *__re
     }
     s0 = wave_sum(s0);
     if constexpr (NRHS > 1) s1 = wave_sum(s1);
-    if (lane == 0) {
-      if constexpr (EpiPre<Epi>::value) contrib += epi.row(r, s0, s1, pre);
-      else contrib += epi.row(r, s0, s1);
+    if (lane == slot) {
+      k0 = s0;
+      k1 = s1;
     }
   };
-  f4 a0[NC], a1[NC];
-  Pre p0{}, p1{};
-  int row = gw;
-  if (row < m) load(a0, p0, row);
-  while (row < m) {
-    const int r1 = row + W;
-    if (r1 < m) load(a1, p1, r1);
-    compute(a0, p0, row);
-    if (r1 >= m) break;
-    const int r2 = r1 + W;
-    if (r2 < m) load(a0, p0, r2);
-    compute(a1, p1, r1);
-    row = r2;
+  // rows i0 .. i0 + cnt - 1 of the wave per batch (cnt <= 64, even except at
+  // the end, so row i is in a0 for even i and in a1 for odd i)
+  for (int i0 = 0; i0 < nrows; i0 += kWave) {
+    const int cnt = min(kWave, nrows - i0);
+    for (int t = 0; t < cnt; t += 2) {
+      const int i = i0 + t;
+      if (i + 1 < nrows) load(a1, gw + (i + 1) * W);
+      compute(a0, t);
+      if (t + 1 >= cnt) break;
+      if (i + 2 < nrows) load(a0, gw + (i + 2) * W);
+      compute(a1, t + 1);
+    }
+    if (lane < cnt) contrib += epi.row(gw + (i0 + lane) * W, k0, k1);
   }
   const double bsum = block_sum(contrib, bs);
   if (threadIdx.x == 0) epi.block_done(b.x, bsum);

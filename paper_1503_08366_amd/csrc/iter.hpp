@@ -261,9 +261,9 @@ template <typename T> struct EpiTallPass1 : EpiBase<T> {
   __device__ void tile_done(int tile, double v) const { this->p.s_dual[tile] = v; }
 };
 
-// Row epilogues also take their per-row inputs through pre(), which the
-// whole-row kernel issues together with the row's loads; row(i, s0, s1) is
-// the form the LDS-staged kernel and the grouped launches call.
+// Row epilogues gather a row's own inputs in pre(i) and finish it in
+// row(i, s0, s1, pre) (row(i, s0, s1) is both in one call, the form every row
+// pass uses).
 template <typename T> struct Pre1 {
   T a;
 };
