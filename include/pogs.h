@@ -304,7 +304,9 @@ int pogs_prox_noalloc(const pogs_fn *fn, pogs_dtype dt, double rho, const void *
  * `reps` back-to-back launches of each iteration kernel alone, and writes
  *   ms[0] average ms per full iteration,
  *   direct projection: ms[1] prox step, ms[2] first pass over A, ms[3] solve
- *   with the cached inverse, ms[4] second pass over A;
+ *   with the cached inverse, ms[4] second pass over A; when m >= n the prox
+ *   step runs inside the first pass and its finish (ms[1] = 0, ms[2] covers
+ *   both launches);
  *   CGLS (context set up for it, every projection running cg_max_iter
  *   steps): ms[1] prox step, ms[2] the two passes that start a projection,
  *   ms[3] one CG step (two passes), ms[4] = 0

@@ -60,7 +60,7 @@ template <typename T> __device__ bool cg_first_enter(const IterArgs<T> &p) {
   __shared__ double sc[kBlock / kWave];
   if (p.ctrl->st[p.par].done) return false;
   if (blockIdx.x == 0) {
-    const double mu2 = block_total(p.s_mu + (size_t)p.par * p.nbx, p.nbx, sc);
+    const double mu2 = block_total(p.s_mu + (size_t)p.par * p.n_smu, p.n_smu, sc);
     if (threadIdx.x == 0) {
       Ctrl &q = *p.ctrl;
       const double eps_dual = q.eps_abs + q.eps_rel * sqrt(mu2);

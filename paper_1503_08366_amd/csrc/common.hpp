@@ -49,6 +49,50 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Sum over the 64 lanes of a wave without LDS traffic: DPP exchanges within
+// rows of 16 lanes (lanes 1 apart, 2 apart, then the mirror images within 8
+// and within 16), then the gfx950 permlane swaps between the two rows of each
+// 32-lane half and between the two halves.  Each step adds the two values of
+// a lane pair in the same order in both lanes, so every lane ends with the
+// same bits.  The order of the additions differs from wave_sum's.
+__device__ inline double dpp_pair_sum(double v, int ctrl) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)b, hi = (int)(b >> 32);
+  switch (ctrl) {  // the control must be a constant per call site
+    case 0xB1: lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xf, 0xf, false);
+               hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xf, 0xf, false); break;  // quad_perm 1,0,3,2
+    case 0x4E: lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xf, 0xf, false);
+               hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xf, 0xf, false); break;  // quad_perm 2,3,0,1
+    case 0x141: lo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xf, 0xf, false);
+                hi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xf, 0xf, false); break;  // row_half_mirror
+    default: lo = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xf, 0xf, false);
+             hi = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xf, 0xf, false); break;  // row_mirror
+  }
+  return v + __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+__device__ inline double swap_pair_sum16(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto l = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  return __longlong_as_double((long long)l[0] | ((long long)h[0] << 32)) +
+         __longlong_as_double((long long)l[1] | ((long long)h[1] << 32));
+}
+__device__ inline double swap_pair_sum32(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto l = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  return __longlong_as_double((long long)l[0] | ((long long)h[0] << 32)) +
+         __longlong_as_double((long long)l[1] | ((long long)h[1] << 32));
+}
+__device__ inline double wave_sum_dpp(double v) {
+  v = dpp_pair_sum(v, 0xB1);
+  v = dpp_pair_sum(v, 0x4E);
+  v = dpp_pair_sum(v, 0x141);
+  v = dpp_pair_sum(v, 0x140);
+  v = swap_pair_sum16(v);
+  return swap_pair_sum32(v);
+}
+
 // Sum over groups of W consecutive lanes (W a power of two <= 64).
 template <int W> __device__ inline double group_sum(double v) {
 #pragma unroll

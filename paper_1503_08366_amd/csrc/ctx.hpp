@@ -191,6 +191,9 @@ struct pogs_ctx {
   double *obj_dev = nullptr;
   int splits = 0, rps = 0, ncolp = 0;
   int nbx = 0, nby = 0, n_pri = 0, n_dual = 0;
+  int smu_cap = 0, syh_cap = 0;  // s_mu / s_yh slots per parity: max(nbx, n_dual), max(nby, splits, fp_blocks)
+  int fp_blocks = 0;   // workgroups of the one-pass kernel (0: the context cannot run it)
+  bool fused = false;  // iterations run the one-pass tall launches (set per solve, see IterArgs::fused)
   double ms_setup = 0.0;
   hipGraphExec_t graph = nullptr;
   int graph_chunk = 0;
@@ -202,17 +205,23 @@ struct pogs_ctx {
   size_t esz() const { return dt == POGS_F32 ? 4 : 8; }
   template <typename T> T *vecp(int idx) const {
     // vectors 0..3: x, y, xt, yt; 4..7: xh, yh, mu, nu; 8: cx, 9: dy, 10: rhs; 11..14: outputs;
-    // 15..17: CGLS p, q, s
-    static const int kind[18] = {0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 2, 0, 1, 0, 1, 0, 1, 0};  // 0: n, 1: m, 2: q
+    // 15..17: CGLS p, q, s; 18..23: the second half-step set xh, yh, mu, nu, cx, dy (odd
+    // iterations of the one-pass iteration)
+    static const int kind[24] = {0, 1, 0, 1, 0, 1, 0, 1, 0, 1, 2, 0, 1, 0, 1, 0, 1, 0,
+                                 0, 1, 0, 1, 0, 1};  // 0: n, 1: m, 2: q
     size_t off = 0;
     const size_t L[3] = {(size_t)round_up(n, 64), (size_t)round_up(m, 64), (size_t)round_up(q, 64)};
     for (int i = 0; i < idx; ++i) off += L[kind[i]];
     return reinterpret_cast<T *>(vec) + off;
   }
-  size_t vec_elems() const {  // the 18 vectors of vecp: 9 of length n, 8 of m, 1 of q
-    return 9 * (size_t)round_up(n, 64) + 8 * (size_t)round_up(m, 64) + (size_t)round_up(q, 64);
+  size_t vec_elems() const {  // the 24 vectors of vecp: 12 of length n, 11 of m, 1 of q
+    return 12 * (size_t)round_up(n, 64) + 11 * (size_t)round_up(m, 64) + (size_t)round_up(q, 64);
   }
-  template <typename T> IterArgs<T> iter_args() const {
+  // The arguments of iteration parity `set`: the one-pass iteration keeps the
+  // half step of even iterations in vectors 4..9 and of odd ones in 18..23
+  // (iteration k computes part of iteration k + 1's half step while its own is
+  // still needed); every other mode uses set 0.
+  template <typename T> IterArgs<T> iter_args(int set = 0) const {
     IterArgs<T> p{};
     p.m = (int)m;
     p.n = (int)n;
@@ -236,15 +245,33 @@ struct pogs_ctx {
     p.cx = vecp<T>(8);
     p.dy = vecp<T>(9);
     p.rhs = vecp<T>(10);
+    {
+      T *h0[6] = {vecp<T>(4), vecp<T>(5), vecp<T>(6), vecp<T>(7), vecp<T>(8), vecp<T>(9)};
+      T *h1[6] = {vecp<T>(18), vecp<T>(19), vecp<T>(20), vecp<T>(21), vecp<T>(22), vecp<T>(23)};
+      T **cur = set ? h1 : h0, **nxt = set ? h0 : h1;
+      p.xh = cur[0];
+      p.yh = cur[1];
+      p.mu = cur[2];
+      p.nu = cur[3];
+      p.cx = cur[4];
+      p.dy = cur[5];
+      p.nyh = nxt[1];
+      p.nnu = nxt[3];
+      p.ndy = nxt[5];
+    }
     p.part = part;
     p.nbx = nbx;
     p.nby = nby;
-    p.s_mu = slots;                    // 2 x nbx (by iteration parity)
-    p.s_yh = slots + 2 * nbx;          // 2 x nby
-    p.s_pri = slots + 2 * (nbx + nby);
-    p.s_dual = p.s_pri + n_pri;
+    p.fused = fused ? 1 : 0;
+    p.n_smu = fused ? n_dual : nbx;
+    p.n_syh = fused ? std::max(splits, fp_blocks) : nby;
+    p.s_mu = slots;                    // 2 x n_smu (by iteration parity), room for 2 x smu_cap
+    p.s_yh = slots + 2 * smu_cap;      // 2 x n_syh, room for 2 x syh_cap
+    p.s_pri = p.s_yh + 2 * syh_cap;    // n_pri, room for max(n_pri, fp_blocks)
+    p.s_dual = p.s_pri + std::max(n_pri, fp_blocks);
     p.par = 0;
-    p.n_pri = n_pri;
+    p.n_pri = fused ? fp_blocks : n_pri;
+    p.fp_blocks = fp_blocks;
     p.n_dual = n_dual;
     p.ctrl = ctrl;
     p.nt_rows = nt_rows;

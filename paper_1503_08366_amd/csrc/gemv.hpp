@@ -56,7 +56,7 @@ __device__ __forceinline__ void gemv_t_body(
   constexpr int VN = Vec16<TA>::N;
   constexpr int TILE = kWave * VN;
   __shared__ double red[4][NRHS][TILE];
-  if (epi.skip()) return;
+  const bool stopped = epi.skip();  // used once the first group's loads are out
 
   const int lane = threadIdx.x & (kWave - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -72,37 +72,52 @@ __device__ __forceinline__ void gemv_t_body(
 #pragma unroll
     for (int c = 0; c < VN; ++c) acc[r][c] = 0.0;
 
-  if (col < n) {
-    const TA *base = A + col;
-    int i = r0 + w;
-    for (; i + 28 < r1; i += 32) {
-      V a[8];
-      double s[8][NRHS];
+  // groups of 8 of the wave's rows (4 apart), loaded together, then used
+  const TA *base = A + (col < n ? col : 0);
+  V a[8];
+  double s[8][NRHS];
+  auto group_load = [&](int i) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        a[u] = mat_load<NT>(reinterpret_cast<const V *>(base + (size_t)(i + 4 * u) * ld));
-        s[u][0] = (double)v0[i + 4 * u];
-        if constexpr (NRHS > 1) s[u][1] = (double)v1[i + 4 * u];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int c = 0; c < VN; ++c) {
-          const double e = elem_op<SQUARE>((double)a[u][c]);
-#pragma unroll
-          for (int r = 0; r < NRHS; ++r) acc[r][c] = fma(e, s[u][r], acc[r][c]);
-        }
+    for (int u = 0; u < 8; ++u) {
+      a[u] = mat_load<NT>(reinterpret_cast<const V *>(base + (size_t)(i + 4 * u) * ld));
+      s[u][0] = (double)v0[i + 4 * u];
+      if constexpr (NRHS > 1) s[u][1] = (double)v1[i + 4 * u];
     }
-    for (; i < r1; i += 4) {
-      const V a = mat_load<NT>(reinterpret_cast<const V *>(base + (size_t)i * ld));
-      double s[NRHS];
-      s[0] = (double)v0[i];
-      if constexpr (NRHS > 1) s[1] = (double)v1[i];
+  };
+  auto group_fma = [&]() {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
 #pragma unroll
       for (int c = 0; c < VN; ++c) {
-        const double e = elem_op<SQUARE>((double)a[c]);
+        const double e = elem_op<SQUARE>((double)a[u][c]);
 #pragma unroll
-        for (int r = 0; r < NRHS; ++r) acc[r][c] = fma(e, s[r], acc[r][c]);
+        for (int r = 0; r < NRHS; ++r) acc[r][c] = fma(e, s[u][r], acc[r][c]);
+      }
+  };
+  const bool first = col < n && r0 + w + 28 < r1;
+  if (first) group_load(r0 + w);
+  if (stopped) return;
+
+  if (col < n) {
+    int i = r0 + w;
+    if (first) {
+      group_fma();
+      i += 32;
+    }
+    for (; i + 28 < r1; i += 32) {
+      group_load(i);
+      group_fma();
+    }
+    for (; i < r1; i += 4) {
+      const V x = mat_load<NT>(reinterpret_cast<const V *>(base + (size_t)i * ld));
+      double sv[NRHS];
+      sv[0] = (double)v0[i];
+      if constexpr (NRHS > 1) sv[1] = (double)v1[i];
+#pragma unroll
+      for (int c = 0; c < VN; ++c) {
+        const double e = elem_op<SQUARE>((double)x[c]);
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) acc[r][c] = fma(e, sv[r], acc[r][c]);
       }
     }
   }
@@ -141,7 +156,7 @@ __device__ __forceinline__ void gemv_t_finish_body(const Blk &b, int n, int spli
   constexpr int G = kBlock / kFinishCols;
   __shared__ double red[G][2][kFinishCols];
   __shared__ double bs[kBlock / kWave];
-  if (epi.skip()) return;
+  const bool stopped = epi.skip();  // used once the partial loads are out
   const int c = threadIdx.x % kFinishCols;
   const int g = threadIdx.x / kFinishCols;
   const int cg = b.x * kFinishCols + c;
@@ -152,6 +167,7 @@ __device__ __forceinline__ void gemv_t_finish_body(const Blk &b, int n, int spli
 #pragma unroll
       for (int r = 0; r < NRHS; ++r) s[r] += part[(size_t)(sp * NRHS + r) * ncolp + cg];
   }
+  if (stopped) return;
   red[g][0][c] = s[0];
   red[g][1][c] = s[1];
   __syncthreads();
@@ -328,7 +344,7 @@ __device__ __forceinline__ void gemv_n_rows_body(const Blk &b, const float *__re
   constexpr int CPT = (CH + kBlock - 1) / kBlock;   // pieces per thread
   __shared__ float xs[NRHS][256 * NC];
   __shared__ double bs[kBlock / kWave];
-  if (epi.skip()) return;
+  const bool stopped = epi.skip();  // used once the first loads are out
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
   const int W = b.nx * (kBlock / kWave);
   const int gw = b.x * (kBlock / kWave) + w;
@@ -364,6 +380,7 @@ __device__ __forceinline__ void gemv_n_rows_body(const Blk &b, const float *__re
   };
   f4 a0[NC], a1[NC];
   if (nrows > 0) load(a0, gw);
+  if (stopped) return;  // nothing is written once the solver has stopped
 
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {

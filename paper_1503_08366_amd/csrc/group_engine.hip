@@ -251,6 +251,9 @@ int GroupEngine::add(const Input &in, int *handle) {
   double *sl = at<double>(M.arena, g.o_slots);
   it.nbx = g.nbx;
   it.nby = g.nby;
+  it.n_smu = g.nbx;
+  it.n_syh = g.nby;
+  it.fused = 0;
   it.s_mu = sl;
   it.s_yh = sl + 2 * g.nbx;
   it.s_pri = sl + 2 * (g.nbx + g.nby);

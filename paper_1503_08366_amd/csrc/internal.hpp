@@ -1,6 +1,8 @@
 // Internal structures shared by the kernels' host launchers and the C ABI.
 #pragma once
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "../../include/pogs.h"
 
@@ -16,6 +18,8 @@ struct CtrlState {
   int done;         // 0 running, else 1 + pogs status
   int pending;      // 1: the partial sums of iteration k wait for their stop test
   int by_gap;       // stopped by the gap test: the result is (x, y, -rho x~, -rho y~)
+  int spec;         // one-pass iteration: this iteration's y-side half step and column sums
+                    // are the ones the previous iteration computed with an unchanged rho
   double eta, eps_gap;  // gap of the state after k iterations and its tolerance (gap rule)
 };
 
@@ -78,6 +82,22 @@ constexpr size_t kSegBytes = (size_t)1 << 20;
 constexpr int kSegRows = 512;
 constexpr int kSegGrid = 2048;
 
+// Workgroups of the one-pass tall iteration (tall_one_pass_body) for an m x n
+// matrix with leading dimension ld, or 0 where it does not apply (not float32,
+// m < n, rows longer than 2048 entries, sparse, or rows over 1024 entries and
+// more than 64 rows per wave, which keeps that variant's float32 column sums
+// short).  Each workgroup (8 waves) writes one split partial of the column
+// sums (2 ld float64 values): 256 of them, as many as are resident at once at
+// two waves per SIMD, and at least 64 rows per workgroup so small problems do
+// not pay for partials they cannot use.
+constexpr int kOnePassWaves = 8;
+inline int one_pass_blocks(int64_t m, int64_t n, int ld, int elem_size, bool sparse) {
+  if (elem_size != 4 || sparse || m < n || ld > 2048) return 0;
+  const int64_t cap = 256;
+  if (ld > 1024 && m > 64 * kOnePassWaves * cap) return 0;
+  return (int)std::min<int64_t>(cap, std::max<int64_t>(1, (m + 63) / 64));
+}
+
 // Default load policy of the passes over A (when not tuned): a matrix larger
 // than this is streamed with non-temporal loads (the MI355X last-level cache
 // holds 256 MB; below this size A partly stays cached from one pass to the
@@ -96,9 +116,15 @@ template <typename T> struct IterArgs {
   T *cx, *dy;            // projection inputs c = x_r + x~, d = y_r + y~
   T *rhs;                // right-hand side of the reduced system (length q)
   double *part;          // gemv_t split partials
-  double *s_mu, *s_yh;   // prox-block partial sums of mu_h^2, y_h^2 (2 x nbx, 2 x nby: by parity)
+  double *s_mu, *s_yh;   // partial sums of mu_h^2, y_h^2 (2 x n_smu, 2 x n_syh: by parity)
   double *s_pri, *s_dual;// partial sums of the residuals
   int nbx, nby;          // prox blocks over x (n) and y (m)
+  int n_smu, n_syh;      // slots of s_mu, s_yh per parity: nbx, nby when a prox launch
+                         // writes them; finish tiles and row splits in the fused iteration
+  int fused;             // 1: the one-pass tall iteration (m >= n, float32, rows of at most
+                         // 2048 entries, direct projection, residual stopping)
+  T *nyh, *nnu, *ndy;    // the next iteration's half-step set, y side (one-pass iteration)
+  int fp_blocks;         // workgroups of the one-pass kernel
   int n_pri, n_dual;     // number of residual partial slots
   Ctrl *ctrl;
   int par;               // parity of this iteration (selects st[] and the prox slots)

@@ -35,6 +35,29 @@ __global__ __launch_bounds__(kBlock) void prox_kernel(IterArgs<T> p) {
   prox_body<T>(hw_block(), p);
 }
 
+template <typename T, bool NT>
+__global__ __launch_bounds__(kBlock) void tall_pass1_prox_kernel(IterArgs<T> p, int rps, int ncolp) {
+  tall_pass1_prox_body<T, NT>(hw_block(), p, rps, ncolp);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void tall_finish_prox_kernel(IterArgs<T> p, int splits, int ncolp) {
+  tall_finish_prox_body<T>(hw_block(), p, splits, ncolp);
+}
+
+template <int NC, bool NT>
+__global__ __launch_bounds__(kOnePassThreads) void tall_one_pass_kernel(IterArgs<float> p, int ncolp) {
+  tall_one_pass_body<NC, NT>(hw_block(), p, ncolp);
+}
+
+template <bool NT> static void launch_one_pass_nt(const IterArgs<float> &p, int ncolp, hipStream_t s) {
+  const dim3 grid((unsigned)p.fp_blocks), block(kOnePassThreads);
+  if (p.ld <= 256) hipLaunchKernelGGL((tall_one_pass_kernel<1, NT>), grid, block, 0, s, p, ncolp);
+  else if (p.ld <= 512) hipLaunchKernelGGL((tall_one_pass_kernel<2, NT>), grid, block, 0, s, p, ncolp);
+  else if (p.ld <= 1024) hipLaunchKernelGGL((tall_one_pass_kernel<4, NT>), grid, block, 0, s, p, ncolp);
+  else hipLaunchKernelGGL((tall_one_pass_kernel<8, NT>), grid, block, 0, s, p, ncolp);
+}
+
 // Standalone projection (no solver state): outputs go to caller buffers.
 template <typename T> struct ProjArgs {
   const T *c, *d;
@@ -161,15 +184,29 @@ int gemv_n_blocks(int m, int ncols, int elem_size, int) {
 }
 
 // which: 0 prox (with the previous stop test), 1 first pass over A, 2 solve, 3 second pass over A.
+// The one-pass tall iteration (p.fused) has no separate prox launch: part 0 is
+// empty, part 1 is the stop test with the first pass where the previous
+// iteration's results do not stand (tall_pass1_prox_body) and the finish
+// with the x side of the prox step, part 3 the pass that reads A for both
+// iterations.
 template <typename T>
 void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps, int ncolp, hipStream_t s) {
   const bool tall = p.m >= p.n;
   switch (which) {
     case 0:
+      if (p.fused) break;
       hipLaunchKernelGGL(prox_kernel<T>, dim3(p.nbx + p.nby), dim3(kBlock), 0, s, p);
       break;
     case 1:
-      if (tall) {
+      if (p.fused) {
+        const dim3 grid((unsigned)cdiv(p.n, gemv_t_tile(sizeof(T))), (unsigned)splits);
+        if (p.nt_cols)
+          hipLaunchKernelGGL((tall_pass1_prox_kernel<T, true>), grid, dim3(kBlock), 0, s, p, rps, ncolp);
+        else
+          hipLaunchKernelGGL((tall_pass1_prox_kernel<T, false>), grid, dim3(kBlock), 0, s, p, rps, ncolp);
+        hipLaunchKernelGGL(tall_finish_prox_kernel<T>, dim3((unsigned)cdiv(p.n, kFinishCols)), dim3(kBlock), 0, s,
+                           p, splits, ncolp);
+      } else if (tall) {
         EpiTallPass1<T> e{{p}};
         gemv_t<T, T, 2>(p.A, p.m, p.n, p.ld, p.dy, p.nu, splits, rps, p.part, ncolp, e, s, p.nt_cols);
       } else {
@@ -188,7 +225,12 @@ void launch_iteration_part(const IterArgs<T> &p, int which, int splits, int rps,
       }
       break;
     default:
-      if (tall) {
+      if (p.fused) {
+        if constexpr (std::is_same<T, float>::value) {
+          if (p.nt_rows) launch_one_pass_nt<true>(p, ncolp, s);
+          else launch_one_pass_nt<false>(p, ncolp, s);
+        }
+      } else if (tall) {
         EpiTallPass2<T> e{{p}};
         gemv_n<T, T, 2>(p.A, p.m, p.n, p.ld, p.x, p.xh, e, s, p.nt_rows);
       } else {

@@ -158,8 +158,12 @@ template <typename T> int alloc_iteration(pogs_ctx *c) {
   if (c->sparse) c->splits = 1;  // no column-sum partials
   // prox sums (two parities), residual sums, CGLS sums (||s||^2 and s^T p by
   // step parity, ||q||^2), then the unscale kernel's sums
-  const int nslots = 2 * (c->nbx + c->nby) + c->n_pri + c->n_dual + 4 * c->n_dual + c->n_pri +
-                     2 * (c->nbx + c->nby) + c->nbx + c->nby;
+  c->fp_blocks = one_pass_blocks(m, n, c->ld, (int)sizeof(T), c->sparse);
+  c->smu_cap = std::max(c->nbx, c->n_dual);
+  c->syh_cap = std::max({c->nby, c->splits, c->fp_blocks});
+  c->fused = false;
+  const int nslots = 2 * (c->smu_cap + c->syh_cap) + std::max(c->n_pri, c->fp_blocks) + c->n_dual +
+                     4 * c->n_dual + c->n_pri + 2 * (c->nbx + c->nby) + c->nbx + c->nby;
   const int ntiles = (int)cdiv(n, gemv_t_tile(sizeof(T)));
   // raw functions: fh0 | gh0 | f0 | g0, uploaded in one copy
   Carve raw;
@@ -174,7 +178,7 @@ template <typename T> int alloc_iteration(pogs_ctx *c) {
   const size_t o_fh = cv.take(m), o_gh = cv.take(n);
   const size_t o_fs = cv.take((size_t)5 * m * sizeof(T)), o_gs = cv.take((size_t)5 * n * sizeof(T));
   const size_t o_raw = cv.take(c->fn_bytes);
-  const size_t o_part = cv.take((size_t)c->splits * 2 * c->ncolp * 8);
+  const size_t o_part = cv.take((size_t)std::max(c->splits, c->fp_blocks) * 2 * c->ncolp * 8);
   const size_t o_slots = cv.take((size_t)nslots * 8);
   const size_t o_cnt = cv.take((size_t)(ntiles + 64) * sizeof(unsigned));
   const size_t o_ctrl = cv.take(sizeof(Ctrl));
@@ -541,8 +545,10 @@ int even_chunk(int requested) {
 // cg_cap > 0 selects the CGLS projection with that step cap; gap adds the
 // gap test after each prox step.
 template <typename T> void launch_chunk(pogs_ctx *c, int chunk, int cg_cap, int gap, hipStream_t s) {
-  IterArgs<T> p = c->iter_args<T>();
+  const IterArgs<T> p0 = c->iter_args<T>(0), p1 = c->iter_args<T>(c->fused ? 1 : 0);
+  IterArgs<T> p = p0;
   for (int i = 0; i < chunk; ++i) {
+    p = (i & 1) ? p1 : p0;  // half-step set by iteration parity (one-pass iteration)
     p.par = i & 1;
     if (c->sparse) launch_iteration_cg_sparse<T>(p, cg_cap, s);
     else if (cg_cap > 0) launch_iteration_cg<T>(p, c->splits, c->rps, c->ncolp, cg_cap, s);
@@ -582,6 +588,8 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   hipStream_t s = c->stream;
   const int cg_cap = p.projection == POGS_PROJ_CGLS ? p.cg_max_iter : 0;
   const int gap = p.stop_rule == POGS_STOP_GAP ? 1 : 0;
+  // tall float32 direct solves with the residual rule read A once per iteration
+  c->fused = c->fp_blocks > 0 && cg_cap == 0 && !gap;
   int rc;
   if ((rc = upload_fns<T>(c, f, g))) return rc;
   // zero state (Algorithm 1 starts from x = y = x~ = y~ = 0), or the warm start
@@ -645,8 +653,10 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
               cs.eps_pri, cs.r_dual, cs.eps_dual, cs.rho);
     if (cs.done) break;
   }
-  // unscale into the caller's buffers (device) or staging (host)
-  const IterArgs<T> ia = c->iter_args<T>();
+  // unscale into the caller's buffers (device) or staging (host); the
+  // one-pass iteration left the last iteration's half step in set (k - 1) % 2
+  const int last_set = c->fused ? ((c->ctrl_host->st[0].k - 1) & 1) : 0;
+  const IterArgs<T> ia = c->iter_args<T>(last_set);
   T *xo = c->vecp<T>(11), *yo = c->vecp<T>(12), *muo = c->vecp<T>(13), *nuo = c->vecp<T>(14);
   if (out->mem == POGS_DEVICE) {
     xo = (T *)out->x;
@@ -702,6 +712,7 @@ template <typename T> int profile_impl(pogs_ctx *c, int reps, double *ms) {
     h.st[b].rescale = 1.0;
   }
   const int cg_cap = c->proj == POGS_PROJ_CGLS ? c->params.cg_max_iter : 0;
+  c->fused = c->fp_blocks > 0 && cg_cap == 0;  // the launches of a residual-rule solve
   h.cg_tol = c->params.cg_tol;
   h.cg_cap = cg_cap;
   h.cg.stop = -1;
@@ -730,6 +741,10 @@ template <typename T> int profile_impl(pogs_ctx *c, int reps, double *ms) {
   };
   ms[4] = 0.0;
   for (int w = 0; w < (cg_cap > 0 ? 3 : 4); ++w) {
+    if (w == 0 && p.fused) {  // no prox launch: the prox step is inside pass 1
+      ms[1] = 0.0;
+      continue;
+    }
     part(w);  // warm
     POGS_HIP_TRY(hipEventRecord(e0, s));
     for (int i = 0; i < reps; ++i) part(w);
