@@ -596,6 +596,46 @@ class Result:
     eps_gap: float = float("nan")
 
 
+def warm_state(Ah, fh, gh, D, E, rho0: float, x0=None, nu0=None):
+    """Iteration state (x, y, x~, y~) in the scaled variables from a warm start
+    (x0, nu0) in the original ones (Section 5; either may be None).
+
+    Reading of the state: x = E^-1 x0 and y = A^ x (a point of the graph);
+    y~ = -(D^-1 nu0) / rho0, since nu_h = -rho y~ whenever the prox step leaves y
+    unchanged; x~ = -A^T y~, the relation every projection restores.  From an
+    optimal pair this state is a fixed point of the iteration; x0 = nu0 = 0 is
+    the cold start.
+
+    Reading of the estimate Section 5 promises when only one of them is
+    given: one step of the proximal point method from zero for the missing
+    half, i.e. the value the prox step of the iteration itself returns.
+      x0 only:  nu^ = rho0 (y - prox_f^(y)) (a subgradient of f^ at
+                prox_f^(y), the dual of the prox step from (y, y~ = 0)), so
+                y~ = prox_f^(y) - y;
+      nu0 only: mu^ = -A^T nu^ = -rho0 x~ (dual feasibility, Section 2) and
+                x = prox_g^(mu^ / rho0) = prox_g^(-x~) (the x half step from
+                (x = 0, x~)), then y = A^ x.
+    """
+    m, n = Ah.shape
+    x = np.zeros(n)
+    y = np.zeros(m)
+    xt = np.zeros(n)
+    yt = np.zeros(m)
+    if x0 is not None:
+        x = np.asarray(x0, dtype=np.float64) / E
+        y = Ah @ x
+    if nu0 is not None:
+        yt = -(np.asarray(nu0, dtype=np.float64) / D) / rho0
+        xt = -(Ah.T @ yt)
+    if x0 is not None and nu0 is None:
+        yt = prox_param(fh, y, rho0) - y
+        xt = -(Ah.T @ yt)
+    elif nu0 is not None and x0 is None:
+        x = prox_param(gh, -xt, rho0)
+        y = Ah @ x
+    return x, y, xt, yt
+
+
 def solve(A, f, g, params: Params = Params(), record: bool = False,
           D: Optional[np.ndarray] = None, E: Optional[np.ndarray] = None,
           x0: Optional[np.ndarray] = None, nu0: Optional[np.ndarray] = None) -> Result:
@@ -628,12 +668,8 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
     The returned tuple is the last half-step tuple (Section 5) mapped back to
     the original variables: x = E x_h, y = D^-1 y_h, mu = E^-1 mu_h, nu = D nu_h.
 
-    Warm start (Section 5 lets the caller supply x0 and nu0; the state they
-    define is not spelled out).  Reading: x = E^-1 x0 and y = A^ x (a point of
-    the graph); y~ = -(D^-1 nu0) / rho0, since nu_h = -rho y~ whenever the
-    prox step leaves y unchanged; x~ = -A^T y~, the relation every projection
-    restores.  From an optimal pair this state is a fixed point of the
-    iteration; x0 = 0, nu0 = 0 is the cold start.
+    Warm start (Section 5: the caller may supply x0 and nu0; with only one
+    of them the other is estimated): see warm_state.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
@@ -656,16 +692,7 @@ def solve(A, f, g, params: Params = Params(), record: bool = False,
     proj = None if cg else Projector(Ah)
     cg_steps = 0
 
-    x = np.zeros(n)
-    y = np.zeros(m)
-    xt = np.zeros(n)
-    yt = np.zeros(m)
-    if x0 is not None:
-        x = np.asarray(x0, dtype=np.float64) / E
-        y = Ah @ x
-    if nu0 is not None:
-        yt = -(np.asarray(nu0, dtype=np.float64) / D) / params.rho0
-        xt = -(Ah.T @ yt)
+    x, y, xt, yt = warm_state(Ah, fh, gh, D, E, params.rho0, x0, nu0)
     rho = params.rho0
     l = u = 0
     hist = {"r_pri": [], "r_dual": [], "eps_pri": [], "eps_dual": [], "rho": [],

@@ -327,3 +327,81 @@ def test_warm_start_along_a_lambda_path_saves_iterations():
     assert warm.converged and cold.converged
     assert warm.iters < cold.iters
     assert abs(warm.optval - cold.optval) <= 1e-3 * max(1.0, abs(cold.optval))
+
+
+# --------------------------------------------------------------------------
+# Warm start with one half missing (Section 5: "estimated"; reading: one
+# proximal point step from zero, the value the prox step itself returns)
+# --------------------------------------------------------------------------
+def test_estimated_dual_from_x0_closed_form():
+    """f = 1/2 ||y - b||^2 with rho: prox(v) = (b + rho v)/(1 + rho), so the
+    estimated scaled dual is y~ = prox(y) - y = (b - y)/(1 + rho) with y = A x0,
+    and x~ = -A^T y~ (no pre-conditioning: D = E = 1)."""
+    rng = np.random.default_rng(21)
+    m, n, rho = 40, 15, 1.7
+    A = rng.normal(size=(m, n))
+    b = rng.normal(size=m)
+    x0 = rng.normal(size=n)
+    f = W.Fn("square", m, b=b)
+    g = W.Fn("abs", n, c=0.3)
+    x, y, xt, yt = O.warm_state(A, O.as_param(f), O.as_param(g), np.ones(m), np.ones(n), rho, x0=x0)
+    y_ref = A @ x0
+    np.testing.assert_allclose(x, x0, rtol=0, atol=0)
+    np.testing.assert_allclose(y, y_ref, rtol=1e-14)
+    np.testing.assert_allclose(yt, (b - y_ref) / (1.0 + rho), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(xt, -(A.T @ ((b - y_ref) / (1.0 + rho))), rtol=1e-12, atol=1e-13)
+
+
+def test_estimated_dual_vanishes_at_a_feasible_point_of_an_indicator():
+    """f = indicator(y <= b): at a strictly feasible y = A x0 the prox leaves y
+    unchanged, so the estimated dual is zero."""
+    rng = np.random.default_rng(22)
+    m, n = 30, 10
+    A = rng.normal(size=(m, n))
+    x0 = rng.normal(size=n)
+    b = A @ x0 + rng.uniform(0.1, 1.0, m)
+    f = W.Fn("ind_le0", m, b=b)
+    g = W.Fn("zero", n)
+    _, _, xt, yt = O.warm_state(A, O.as_param(f), O.as_param(g), np.ones(m), np.ones(n), 1.0, x0=x0)
+    assert np.array_equal(yt, np.zeros(m)) and np.array_equal(xt, np.zeros(n))
+
+
+def test_estimated_primal_from_nu0_closed_form():
+    """g = 1/2 ||x||^2: prox(v) = rho v/(1 + rho); from nu0 alone, y~ = -nu0/rho,
+    x~ = -A^T y~ and x = prox(-x~) = -A^T nu0 / (1 + rho), y = A x."""
+    rng = np.random.default_rng(23)
+    m, n, rho = 35, 12, 0.6
+    A = rng.normal(size=(m, n))
+    nu0 = rng.normal(size=m)
+    f = W.Fn("square", m, b=rng.normal(size=m))
+    g = W.Fn("square", n)
+    x, y, xt, yt = O.warm_state(A, O.as_param(f), O.as_param(g), np.ones(m), np.ones(n), rho, nu0=nu0)
+    np.testing.assert_allclose(yt, -nu0 / rho, rtol=1e-15)
+    np.testing.assert_allclose(x, -(A.T @ nu0) / (1.0 + rho), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(y, A @ x, rtol=1e-12, atol=1e-14)
+
+
+def test_warm_start_from_x_alone_converges_faster():
+    """From x* alone the estimated dual starts the iteration near the optimum:
+    the same optimum in fewer iterations than a cold start."""
+    p = W.lasso(120, 40, seed=24, dtype=np.float64)
+    ref = O.solve(p.A, p.f, p.g, TIGHT)
+    assert ref.converged
+    prm = O.Params(eps_cmp=2.0 ** -52)
+    cold = O.solve(p.A, p.f, p.g, prm)
+    warm = O.solve(p.A, p.f, p.g, prm, x0=ref.x)
+    assert warm.converged and cold.converged
+    assert warm.iters < cold.iters, (warm.iters, cold.iters)
+    assert abs(warm.optval - ref.optval) <= 1e-3 * max(1.0, abs(ref.optval))
+
+
+def test_warm_start_from_nu_alone_reaches_the_optimum():
+    """From nu* alone the estimated primal is the x half step the iteration
+    takes from x = 0 (zero for l1 terms whose dual lies inside the threshold:
+    the dual alone does not locate x there); the solve still reaches the
+    optimum."""
+    p = W.lasso(120, 40, seed=24, dtype=np.float64)
+    ref = O.solve(p.A, p.f, p.g, TIGHT)
+    warm = O.solve(p.A, p.f, p.g, O.Params(eps_cmp=2.0 ** -52), nu0=ref.nu)
+    assert warm.converged
+    assert abs(warm.optval - ref.optval) <= 1e-3 * max(1.0, abs(ref.optval))
