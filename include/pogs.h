@@ -230,11 +230,14 @@ int pogs_init_sparse(pogs_ctx **out, int64_t m, int64_t n, int64_t nnz, const in
  * Warm start (Section 5: the caller may supply x0 and nu0): x0 (len n) and
  * nu0 (len m), in the context's dtype and in the memory space out->mem says,
  * are a primal point and a dual estimate in the original variables; either
- * may be NULL (that part starts from zero, as Algorithm 1 does).  The state
- * they define: x = E^-1 x0 and y = A^ x on the graph, y~ = -(D^-1 nu0)/rho0
- * (the scaled dual the prox step returns when it leaves y unchanged) and
- * x~ = -A^T y~ (the relation every projection restores); from an optimal
- * pair this state is a fixed point and the solve stops after one iteration.
+ * may be NULL.  The state they define: x = E^-1 x0 and y = A^ x on the graph,
+ * y~ = -(D^-1 nu0)/rho0 (the scaled dual the prox step returns when it leaves
+ * y unchanged) and x~ = -A^T y~ (the relation every projection restores);
+ * from an optimal pair this state is a fixed point and the solve stops after
+ * one iteration.  When only one is given the other is estimated (Section 5),
+ * as one proximal point step from zero: x0 only -> y~ = prox_f^(y) - y
+ * (rho0), then x~ = -A^T y~; nu0 only -> x = prox_g^(-x~), then y = A^ x.
+ * Both NULL is the cold start of Algorithm 1.
  * The projection is params->projection: a context set up for the direct
  * projection also runs CGLS solves; a context set up for CGLS only runs CGLS.
  * params->stop_rule selects the residual or the gap test (see pogs_stop_rule).

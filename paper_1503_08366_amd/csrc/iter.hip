@@ -284,7 +284,9 @@ void launch_project(const IterArgs<T> &p, int splits, int rps, int ncolp, const 
 // Warm start from (x0, nu0) in the original variables: x = E^-1 x0 and
 // y = A^ x (a point of the graph); y~ = -(D^-1 nu0) / rho0 (the scaled dual
 // the prox step returns when it leaves y unchanged); x~ = -A^T y~ (the
-// relation every projection restores).
+// relation every projection restores).  With only one of them, the other is
+// estimated by warm_estimate_kernel: x0 only -> y~ = prox_f^(y) - y, then
+// x~ = -A^T y~; nu0 only -> x = prox_g^(-x~), then y = A^ x.
 // ---------------------------------------------------------------------------
 template <typename T> struct EpiWarmY : EpiNoSkip<T> {  // y = A x
   T *y;
@@ -310,9 +312,21 @@ void launch_warm_start(const IterArgs<T> &p, int splits, int rps, int ncolp, con
   if (nu0) {
     hipLaunchKernelGGL(warm_scale_kernel<T>, dim3(cdiv(p.m, kBlock)), dim3(kBlock), 0, s, nu0, D, true,
                        -1.0 / rho0, p.m, p.yt);
+  } else if (x0) {
+    hipLaunchKernelGGL(warm_estimate_kernel<T>, dim3(cdiv(p.m, kBlock)), dim3(kBlock), 0, s, p.f, (const T *)p.y,
+                       p.yt, p.m, (T)rho0, 0);
+  }
+  if (nu0 || x0) {
     EpiWarmXt<T> e;
     e.xt = p.xt;
     gemv_t<T, T, 1>(p.A, p.m, p.n, p.ld, (const T *)p.yt, (const T *)p.yt, splits, rps, p.part, ncolp, e, s);
+  }
+  if (nu0 && !x0) {
+    hipLaunchKernelGGL(warm_estimate_kernel<T>, dim3(cdiv(p.n, kBlock)), dim3(kBlock), 0, s, p.g, (const T *)p.xt,
+                       p.x, p.n, (T)rho0, 1);
+    EpiWarmY<T> e;
+    e.y = p.y;
+    gemv_n<T, T, 1>(p.A, p.m, p.n, p.ld, (const T *)p.x, (const T *)p.x, e, s);
   }
 }
 

@@ -897,6 +897,21 @@ __device__ __forceinline__ void unscale_body(
   }
 }
 
+// The half of a warm start the caller left out (Section 5: it is
+// estimated), as one proximal point step from zero, the value the prox step
+// of the iteration returns: primal = 0 -> out = prox_F(v) - v (the scaled
+// dual y~ from y; nu^ = rho (y - prox_f^(y))); primal = 1 -> out = prox_F(-v)
+// (x from the scaled dual x~: prox_g^(mu^ / rho) with mu^ = -A^T nu^ = -rho x~).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void warm_estimate_kernel(FnDev<T> F, const T *v, T *out, int len, T rho,
+                                                               int primal) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= len) return;
+  const T vi = v[i];
+  if (primal) out[i] = prox_param<T>(F.h[i], F.a[i], F.b[i], F.c[i], F.d[i], F.e[i], -vi, rho);
+  else out[i] = prox_param<T>(F.h[i], F.a[i], F.b[i], F.c[i], F.d[i], F.e[i], vi, rho) - vi;
+}
+
 // out = f * (v0 / S) or f * (v0 * S), elementwise (the warm start's change of variables)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void warm_scale_kernel(const T *v0, const double *S, bool divide, double f,

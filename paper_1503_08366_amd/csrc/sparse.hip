@@ -383,10 +383,20 @@ void launch_warm_start_sparse(const IterArgs<T> &p, const double *D, const doubl
                        p.x);
     POGS_SP_DISPATCH(p.sa.lpr, sp_warm_kernel, p.sa.grid, s, p.sa, (const T *)p.x, EpiSpWarm<T>{p.y, 1.0})
   }
+  // the missing half estimated as in the dense warm start (one proximal point step)
   if (nu0) {
     hipLaunchKernelGGL(warm_scale_kernel<T>, dim3(cdiv(p.m, kBlock)), dim3(kBlock), 0, s, nu0, D, true,
                        -1.0 / rho0, p.m, p.yt);
+  } else if (x0) {
+    hipLaunchKernelGGL(warm_estimate_kernel<T>, dim3(cdiv(p.m, kBlock)), dim3(kBlock), 0, s, p.f, (const T *)p.y,
+                       p.yt, p.m, (T)rho0, 0);
+  }
+  if (nu0 || x0)
     POGS_SP_DISPATCH(p.sat.lpr, sp_warm_seg_kernel, p.sat.grid, s, p.sat, (const T *)p.yt, EpiSpWarm<T>{p.xt, -1.0})
+  if (nu0 && !x0) {
+    hipLaunchKernelGGL(warm_estimate_kernel<T>, dim3(cdiv(p.n, kBlock)), dim3(kBlock), 0, s, p.g, (const T *)p.xt,
+                       p.x, p.n, (T)rho0, 1);
+    POGS_SP_DISPATCH(p.sa.lpr, sp_warm_kernel, p.sa.grid, s, p.sa, (const T *)p.x, EpiSpWarm<T>{p.y, 1.0})
   }
 }
 

@@ -200,14 +200,21 @@ def test_solve_classes(kind, shape, dt):
     _check_solve(prob, dt)
 
 
-def test_maxiter_status_and_repeat_solves():
+@pytest.mark.parametrize("adaptive", [1, 0])
+@pytest.mark.parametrize("cap", [7, 8])
+def test_maxiter_status_and_repeat_solves(cap, adaptive):
+    """The tuple returned at the iteration cap is that iteration's half step,
+    for an odd and an even cap (the tall float32 iteration keeps consecutive
+    half steps in alternating buffers), with Algorithm 3 on and off."""
     prob = W.lasso(300, 100, 5)
-    prm = P.default_params(max_iter=7, chunk_iters=3)
+    prm = P.default_params(max_iter=cap, chunk_iters=3, adaptive_rho=adaptive)
     with P.Context(prob.A, prm) as ctx:
         r = ctx.solve(prob.f, prob.g, prm)
-        assert r.status == P.POGS_MAXITER and r.iters == 7
-        ref = O.solve(prob.A.astype(np.float64), prob.f, prob.g, O.Params(max_iter=7, eps_cmp=FLT_EPS))
+        assert r.status == P.POGS_MAXITER and r.iters == cap
+        ref = O.solve(prob.A.astype(np.float64), prob.f, prob.g,
+                      O.Params(max_iter=cap, eps_cmp=FLT_EPS, adaptive_rho=bool(adaptive)))
         np.testing.assert_allclose(r.x, ref.x, rtol=1e-4, atol=1e-5)
+        np.testing.assert_allclose(r.nu, ref.nu, rtol=1e-4, atol=1e-5)
         # a second solve on the same context starts from zero again
         r2 = ctx.solve(prob.f, prob.g, prm)
         np.testing.assert_array_equal(r.x, r2.x)

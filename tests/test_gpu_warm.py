@@ -82,3 +82,43 @@ def test_warm_start_from_device_tensors():
         dev = ctx.solve(p.f, p.g, device_out=True, x0=torch.tensor(ref.x), nu0=torch.tensor(ref.nu))
     assert dev.iters == host.iters
     np.testing.assert_array_equal(np.asarray(dev.x.cpu()) if hasattr(dev.x, "cpu") else dev.x, host.x)
+
+
+@pytest.mark.parametrize("half", ["x0", "nu0"])
+@pytest.mark.parametrize("kind", ["tall_lasso", "wide_lasso", "logistic", "nnls"])
+def test_half_warm_start_matches_the_oracle(kind, half):
+    """Only one half given: the other is estimated (Section 5) the same way
+    on both sides (one proximal point step from zero); iteration counts and
+    objectives follow the oracle's warm-started solve."""
+    if kind == "tall_lasso":
+        p = W.lasso(1500, 400, 71)
+    elif kind == "wide_lasso":
+        p = W.lasso(300, 900, 72)
+    elif kind == "logistic":
+        p = W.logistic(1200, 300, 73)
+    else:
+        p = W.nnls_from(W.lasso(1400, 350, 74))
+    prm = O.Params(eps_cmp=FLT_EPS)
+    start = O.solve(p.A.astype(np.float64), p.f, p.g, TIGHT)
+    kw = {"x0": start.x} if half == "x0" else {"nu0": start.nu}
+    ref = O.solve(p.A.astype(np.float64), p.f, p.g, prm, **kw)
+    with P.Context(p.A) as ctx:
+        r = ctx.solve(p.f, p.g, **kw)
+    print(kind, half, "gpu", r.iters, "oracle", ref.iters, flush=True)
+    assert r.converged and ref.converged
+    assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
+    assert abs(r.optval - ref.optval) <= _tol(ref.optval)
+
+
+def test_half_warm_start_sparse_matches_the_oracle():
+    p = W.sparse_problem("lasso", 3000, 800, 12, seed=75)
+    dense = p.A.toarray().astype(np.float64)
+    start = O.solve(dense, p.f, p.g, TIGHT)
+    prm = P.default_params(projection="cgls")
+    ref = O.solve(dense, p.f, p.g, O.Params(eps_cmp=FLT_EPS, projection="cgls", cg_max_iter=prm.cg_max_iter,
+                                            cg_tol=prm.cg_tol), x0=start.x)
+    with P.SparseContext(p.A) as ctx:
+        r = ctx.solve(p.f, p.g, x0=start.x)
+    assert r.converged and ref.converged
+    assert abs(r.iters - ref.iters) <= 3, (r.iters, ref.iters)
+    assert abs(r.optval - ref.optval) <= _tol(ref.optval)
