@@ -52,6 +52,8 @@ struct Ctrl {
   int cg_cap;     // CGLS step cap per projection
   int stop_gap;   // 1: gap-based stopping (Section 3.4) instead of the residual test
   CgState cg;
+  double spec_rho[2];  // one-pass iteration: the rho with which the previous iteration's
+                       // one-pass kernel formed the half step of parity i's iteration
 };
 
 // Separable function as device arrays (per element).

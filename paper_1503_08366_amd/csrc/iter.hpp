@@ -25,18 +25,21 @@ namespace pogs {
 // (in that order).  The first kSlotUnroll loads are issued together: a loop
 // whose trip count the compiler cannot see waits for each load before the
 // next, and these slot loads open every kernel that runs the stop test.
+// The sums are taken over kBlock threads whatever the workgroup size, so that
+// a wider workgroup (with its other threads adding zeros) gets the same bits.
 constexpr int kSlotUnroll = 4;
 __device__ inline double slot_partial(const double *s, int cnt) {
+  if ((int)threadIdx.x >= kBlock) return 0.0;
   double v[kSlotUnroll];
 #pragma unroll
   for (int k = 0; k < kSlotUnroll; ++k) {
-    const int i = threadIdx.x + k * blockDim.x;
+    const int i = threadIdx.x + k * kBlock;
     v[k] = i < cnt ? s[i] : 0.0;
   }
   double t = 0.0;
 #pragma unroll
   for (int k = 0; k < kSlotUnroll; ++k) t += v[k];
-  for (int i = threadIdx.x + kSlotUnroll * blockDim.x; i < cnt; i += blockDim.x) t += s[i];
+  for (int i = threadIdx.x + kSlotUnroll * kBlock; i < cnt; i += kBlock) t += s[i];
   return t;
 }
 
@@ -316,16 +319,20 @@ __device__ __forceinline__ void tall_pass1_prox_body(const Blk &b, const IterArg
     }
   };
 
-  if (threadIdx.x == 0) st = p.ctrl->st[1 - par];
+  __shared__ double spec_rho;
+  if (threadIdx.x == 0) {
+    st = p.ctrl->st[1 - par];
+    spec_rho = p.ctrl->spec_rho[par];
+  }
   double part[4];
   control_partials(p, 1 - par, part);
   V a[8];
   __syncthreads();
   const bool after_iteration = st.pending != 0;  // an iteration ran before this one in the solve
   if (!st.done && st.pending) control_apply(p, part, st, bs);
-  // the previous iteration's one-pass kernel computed this step with the
-  // same rho (no rescale): its results stand
-  const bool spec = after_iteration && !st.done && st.rescale == 1.0;
+  // the previous iteration's one-pass kernel computed this step with the rho
+  // Algorithm 3 has just chosen (and the matching rescale): its results stand
+  const bool spec = after_iteration && !st.done && st.rho == spec_rho;
   if (b.x == 0 && b.y == 0 && threadIdx.x == 0) {
     CtrlState out = st;
     out.pending = st.done ? 0 : 1;
@@ -509,11 +516,14 @@ __device__ __forceinline__ void tall_finish_prox_body(const Blk &b, const IterAr
 // entries).  While a row of A is in registers the kernel finishes iteration k
 // (second pass: y = A x, t = A x_h, y~ = d - y, (t - y_h)^2) and starts
 // iteration k + 1: the y side of its prox step from the y, y~ just formed,
-// with iteration k's rho and no rescale, then that row's share of the column
-// sums A^T [d', nu_h'].  Algorithm 3 keeps rho for most iterations; when the
-// stop test after iteration k changes it (or stops), the next first-pass
-// kernel recomputes those values (tall_pass1_prox_body) and these are
-// discarded.  Iteration k + 1's half step goes to the other half-step set, so
+// then that row's share of the column sums A^T [d', nu_h'].  The half step
+// needs the rho that Algorithm 3 picks after iteration k.  Of its inputs only
+// the primal residual is still open here (the dual residual and both
+// tolerances are final once the first pass's finish has run), so each
+// workgroup evaluates the rule with those values and takes, for the open
+// test, the outcome of the previous iteration's.  When the stop test after
+// iteration k picks another rho (or stops), the next first-pass kernel
+// recomputes those values (tall_pass1_prox_body) and these are discarded.  Iteration k + 1's half step goes to the other half-step set, so
 // iteration k's (the result, should the stop test end the solve here) stays.
 // Workgroups of kOnePassThreads; wave gw takes rows gw, gw + W, ... as in
 // gemv_n_rows_body; lane l keeps the column sums of columns 4 l + 256 u + c
@@ -535,9 +545,14 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
   using Acc = typename std::conditional<(NC >= 8), float, double>::type;
   __shared__ float xs[2][256 * NC];
   __shared__ Acc red[NW][2][256 * NC];  // every wave's column sums (128 KB)
-  __shared__ double bs[NW];
+  __shared__ double bs[4 * NW];
+  __shared__ double rho_next;
   const CtrlState &gst = p.ctrl->st[p.par];
   const bool stopped = gst.done != 0;  // used once the first loads are out
+  double part[4];
+  part[0] = slot_partial(p.s_mu + (size_t)p.par * p.n_smu, p.n_smu);
+  part[1] = part[2] = 0.0;  // the primal tolerance is not needed (see below)
+  part[3] = slot_partial(p.s_dual, p.n_dual);
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x >> 6;
   const int W = b.nx * NW;
@@ -584,8 +599,25 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
       *reinterpret_cast<f4 *>(&xs[1][4 * q]) = stg[1][j];
     }
   }
+  // the sums are those of control_apply bit for bit (threads past kBlock add zeros)
+  block_sum4(part, bs);
+  if (threadIdx.x == 0) {
+    const Ctrl &q = *p.ctrl;
+    const double r_dual = sqrt(part[3]);
+    const double eps_dual = q.eps_abs + q.eps_rel * sqrt(part[0]);
+    const double rho = gst.rho;
+    double next = rho;
+    if (q.adaptive) {
+      if (r_dual < eps_dual && q.tau * gst.k > gst.l) next = q.delta * rho;
+      else if (gst.r_pri < gst.eps_pri && q.tau * gst.k > gst.u) next = rho / q.delta;
+    }
+    rho_next = next;
+    if (b.x == 0) p.ctrl->spec_rho[1 - p.par] = next;
+  }
   __syncthreads();
-  const float rho = (float)gst.rho, alpha = (float)p.ctrl->alpha;
+  const double rho_d = rho_next;
+  const float rho = (float)rho_d, resc = (float)(rho_d != gst.rho ? gst.rho / rho_d : 1.0);
+  const float alpha = (float)p.ctrl->alpha;
 
   Acc acc[2][NC][4];
 #pragma unroll
@@ -627,9 +659,9 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
     const float ytv = bcast(b_dy, t) - yv;
     const double r = s1 - (double)bcast(b_yh, t);
     pri += r * r;
-    // iteration k + 1: y side of the half step with this iteration's rho
+    // iteration k + 1: y side of the half step with the predicted rho
     const HalfStep<float> hs = half_step<float>(__builtin_amdgcn_readlane(b_fh, t), bcast(b_fa, t), bcast(b_fb, t),
-                                                bcast(b_fc, t), bcast(b_fd, t), bcast(b_fe, t), yv, ytv, rho, 1.0f,
+                                                bcast(b_fc, t), bcast(b_fd, t), bcast(b_fe, t), yv, ytv, rho, resc,
                                                 alpha);
     yh2 += (double)hs.h * (double)hs.h;
     if (lane == t) {
