@@ -54,19 +54,20 @@ __device__ inline double wave_sum(double v) {
 // and within 16), then the gfx950 permlane swaps between the two rows of each
 // 32-lane half and between the two halves.  Each step adds the two values of
 // a lane pair in the same order in both lanes, so every lane ends with the
-// same bits.  The order of the additions differs from wave_sum's.
+// same bits.  The order of the additions differs from wave_sum's.  Every
+// pattern reads a valid lane, so the DPP moves need no old value.
 __device__ inline double dpp_pair_sum(double v, int ctrl) {
   const long long b = __double_as_longlong(v);
   int lo = (int)b, hi = (int)(b >> 32);
   switch (ctrl) {  // the control must be a constant per call site
-    case 0xB1: lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xf, 0xf, false);
-               hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xf, 0xf, false); break;  // quad_perm 1,0,3,2
-    case 0x4E: lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xf, 0xf, false);
-               hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xf, 0xf, false); break;  // quad_perm 2,3,0,1
-    case 0x141: lo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xf, 0xf, false);
-                hi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xf, 0xf, false); break;  // row_half_mirror
-    default: lo = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xf, 0xf, false);
-             hi = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xf, 0xf, false); break;  // row_mirror
+    case 0xB1: lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xf, 0xf, false);
+               hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xf, 0xf, false); break;  // quad_perm 1,0,3,2
+    case 0x4E: lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xf, 0xf, false);
+               hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xf, 0xf, false); break;  // quad_perm 2,3,0,1
+    case 0x141: lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xf, 0xf, false);
+                hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xf, 0xf, false); break;  // row_half_mirror
+    default: lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xf, 0xf, false);
+             hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xf, 0xf, false); break;  // row_mirror
   }
   return v + __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }

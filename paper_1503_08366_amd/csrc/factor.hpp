@@ -322,73 +322,81 @@ template <class Fn> __device__ inline void acc_store(const F64Acc acc[2][2], Fn 
   f64_tile_store(acc, (w >> 1) * 32, (w & 1) * 32, fn);
 }
 
-// 1 / sqrt(p) for p > 0: the hardware estimate refined by two Newton steps
-// for f(y) = 1 / y^2 - p, y <- y (3 - p y^2) / 2 (each step squares the
-// relative error, so the estimate's ~2^-22 becomes the float64 rounding
-// level).  Cheaper on the factor's critical path than sqrt() followed by a
-// division, which are both correctly rounded expansions.
-__device__ inline double rsqrt_newton(double p) {
-  double y = __builtin_amdgcn_rsq(p);
-  const double h = 0.5 * p;
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
-  return y;
+// sqrt(p) and 1 / sqrt(p) for p > 0 by Goldschmidt's coupled iteration
+// (g -> sqrt(p), h -> 1 / (2 sqrt(p)); e = 1/2 - g h, then g += g e and
+// h += h e), started from the hardware reciprocal square root estimate.
+// Each step squares the relative error, so two steps take the estimate's
+// ~2^-22 to the float64 rounding level.  The two updates of a step are
+// independent, so the dependent chain is one multiply and two fmas per step,
+// shorter on the factor's critical path than sqrt() and a division, which
+// are correctly rounded expansions.
+__device__ inline void sqrt_rsqrt(double p, double &g, double &rs) {
+  const double y = __builtin_amdgcn_rsq(p);
+  g = p * y;
+  double h = 0.5 * y;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+  }
+  rs = 2.0 * h;
 }
 
 // Value of v in lane K of each row of 16 lanes, for every lane of that row
 // (DPP row_newbcast: a VGPR-to-VGPR move at ALU rate, no scalar registers).
+// Every lane reads a valid source lane, so the moves need no old value.
 template <int K> __device__ inline double row_bcast(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + K, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + K, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x150 + K, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + K, 0xf, 0xf, false);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 // 16 x 16 leaf, one copy per row of 16 lanes: lane r holds row r of the
-// block in a[0..15].  Column J of the Cholesky factor: the pivot's
-// reciprocal square root rd gives L_JJ = piv rd (lane J) and L_rJ = a_J rd,
-// then the right-looking update a_k -= L_rJ L_kJ of the later columns.
-template <int J, int... K>
-__device__ inline void leaf_update(double (&a)[16], double lj, std::integer_sequence<int, K...>) {
-  ((a[J + 1 + K] = fma(-lj, row_bcast<J + 1 + K>(lj), a[J + 1 + K])), ...);
+// block in a[0..15] and column r of W = L^{-1} in x[0..15].  Column J of the
+// Cholesky factor: L_JJ = sqrt(piv) (lane J), L_rJ = a_J / sqrt(piv), then
+// the right-looking update a_I -= L_rJ L_IJ of the later columns.  Step J of
+// W's forward substitution by columns needs exactly column J of L and
+// 1 / L_JJ, which every lane holds at that point (the broadcasts are shared):
+// x_J = acc_J / L_JJ, then acc_I -= L_IJ x_J (acc starts as column r of I).
+// The pivots of I + G are at least 1 in exact arithmetic; one that is not
+// positive and finite is counted in nbad (the setup then fails), off the
+// dependent chain.
+template <int I>
+__device__ inline void leaf_pair(double (&a)[16], double (&acc)[16], double lj, double xj) {
+  const double l = row_bcast<I>(lj);  // L_IJ
+  a[I] = fma(-lj, l, a[I]);
+  acc[I] = fma(-l, xj, acc[I]);
 }
-template <int J> __device__ inline void leaf_column(double (&a)[16], double &rdiag, unsigned &nbad, int r) {
-  double piv = row_bcast<J>(a[J]);
-  if (!(piv > 0.0) || !isfinite(piv)) {
-    ++nbad;
-    piv = 1.0;
-  }
-  const double rd = rsqrt_newton(piv);
-  if (r == J) rdiag = rd;
-  const double lj = (r == J ? piv : a[J]) * rd;
+template <int J, int... K>
+__device__ inline void leaf_updates(double (&a)[16], double (&acc)[16], double lj, double xj,
+                                    std::integer_sequence<int, K...>) {
+  (leaf_pair<J + 1 + K>(a, acc, lj, xj), ...);
+}
+template <int J>
+__device__ inline void leaf_column(double (&a)[16], double (&acc)[16], double (&x)[16], unsigned &nbad, int r) {
+  const double piv = row_bcast<J>(a[J]);
+  nbad += (piv > 0.0 && isfinite(piv)) ? 0u : 1u;
+  double g, rd;
+  sqrt_rsqrt(piv, g, rd);
+  const double lj = r == J ? g : a[J] * rd;
   a[J] = lj;
-  leaf_update<J>(a, lj, std::make_integer_sequence<int, 15 - J>{});
-  __builtin_amdgcn_sched_barrier(0);  // keep each column's broadcasts in its column (register pressure)
+  x[J] = acc[J] * rd;
+  leaf_updates<J>(a, acc, lj, x[J], std::make_integer_sequence<int, 15 - J>{});
 }
 template <int... J>
-__device__ inline void leaf_factor(double (&a)[16], double &rdiag, unsigned &nbad, int r,
-                                   std::integer_sequence<int, J...>) {
-  (leaf_column<J>(a, rdiag, nbad, r), ...);
-}
-
-// W = L^{-1} of the leaf, column r of W in lane r (x[0..15]), by forward
-// substitution swept by columns of L: once W_K is known every later row
-// takes its term, so the dependent chain is one product and one fma per K.
-template <int K, int... R>
-__device__ inline void inv_update(double (&acc)[16], const double (&a)[16], double xk,
-                                  std::integer_sequence<int, R...>) {
-  ((acc[K + 1 + R] = fma(-row_bcast<K + 1 + R>(a[K]), xk, acc[K + 1 + R])), ...);
-}
-template <int K>
-__device__ inline void inv_column(double (&acc)[16], double (&x)[16], const double (&a)[16], double rdiag) {
-  x[K] = acc[K] * row_bcast<K>(rdiag);
-  inv_update<K>(acc, a, x[K], std::make_integer_sequence<int, 15 - K>{});
-  __builtin_amdgcn_sched_barrier(0);
-}
-template <int... K>
-__device__ inline void leaf_inverse(double (&acc)[16], double (&x)[16], const double (&a)[16], double rdiag,
-                                    std::integer_sequence<int, K...>) {
-  (inv_column<K>(acc, x, a, rdiag), ...);
+__device__ inline void leaf_factor_inverse(double (&a)[16], double (&x)[16], unsigned &nbad, int r,
+                                           std::integer_sequence<int, J...>) {
+  double acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = r == k ? 1.0 : 0.0;
+  (leaf_column<J>(a, acc, x, nbad, r), ...);
+  // An empty statement that every lane executes and that reads the results:
+  // without it the compiler moves the leaf into the branch where only some
+  // lanes store it, and that schedule holds over 300 registers instead of ~110.
+#pragma unroll
+  for (int k = 0; k < 16; ++k) asm volatile("" ::"v"(a[k]), "v"(x[k]));
 }
 
 // Value of v in lane l (l uniform), as two 32-bit lane reads.
@@ -420,8 +428,8 @@ template <class FA, class FB> __device__ inline F64Acc mfma_block16(F64Acc acc, 
 // Then X = L^{-1} by block diagonals: X_ii = W_i, and for i > j
 // X_ij = -W_i sum_{j <= k < i} L_ik X_kj, the partial sums parked in the
 // (unused) upper blocks of X.  Writes L_kk (upper part zeroed) back into K and
-// L_kk^{-1} into Dinv block kb.  A non-positive pivot counts in *bad and is
-// replaced by 1.  Launched with 256 threads.
+// L_kk^{-1} into Dinv block kb.  A pivot that is not positive and finite
+// counts in *bad.  Launched with 256 threads.
 __device__ __forceinline__ void potrf_diag(double *K, int Q, int kb, double *Dinv, unsigned *bad, CholLds &s) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
@@ -445,19 +453,17 @@ __device__ __forceinline__ void potrf_diag(double *K, int Q, int kb, double *Din
   for (int sb = 0; sb < 4; ++sb) {
     const int s0 = sb * 16;
     // leaf (every row of 16 lanes of every wave computes the same values)
-    double a[16], x[16], acc[16];
-    double rdiag = 0.0;  // 1 / L_jj, kept in lane j
+    double a[16], x[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) a[k] = s.L[s0 + r16][s0 + k];
-    leaf_factor(a, rdiag, nbad, r16, std::make_integer_sequence<int, 16>{});
+    leaf_factor_inverse(a, x, nbad, r16, std::make_integer_sequence<int, 16>{});
+    if (lane < 16) {  // every wave holds the leaf: wave w writes columns 4w .. 4w + 3
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) acc[rr] = r16 == rr ? 1.0 : 0.0;
-    leaf_inverse(acc, x, a, rdiag, std::make_integer_sequence<int, 16>{});
-    if (w == 0 && lane < 16) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) s.L[s0 + lane][s0 + k] = a[k];
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) s.X[s0 + rr][s0 + lane] = x[rr];
+      for (int k = 0; k < 16; ++k)
+        if ((k >> 2) == w) {
+          s.L[s0 + lane][s0 + k] = a[k];
+          s.X[s0 + k][s0 + lane] = x[k];
+        }
     }
     __syncthreads();
     // panel
