@@ -343,14 +343,12 @@ __device__ inline void sqrt_rsqrt(double p, double &g, double &rs) {
   rs = 2.0 * h;
 }
 
-// Value of v in lane K of each row of 16 lanes, for every lane of that row
-// (DPP row_newbcast: a VGPR-to-VGPR move at ALU rate, no scalar registers).
-// Every lane reads a valid source lane, so the moves need no old value.
+// Value of v in lane K of each row of 16 lanes, for every lane of that row:
+// one 64-bit DPP move (row_newbcast is the DPP control gfx950 allows on 64-bit
+// moves), no scalar registers.  Every lane reads a valid source lane, so the
+// old value (with bound_ctrl set) is never used.
 template <int K> __device__ inline double row_bcast(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x150 + K, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + K, 0xf, 0xf, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + K, 0xf, 0xf, true);
 }
 
 // 16 x 16 leaf, one copy per row of 16 lanes: lane r holds row r of the
@@ -427,27 +425,15 @@ template <class FA, class FB> __device__ inline F64Acc mfma_block16(F64Acc acc, 
 //   update: B_IJ -= L_Is L_Js^T for s < J <= I (f64 MFMA).
 // Then X = L^{-1} by block diagonals: X_ii = W_i, and for i > j
 // X_ij = -W_i sum_{j <= k < i} L_ik X_kj, the partial sums parked in the
-// (unused) upper blocks of X.  Writes L_kk (upper part zeroed) back into K and
-// L_kk^{-1} into Dinv block kb.  A pivot that is not positive and finite
+// (unused) upper blocks of X.  potrf_diag_core works on the block in s.L
+// (only its lower triangle, diagonal included, is read) and leaves L in the
+// lower blocks of s.L and X in the lower blocks of s.X; potrf_diag loads
+// block kb of K first and afterwards writes L_kk (upper part zeroed) back into
+// K and L_kk^{-1} into Dinv block kb.  A pivot that is not positive and finite
 // counts in *bad.  Launched with 256 threads.
-__device__ __forceinline__ void potrf_diag(double *K, int Q, int kb, double *Dinv, unsigned *bad, CholLds &s) {
+__device__ __forceinline__ void potrf_diag_core(CholLds &s, unsigned *bad) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
-  double *blk = K + (size_t)kb * NB * Q + (size_t)kb * NB;
-  // every load in flight before the first LDS store (256 threads)
-  constexpr int kPer = NB * NB / 256;
-  double v[kPer];
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int e = t + 256 * u;
-    v[u] = blk[(size_t)(e / NB) * Q + e % NB];
-  }
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int e = t + 256 * u;
-    s.L[e / NB][e % NB] = v[u];
-  }
-  __syncthreads();
   unsigned nbad = 0;
 #pragma unroll
   for (int sb = 0; sb < 4; ++sb) {
@@ -514,6 +500,26 @@ __device__ __forceinline__ void potrf_diag(double *K, int Q, int kb, double *Din
     __syncthreads();
   }
   if (nbad && t == 0) atomicAdd(bad, nbad);
+}
+
+__device__ __forceinline__ void potrf_diag(double *K, int Q, int kb, double *Dinv, unsigned *bad, CholLds &s) {
+  const int t = threadIdx.x;
+  double *blk = K + (size_t)kb * NB * Q + (size_t)kb * NB;
+  // every load in flight before the first LDS store (256 threads)
+  constexpr int kPer = NB * NB / 256;
+  double v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = t + 256 * u;
+    v[u] = blk[(size_t)(e / NB) * Q + e % NB];
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = t + 256 * u;
+    s.L[e / NB][e % NB] = v[u];
+  }
+  __syncthreads();
+  potrf_diag_core(s, bad);
   double *dv = Dinv + (size_t)kb * NB * NB;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {

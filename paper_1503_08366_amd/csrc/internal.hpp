@@ -168,11 +168,13 @@ int run_gram(const T *A, int m, int n, int ld, double *K, int Q, float *ws32, do
              size_t ws_bytes, hipStream_t s);
 size_t gram_workspace_bytes(int m, int n, int elem_size);
 
-// Cholesky of K (Q x Q float64, in place, lower) and the explicit inverse
-// written as T into Kinv (q x q, leading dim ldk).  ws: Q*Q doubles + Q*64 doubles.
+// Cholesky of K (Q x Q float64, full symmetric; overwritten) and the explicit
+// inverse written as T into Kinv (q x q, leading dim ldk).  ws holds
+// factor_workspace_bytes(Q).
 template <typename T>
 int run_factor_inverse(double *K, int q, int Q, T *Kinv, int ldk, double *ws, unsigned *bad,
                        hipStream_t s);
+size_t factor_workspace_bytes(int Q);
 
 // ---- launchers (iter.hip) -------------------------------------------------
 template <typename T> void launch_scale_fn(const uint8_t *h, const double *a, const double *b,

@@ -94,7 +94,7 @@ template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, 
     POGS_HIP_TRY(host_uploader().upload(stage, A, src_elems * selem, s));
     src = stage;
   }
-  unsigned *flags;  // [0] non-finite A, [1] factorisation failures
+  unsigned *flags;  // [0] non-finite A, [1] factorisation failures, [2] factor step flag
   if ((rc = tmp.alloc((void **)&flags, 64))) return rc;
   POGS_HIP_TRY(hipMemsetAsync(flags, 0, 64, s));
   launch_layout<T>(src, sdt, ord, lda, m, n, (T *)c->A, c->ld, flags, s);
@@ -130,7 +130,7 @@ template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, 
     // one block serves the Gram partials, then the factor's workspace
     // (stream order separates the two uses)
     const size_t gb = gram_workspace_bytes(m, n, sizeof(T));
-    const size_t fb = ((size_t)Q * Q + (size_t)Q * 64) * 8;
+    const size_t fb = factor_workspace_bytes(Q);
     void *ws;
     if ((rc = tmp.alloc(&ws, std::max(gb, fb)))) return rc;
     if ((rc = run_gram<T>((const T *)c->A, m, n, c->ld, K, Q, (float *)ws, (double *)ws, gb, s))) return rc;

@@ -7,8 +7,9 @@
 //                 f32 accumulation inside a K split; splits summed in f64),
 //                 K = I + G in float64 (Section 3.5)
 //   factor      : blocked Cholesky K = L L^T in float64 (64 x 64 blocks, f64
-//                 MFMA for the block products), L^{-1} by blocked substitution,
-//                 K^{-1} = L^{-T} L^{-1}, stored in T for the iterations.
+//                 MFMA for the block products), L^{-1} by blocked substitution
+//                 and K^{-1} = L^{-T} L^{-1} accumulated row by row of L^{-1}
+//                 in the same steps, stored in T for the iterations.
 #include <atomic>
 
 #include "setup.hpp"
@@ -347,56 +348,48 @@ int run_gram(const T *A, int m, int n, int ld, double *K, int Q, float *ws32, do
 // ---------------------------------------------------------------------------
 // Blocked Cholesky and explicit inverse (float64, 64 x 64 blocks)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double *K, int Q, int kb, double *Dinv, unsigned *bad) {
-  __shared__ CholLds s;
-  potrf_diag(K, Q, kb, Dinv, bad, s);
+__global__ __launch_bounds__(256) void chol_first_kernel(const double *K, double *B, int Q, double *Dinv,
+                                                         unsigned *bad, unsigned *step) {
+  __shared__ CholLds cl;
+  chol_first_body(K, B, Q, Dinv, bad, step, cl);
 }
 
-
-__global__ __launch_bounds__(256) void factor_panel_kernel(double *K, double *X, int Q, int nbt, int kb,
-                                                           const double *Dinv) {
-  factor_panel_body(blockIdx.x, K, X, Q, nbt, kb, Dinv);
+// L_I0 = K_I0 X_00^T for I > 0 (the panel of step 0).
+__global__ __launch_bounds__(256) void chol_panel0_kernel(double *K, int Q, const double *Dinv) {
+  __shared__ F64Stage st;
+  trsm_tile(K, Q, 0, 1 + blockIdx.x, Dinv, st);
 }
 
-
-__global__ __launch_bounds__(256) void factor_update_kernel(double *K, double *X, int Q, int nbt, int kb,
-                                                            double *Dinv, unsigned *bad) {
-  factor_update_body(blockIdx.x, K, X, Q, nbt, kb, Dinv, bad);
+template <typename T>
+__global__ __launch_bounds__(256, 2) void chol_step_kernel(double *K, double *B, int Q, int nbt, int kb, double *Dinv,
+                                                           int q, T *Kinv, int ldk, unsigned *bad, unsigned *step) {
+  chol_step_body<T>(blockIdx.x, K, B, Q, nbt, kb, Dinv, q, Kinv, ldk, bad, step);
 }
 
 __global__ __launch_bounds__(256) void trtri_init_kernel(double *X, int Q) {
   trtri_init_rows(X, Q, blockIdx.x * 8, min(Q, (int)blockIdx.x * 8 + 8));
 }
 
+size_t factor_workspace_bytes(int Q) { return ((size_t)Q * Q + (size_t)Q * NB) * sizeof(double); }
 
-template <typename T>
-__global__ __launch_bounds__(256) void kinv_kernel(const double *X, int Q, int nbt, int q, T *Kinv, int ldk) {
-  kinv_body<T>(blockIdx.x, X, Q, nbt, q, Kinv, ldk);
-}
-
+// K (Q x Q, full symmetric I + G; overwritten) -> K^{-1} as T (q x q, row
+// stride ldk).  Workspace: B (Q x Q) and the diagonal block inverses (Q x 64).
+// bad[0] counts failures; bad[1] is the step flag.
 template <typename T>
 int run_factor_inverse(double *K, int q, int Q, T *Kinv, int ldk, double *ws, unsigned *bad, hipStream_t s) {
   const int nbt = Q / NB;
-  double *X = ws;                        // Q x Q
-  double *Dinv = ws + (size_t)Q * Q;     // nbt blocks of 64 x 64
-  // X <- I; then per step kb: [panel solve + inverse scaling], [trailing
-  // update + next diagonal factor + inverse update].  Step kb of the blocked
-  // inverse needs block column kb of L and X_kb,. only, so it runs in the
-  // launches of Cholesky step kb.
-  hipLaunchKernelGGL(trtri_init_kernel, dim3(cdiv(Q, 8)), dim3(256), 0, s, X, Q);
-  hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, K, Q, 0, Dinv, bad);
-  for (int kb = 0; kb < nbt; ++kb) {
-    const int rest = nbt - kb - 1;
-    hipLaunchKernelGGL(factor_panel_kernel, dim3(rest + kb + 1), dim3(256), 0, s, K, X, Q, nbt, kb,
-                       (const double *)Dinv);
-    if (rest > 0)
-      hipLaunchKernelGGL(factor_update_kernel, dim3(rest * (rest + 1) / 2 + rest * (kb + 1)), dim3(256), 0, s, K, X,
-                         Q, nbt, kb, Dinv, bad);
-  }
+  double *B = ws;
+  double *Dinv = B + (size_t)Q * Q;
+  unsigned *step = bad + 1;
+  hipLaunchKernelGGL(trtri_init_kernel, dim3(cdiv(Q, 8)), dim3(256), 0, s, B, Q);
+  hipLaunchKernelGGL(chol_first_kernel, dim3(1), dim3(256), 0, s, (const double *)K, B, Q, Dinv, bad, step);
+  if (nbt > 1) hipLaunchKernelGGL(chol_panel0_kernel, dim3(nbt - 1), dim3(256), 0, s, K, Q, (const double *)Dinv);
   // padding columns of K^{-1} are read (times zero) by the row-dot kernels: keep them zero
   (void)hipMemsetAsync(Kinv, 0, (size_t)q * ldk * sizeof(T), s);
-  hipLaunchKernelGGL((kinv_kernel<T>), dim3(nbt * (nbt + 1) / 2), dim3(256), 0, s, (const double *)X, Q, nbt, q,
-                     Kinv, ldk);
+  const int nupd = nbt * (nbt + 1) / 2;
+  for (int kb = 0; kb < nbt; ++kb)
+    hipLaunchKernelGGL((chol_step_kernel<T>), dim3(nupd), dim3(256), 0, s, K, B, Q, nbt, kb, Dinv, q, Kinv, ldk, bad,
+                       step);
   return POGS_OK;
 }
 

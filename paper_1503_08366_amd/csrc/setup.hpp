@@ -220,6 +220,192 @@ __device__ __forceinline__ void factor_update_body(int b, double *K, double *X, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Blocked Cholesky K = L L^T with L^{-1} and K^{-1} folded in (Section 3.5),
+// as the single-problem setup runs it: one launch per step k, in which
+//   workgroup 0          factors the next diagonal block I = k + 1 from
+//                        K_II - L_Ik L_Ik^T (formed into LDS), stores its
+//                        inverse X_II in Dinv block I and in B tile (I, I), and
+//                        releases step flag I;
+//   trailing workgroups  K_IJ -= L_Ik L_Jk^T (k < J <= I, except (I, I) above);
+//                        those of column k + 1 then wait for flag k + 1 and
+//                        form L_I,k+1 = K_I,k+1 X_{k+1,k+1}^T in place;
+//   inverse workgroups   B_rj -= L_rk X_kj (r > k, j <= k; L X = I by block
+//                        forward substitution, B starts as I); those of row
+//                        k + 1 then wait for the flag and form
+//                        X_k+1,j = X_{k+1,k+1} B_k+1,j in place;
+//   K^{-1} workgroups    K^{-1}_IJ += X_kI^T X_kJ (J <= I <= k), adding row k
+//                        of X = L^{-1} once it is final (K^{-1} = X^T X).
+// So the critical chain of a step is one product, the diagonal factor and
+// one product, with no launch between the factor and its panel.
+// K^{-1}_IJ (I >= J) accumulates in K's tile (J, I), which the factorisation
+// no longer reads (an upper tile, or a diagonal tile already factored); the
+// last step writes it as T, mirrored.  Every launch has nbt (nbt + 1) / 2
+// workgroups.  Workgroup 0 is dispatched before every workgroup that waits for
+// it; a wait gives up after kStepSpin polls and counts a failure in *bad
+// (the setup then reports an error) rather than hang.
+// ---------------------------------------------------------------------------
+constexpr unsigned kStepSpin = 1u << 22;
+
+// Every wave's global stores complete (workgroup scope: they are in the
+// device cache), then thread 0 publishes step value v with a device-scope
+// release, which writes that cache back once for the whole workgroup.
+__device__ inline void step_release(unsigned *step, unsigned v) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(step, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The workgroup's own stores complete first (it reads them back), then thread
+// 0 polls for step value >= v with relaxed loads (an acquire per poll would
+// invalidate the caches every other workgroup is using) and acquires once at
+// device scope when it sees it; the barrier orders the other waves after it.
+__device__ inline void step_wait(unsigned *step, unsigned v, unsigned *bad) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned n = 0;
+    while (__hip_atomic_load(step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++n == kStepSpin) {
+        atomicAdd(bad, 1u);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// X_II = L_II^{-1} from potrf_diag_core (upper blocks zeroed) into Dinv block
+// I and B tile (I, I).
+__device__ inline void store_block_inverse(const CholLds &cl, double *Dinv, double *B, int Q, int I) {
+  double *dv = Dinv + (size_t)I * NB * NB;
+  double *bt = B + (size_t)I * NB * Q + (size_t)I * NB;
+#pragma unroll 4
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int r = e / NB, c = e % NB;
+    const double v = (c >> 4) > (r >> 4) ? 0.0 : cl.X[r][c];
+    dv[e] = v;
+    bt[(size_t)r * Q + c] = v;
+  }
+}
+
+// First diagonal block (before step 0): factor K_00, store X_00, reset the step flag.
+__device__ __forceinline__ void chol_first_body(const double *K, double *B, int Q, double *Dinv, unsigned *bad,
+                                                unsigned *step, CholLds &cl) {
+  constexpr int kPer = NB * NB / 256;
+  double v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    v[u] = K[(size_t)(e / NB) * Q + e % NB];
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    cl.L[e / NB][e % NB] = v[u];
+  }
+  __syncthreads();
+  potrf_diag_core(cl, bad);
+  store_block_inverse(cl, Dinv, B, Q, 0);
+  if (threadIdx.x == 0) *step = 0;
+}
+
+// Workgroup 0 of step kb: D = K_II - L_I,kb L_I,kb^T (I = kb + 1) into LDS
+// (K_II is loaded before the product, in the accumulator's element order),
+// its factor and inverse, then step flag I.
+__device__ __forceinline__ void chol_next_diag(const double *K, double *B, int Q, int kb, double *Dinv,
+                                               unsigned *bad, unsigned *step, F64Stage &st, CholLds &cl) {
+  const int I = kb + 1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ib = (w >> 1) * 32, jb = (w & 1) * 32;
+  const double *C = K + (size_t)I * NB * Q + (size_t)I * NB;
+  double c[16];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        c[(i * 2 + j) * 4 + r] = C[(size_t)(ib + i * 16 + 4 * r + (lane >> 4)) * Q + jb + j * 16 + (lane & 15)];
+  F64Acc acc[2][2];
+  acc_zero(acc);
+  const double *LI = K + (size_t)I * NB * Q + (size_t)kb * NB;
+  block_product(acc, LI, Q, 1, LI, 1, Q, NB, st);
+  int e = 0;
+  acc_store(acc, [&](int r, int cc, double v) { cl.L[r][cc] = c[e++] - v; });
+  __syncthreads();
+  potrf_diag_core(cl, bad);
+  store_block_inverse(cl, Dinv, B, Q, I);
+  step_release(step, (unsigned)I);
+}
+
+template <typename T>
+__device__ __forceinline__ void chol_step_body(int b, double *K, double *B, int Q, int nbt, int kb, double *Dinv,
+                                               int q, T *Kinv, int ldk, unsigned *bad, unsigned *step) {
+  __shared__ union {
+    F64Stage st;
+    CholLds cl;
+  } lds;
+  const int rest = nbt - kb - 1;
+  const int n0 = rest > 0 ? 1 : 0;              // the next diagonal block
+  const int nsy = rest * (rest + 1) / 2 - n0;  // the other trailing tiles
+  const int ntr = rest * (kb + 1);              // inverse updates
+  if (b < n0) {
+    chol_next_diag(K, B, Q, kb, Dinv, bad, step, lds.st, lds.cl);
+    return;
+  }
+  b -= n0;
+  if (b < nsy) {
+    int I, J;
+    tri_index(b + 1, &I, &J);  // trailing tile (0, 0) is workgroup 0's
+    I += kb + 1;
+    J += kb + 1;
+    syrk_tile(K, Q, kb, I, J, lds.st);
+    if (J == kb + 1) {
+      step_wait(step, (unsigned)J, bad);
+      trsm_tile(K, Q, J, I, Dinv, lds.st);
+    }
+    return;
+  }
+  b -= nsy;
+  if (b < ntr) {
+    const int r = kb + 1 + b / (kb + 1), j = b % (kb + 1);
+    trtri_update_tile(K, B, Q, kb, r, j, lds.st);
+    if (r == kb + 1) {
+      step_wait(step, (unsigned)r, bad);
+      trtri_scale_tile(Dinv, B, Q, r, j, lds.st);
+    }
+    return;
+  }
+  b -= ntr;
+  int I, J;
+  tri_index(b, &I, &J);  // K^{-1} tile (I, J), J <= I <= kb: += X_kb,I^T X_kb,J
+  F64Acc acc[2][2];
+  acc_zero(acc);
+  const double *Xk = B + (size_t)kb * NB * Q;
+  block_product(acc, Xk + (size_t)I * NB, 1, Q, Xk + (size_t)J * NB, Q, 1, NB, lds.st);
+  double *S = K + (size_t)J * NB * Q + (size_t)I * NB;
+  const bool first = kb == I, last = kb == nbt - 1;
+  acc_store(acc, [&](int r, int c, double v) {
+    double *p = S + (size_t)r * Q + c;
+    const double val = first ? v : *p + v;
+    if (!last) {
+      *p = val;
+      return;
+    }
+    // a diagonal tile is written from its lower triangle only, so each output
+    // element has one writer
+    const int gi = I * NB + r, gj = J * NB + c;
+    if (gi < q && gj < q && (I != J || r >= c)) {
+      Kinv[(size_t)gi * ldk + gj] = (T)val;
+      Kinv[(size_t)gj * ldk + gi] = (T)val;
+    }
+  });
+}
+
 template <typename T>
 __device__ __forceinline__ void kinv_body(int b, const double *X, int Q, int nbt, int q, T *Kinv, int ldk) {
   __shared__ F64Stage st;
