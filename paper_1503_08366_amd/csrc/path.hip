@@ -108,8 +108,19 @@ __global__ __launch_bounds__(256) void path_reduce_kernel(PathArgs p, const floa
   double acc = 0.0;
   if (col < N) {
     for (int i = r0 + rg; i < r1; i += 4) {
+      // eight split partials loaded together, then added in split order (the
+      // same bits as one at a time; a loop with a run-time trip count would
+      // wait for each load before issuing the next)
       double v = 0.0;
-      for (int s = 0; s < splits; ++s) v += (double)part[((size_t)s * M + i) * N + col];
+      int s = 0;
+      for (; s + 8 <= splits; s += 8) {
+        float t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = part[((size_t)(s + u) * M + i) * N + col];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += (double)t[u];
+      }
+      for (; s < splits; ++s) v += (double)part[((size_t)s * M + i) * N + col];
       acc += epi(p, i, col, v);
     }
   }
@@ -284,10 +295,13 @@ __global__ __launch_bounds__(256) void path_unscale_kernel(PathArgs p, const dou
   if (threadIdx.x == 0) obj[r] = tot;
 }
 
+// Splits of K: about two workgroups per CU at most, chunks of at least 256
+// unless that leaves fewer than 128 workgroups (a small product such as the
+// solve), then chunks down to 64.
 int gemm_splits(int M, int N, int K) {
-  const int tiles = (int)(cdiv(M, kGramTB) * cdiv(N, kGramTB));
-  int s = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(512, tiles), cdiv(K, 256)));
-  return s;
+  const int64_t tiles = cdiv(M, kGramTB) * cdiv(N, kGramTB);
+  const int64_t want = std::max<int64_t>(cdiv(K, 256), std::min<int64_t>(cdiv(128, tiles), cdiv(K, 64)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(512, tiles), want));
 }
 
 template <bool A_T>
