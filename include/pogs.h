@@ -309,7 +309,10 @@ int pogs_prox_noalloc(const pogs_fn *fn, pogs_dtype dt, double rho, const void *
  *   direct projection: ms[1] prox step, ms[2] first pass over A, ms[3] solve
  *   with the cached inverse, ms[4] second pass over A; when m >= n the prox
  *   step runs inside the first pass and its finish (ms[1] = 0, ms[2] covers
- *   both launches);
+ *   both launches), and for float32 A with rows of at most 2048 entries
+ *   ms[4] is the one-pass kernel that finishes the iteration and forms the
+ *   next one's y-side half step and column sums in the same read of A (ms[2]
+ *   then covers the stop test and the finish of those column sums);
  *   CGLS (context set up for it, every projection running cg_max_iter
  *   steps): ms[1] prox step, ms[2] the two passes that start a projection,
  *   ms[3] one CG step (two passes), ms[4] = 0

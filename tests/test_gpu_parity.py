@@ -258,6 +258,11 @@ def test_big_setup_and_projection(big):
     np.testing.assert_allclose(y[rows], Ah[rows] @ x.astype(np.float64), rtol=1e-5, atol=1e-5)
     # full projection against the oracle
     xr, yr = O.Projector(Ah)(c.astype(np.float64), d.astype(np.float64))
+    # optimality of the returned pair: x - c + A^T (y - d) = 0 with y = A^ x
+    x64, y64 = x.astype(np.float64), y.astype(np.float64)
+    kkt = np.linalg.norm(x64 - c + Ah.T @ (y64 - d)) / np.linalg.norm(c)
+    print(f"20000x2000 projection: rel err x {np.linalg.norm(x - xr) / np.linalg.norm(xr):.3e} "
+          f"y {np.linalg.norm(y - yr) / np.linalg.norm(yr):.3e}; ||x - c + A^T(y - d)||/||c|| {kkt:.3e}")
     assert np.linalg.norm(x - xr) <= 1e-5 * np.linalg.norm(xr)
     assert np.linalg.norm(y - yr) <= 1e-5 * np.linalg.norm(yr)
 
