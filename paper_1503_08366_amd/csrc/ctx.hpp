@@ -9,39 +9,119 @@
 
 namespace pogs {
 
+// Blocks of contexts that were freed after their stream had drained, kept
+// for the next allocation of the same size on the same device: a context
+// created after another one of the same shape takes its blocks back without
+// a call into the stream-ordered pool (each hipFreeAsync costs the host
+// 7-45 us there, measured on MI355X).  At most kKeep bytes are kept per
+// process; past that the oldest go back to the pool.
+class SpareBlocks {
+ public:
+  static constexpr size_t kKeep = 4ull << 30;
+  void *take(int dev, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto it = blocks_.begin(); it != blocks_.end(); ++it)
+      if (it->dev == dev && it->bytes == bytes) {
+        void *p = it->ptr;
+        held_ -= bytes;
+        blocks_.erase(it);
+        return p;
+      }
+    return nullptr;
+  }
+  // p is idle (no queued work uses it); s orders the frees of evicted blocks
+  void keep(int dev, void *p, size_t bytes, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(mu_);
+    blocks_.push_back({dev, p, bytes});
+    held_ += bytes;
+    while (held_ > kKeep && !blocks_.empty()) {
+      (void)hipFreeAsync(blocks_.front().ptr, s);
+      held_ -= blocks_.front().bytes;
+      blocks_.erase(blocks_.begin());
+    }
+  }
+  // every kept block of device dev back to the pool (before retrying an
+  // allocation that failed)
+  bool flush(int dev, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(mu_);
+    bool any = false;
+    for (auto it = blocks_.begin(); it != blocks_.end();) {
+      if (it->dev == dev) {
+        (void)hipFreeAsync(it->ptr, s);
+        held_ -= it->bytes;
+        it = blocks_.erase(it);
+        any = true;
+      } else {
+        ++it;
+      }
+    }
+    return any;
+  }
+
+ private:
+  struct Block {
+    int dev;
+    void *ptr;
+    size_t bytes;
+  };
+  std::mutex mu_;
+  std::vector<Block> blocks_;
+  size_t held_ = 0;
+};
+inline SpareBlocks &spare_blocks() {
+  static SpareBlocks s;
+  return s;
+}
+
 // Device allocations owned by a context, freed together.  Allocation is
 // stream-ordered (hipMallocAsync / hipFreeAsync on the stream that uses the
 // memory) from the device's default pool, which keeps freed memory cached up
 // to a threshold: a context created after another one reuses its memory
-// without a device synchronisation or an operating-system call.
+// without a device synchronisation or an operating-system call.  Blocks
+// released while the stream is known to be idle go to spare_blocks().
 struct DevArena {
   hipStream_t stream = nullptr;
-  std::vector<void *> ptrs;
+  struct Held {
+    void *ptr;
+    size_t bytes;
+  };
+  std::vector<Held> ptrs;
+  int dev = -1;
   explicit DevArena(hipStream_t s = nullptr) : stream(s) { configure_pool(); }
   DevArena(const DevArena &) = delete;
   DevArena &operator=(const DevArena &) = delete;
   int alloc(void **p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
-    if (hipMallocAsync(p, bytes, stream) != hipSuccess) {
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return POGS_EDEVICE;
+    *p = spare_blocks().take(dev, bytes);
+    if (!*p && hipMallocAsync(p, bytes, stream) != hipSuccess) {
       *p = nullptr;
-      return POGS_ENOMEM;
+      (void)hipGetLastError();
+      if (!spare_blocks().flush(dev, stream) || hipMallocAsync(p, bytes, stream) != hipSuccess) {
+        *p = nullptr;
+        return POGS_ENOMEM;
+      }
     }
-    ptrs.push_back(*p);
+    ptrs.push_back({*p, bytes});
     return POGS_OK;
   }
   void release(void *p) {
-    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    auto it = std::find_if(ptrs.begin(), ptrs.end(), [p](const Held &h) { return h.ptr == p; });
     if (it != ptrs.end()) {
-      (void)hipFreeAsync(*it, stream);
+      (void)hipFreeAsync(it->ptr, stream);
       ptrs.erase(it);
     }
   }
   // Last allocated first: freeing a large block ahead of smaller ones made
   // the next free take 0.3-1.2 ms in the stream-ordered pool (measured on
-  // MI355X); in reverse order every free takes tens of microseconds.
-  void free_all() {
-    for (auto it = ptrs.rbegin(); it != ptrs.rend(); ++it) (void)hipFreeAsync(*it, stream);
+  // MI355X); in reverse order every free takes tens of microseconds.  idle:
+  // the caller has drained the stream, so the blocks may be kept for reuse.
+  void free_all(bool idle = false) {
+    for (auto it = ptrs.rbegin(); it != ptrs.rend(); ++it) {
+      if (idle) spare_blocks().keep(dev, it->ptr, it->bytes, stream);
+      else (void)hipFreeAsync(it->ptr, stream);
+    }
     ptrs.clear();
   }
   ~DevArena() { free_all(); }
@@ -196,6 +276,7 @@ struct pogs_ctx {
   bool fused = false;  // iterations run the one-pass tall launches (set per solve, see IterArgs::fused)
   double ms_setup = 0.0;
   hipGraphExec_t graph = nullptr;
+  unsigned *flags_host = nullptr;  // setup flags read back by pogs_init (pinned)
   int graph_chunk = 0;
   int graph_cg_cap = 0;  // CGLS step cap of the captured graph (0: direct projection)
   int graph_gap = 0;     // the captured graph runs the gap test
@@ -293,13 +374,18 @@ struct pogs_ctx {
   }
   ~pogs_ctx() {
     if (graph) (void)hipGraphExecDestroy(graph);
-    // device memory goes back to the pool on the context's stream, before
-    // that stream is destroyed
+    // device memory goes back to the pool in the order of the context's
+    // stream (a caller's stream needs no wait: later work on it is ordered
+    // after the frees, and the pool orders reuse on other streams); a stream
+    // of the context's own is drained before it is destroyed
     arena.free_all();
-    if (stream) (void)hipStreamSynchronize(stream);
+    if (own_stream && stream) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipStreamDestroy(stream);
+    }
     pinned_slab().put(ctrl_host);
     pinned_slab().put(obj_host);
-    if (own_stream && stream) (void)hipStreamDestroy(stream);
+    pinned_slab().put(flags_host);
   }
 };
 

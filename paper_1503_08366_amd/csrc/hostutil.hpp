@@ -66,6 +66,34 @@ inline int expand_fn(const pogs_fn *fn, int64_t len, HostFn *out) {
   return POGS_OK;
 }
 
+// Validate a pogs_fn of length len and write it expanded: h codes to h (len
+// bytes) and the parameters a, b, c, d, e as five float64 arrays of len
+// entries each, one after the other, at v.  Same checks as expand_fn.
+inline int stage_fn(const pogs_fn *fn, int64_t len, uint8_t *h, double *v) {
+  if (!fn || fn->len != len || !fn->h || (fn->stride != 0 && fn->stride != 1)) return POGS_EINVAL;
+  double *va = v, *vb = v + len, *vc = v + 2 * len, *vd = v + 3 * len, *ve = v + 4 * len;
+  for (int64_t i = 0; i < len; ++i) {
+    const int64_t k = fn->stride ? i : 0;
+    const uint8_t hk = fn->h[k];
+    const double a = fn->a ? fn->a[k] : 1.0;
+    const double b = fn->b ? fn->b[k] : 0.0;
+    const double c = fn->c ? fn->c[k] : 1.0;
+    const double d = fn->d ? fn->d[k] : 0.0;
+    const double e = fn->e ? fn->e[k] : 0.0;
+    if (hk >= kNumH) return POGS_EINVAL;
+    if (!finite(a) || !finite(b) || !finite(c) || !finite(d) || !finite(e)) return POGS_EINVAL;
+    if (c < 0.0 || e < 0.0) return POGS_EINVAL;   // convexity (Section 5: c, e >= 0)
+    if (c > 0.0 && a == 0.0) return POGS_EINVAL;  // h term would be constant
+    h[i] = hk;
+    va[i] = a;
+    vb[i] = b;
+    vc[i] = c;
+    vd[i] = d;
+    ve[i] = e;
+  }
+  return POGS_OK;
+}
+
 inline int check_params(const pogs_params &p) {
   if (!(p.eps_abs >= 0.0) || !(p.eps_rel >= 0.0) || p.max_iter <= 0 || !(p.rho0 > 0.0) || !(p.alpha > 0.0) ||
       !(p.alpha < 2.0) || !(p.delta >= 1.0) || !(p.tau > 0.0) || !(p.tau <= 1.0) || p.equil_iters < 0 ||

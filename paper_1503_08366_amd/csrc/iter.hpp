@@ -523,17 +523,19 @@ __device__ __forceinline__ void tall_finish_prox_body(const Blk &b, const IterAr
 // workgroup evaluates the rule with those values and takes, for the open
 // test, the outcome of the previous iteration's.  When the stop test after
 // iteration k picks another rho (or stops), the next first-pass kernel
-// recomputes those values (tall_pass1_prox_body) and these are discarded.  Iteration k + 1's half step goes to the other half-step set, so
-// iteration k's (the result, should the stop test end the solve here) stays.
-// Workgroups of kOnePassThreads; wave gw takes rows gw, gw + W, ... as in
-// gemv_n_rows_body; lane l keeps the column sums of columns 4 l + 256 u + c
-// (u < NC, c < 4) over its rows, in float64 for rows of at most 1024 entries
-// and in float32 for longer rows (64 float64 sums per lane would not fit the
-// registers of two waves per SIMD; one_pass_blocks keeps those waves at 64
-// rows or fewer); the waves' sums are added in LDS in float64 in wave order and
-// each workgroup writes one split partial.  Every lane
-// finishes each row (the row's sums are the same in all lanes after
-// wave_sum), so no value has to be broadcast.
+// recomputes those values (tall_pass1_prox_body) and these are discarded.
+// Iteration k + 1's half step goes to the other half-step set, so iteration
+// k's (the result, should the stop test end the solve here) stays.
+// Workgroups of kOnePassThreads; wave gw takes a contiguous run of rows (the
+// first m mod W waves one row more than the others), so the inputs and
+// outputs of a batch of its rows are contiguous.  Lane l keeps the column
+// sums of columns 4 l + 256 u + c (u < NC, c < 4) over its rows, in float64
+// for rows of at most 1024 entries and in float32 for longer rows (64 float64
+// sums per lane would not fit the registers of two waves per SIMD;
+// one_pass_blocks keeps those waves at 64 rows or fewer); the waves' sums are
+// added in LDS in float64 in wave order and each workgroup writes one split
+// partial.  Every lane finishes each row (the row's sums are the same in all
+// lanes after wave_sum), so no value has to be broadcast.
 // ---------------------------------------------------------------------------
 constexpr int kOnePassThreads = 512;
 template <int NC, bool NT>
@@ -549,6 +551,14 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
   __shared__ double rho_next;
   const CtrlState &gst = p.ctrl->st[p.par];
   const bool stopped = gst.done != 0;  // used once the first loads are out
+  // every control value the rho rule reads, loaded with the first loads (read
+  // after the barriers below they would cost another round trip to memory)
+  const Ctrl &q = *p.ctrl;
+  const double st_rho = gst.rho, st_rpri = gst.r_pri, st_epri = gst.eps_pri;
+  const int st_k = gst.k, st_l = gst.l, st_u = gst.u;
+  const double q_eabs = q.eps_abs, q_erel = q.eps_rel, q_tau = q.tau, q_delta = q.delta;
+  const float alpha = (float)q.alpha;
+  const int q_adaptive = q.adaptive;
   double part[4];
   part[0] = slot_partial(p.s_mu + (size_t)p.par * p.n_smu, p.n_smu);
   part[1] = part[2] = 0.0;  // the primal tolerance is not needed (see below)
@@ -579,7 +589,9 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
       }
     }
   }
-  const int nrows = gw < m ? (m - 1 - gw) / W + 1 : 0;
+  const int rq = m / W, rr = m % W;
+  const int nrows = rq + (gw < rr ? 1 : 0);
+  const int row0 = gw * rq + min(gw, rr);
   int cofs[NC];
 #pragma unroll
   for (int u = 0; u < NC; ++u) cofs[u] = min(4 * lane + 256 * u, ld - 4);
@@ -589,7 +601,29 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
     for (int u = 0; u < NC; ++u) dst[u] = mat_load<NT>(reinterpret_cast<const f4 *>(rp + cofs[u]));
   };
   f4 a0[NC], a1[NC];
-  if (nrows > 0) load(a0, gw);
+  if (nrows > 0) load(a0, row0);
+  // Rows go in batches of up to 64: lane t loads the inputs of the batch's row
+  // t up front and keeps its outputs until the batch ends, so the row loop
+  // itself issues no memory access other than the rows of A (a load or store
+  // between two rows makes the compiler wait for everything in flight).  Row
+  // t's inputs reach every lane by readlane.  The first batch's inputs are
+  // loaded here, with the first row.
+  float b_dy = 0.f, b_yh = 0.f, b_fa = 0.f, b_fb = 0.f, b_fc = 0.f, b_fd = 0.f, b_fe = 0.f;
+  int b_fh = 0;
+  auto load_inputs = [&](int i0) {
+    if (lane < min(kWave, nrows - i0)) {
+      const int mine = row0 + i0 + lane;
+      b_dy = p.dy[mine];
+      b_yh = p.yh[mine];
+      b_fh = p.f.h[mine];
+      b_fa = p.f.a[mine];
+      b_fb = p.f.b[mine];
+      b_fc = p.f.c[mine];
+      b_fd = p.f.d[mine];
+      b_fe = p.f.e[mine];
+    }
+  };
+  load_inputs(0);
   if (stopped) return;
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
@@ -602,22 +636,19 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
   // the sums are those of control_apply bit for bit (threads past kBlock add zeros)
   block_sum4(part, bs);
   if (threadIdx.x == 0) {
-    const Ctrl &q = *p.ctrl;
     const double r_dual = sqrt(part[3]);
-    const double eps_dual = q.eps_abs + q.eps_rel * sqrt(part[0]);
-    const double rho = gst.rho;
-    double next = rho;
-    if (q.adaptive) {
-      if (r_dual < eps_dual && q.tau * gst.k > gst.l) next = q.delta * rho;
-      else if (gst.r_pri < gst.eps_pri && q.tau * gst.k > gst.u) next = rho / q.delta;
+    const double eps_dual = q_eabs + q_erel * sqrt(part[0]);
+    double next = st_rho;
+    if (q_adaptive) {
+      if (r_dual < eps_dual && q_tau * st_k > st_l) next = q_delta * st_rho;
+      else if (st_rpri < st_epri && q_tau * st_k > st_u) next = st_rho / q_delta;
     }
     rho_next = next;
     if (b.x == 0) p.ctrl->spec_rho[1 - p.par] = next;
   }
   __syncthreads();
   const double rho_d = rho_next;
-  const float rho = (float)rho_d, resc = (float)(rho_d != gst.rho ? gst.rho / rho_d : 1.0);
-  const float alpha = (float)p.ctrl->alpha;
+  const float rho = (float)rho_d, resc = (float)(rho_d != st_rho ? st_rho / rho_d : 1.0);
 
   Acc acc[2][NC][4];
 #pragma unroll
@@ -627,13 +658,6 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
 #pragma unroll
       for (int k = 0; k < 4; ++k) acc[r][u][k] = Acc(0);
   double pri = 0.0, yh2 = 0.0;
-  // Rows go in batches of up to 64: lane t loads the inputs of the batch's row
-  // t up front and keeps its outputs until the batch ends, so the row loop
-  // itself issues no memory access other than the rows of A (a load or store
-  // between two rows makes the compiler wait for everything in flight).  Row
-  // t's inputs reach every lane by readlane.
-  float b_dy = 0.f, b_yh = 0.f, b_fa = 0.f, b_fb = 0.f, b_fc = 0.f, b_fd = 0.f, b_fe = 0.f;
-  int b_fh = 0;
   float o_y = 0.f, o_yt = 0.f, o_h = 0.f, o_nu = 0.f, o_d = 0.f;
   auto bcast = [](float v, int t) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t)); };
   auto row = [&](const f4 *a, int t) {
@@ -684,23 +708,14 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
   // row i of the wave is in a0 for even i and a1 for odd i (batches are 64 rows)
   for (int i0 = 0; i0 < nrows; i0 += kWave) {
     const int cnt = min(kWave, nrows - i0);
-    const int mine = gw + (i0 + lane) * W;
-    if (lane < cnt) {
-      b_dy = p.dy[mine];
-      b_yh = p.yh[mine];
-      b_fh = p.f.h[mine];
-      b_fa = p.f.a[mine];
-      b_fb = p.f.b[mine];
-      b_fc = p.f.c[mine];
-      b_fd = p.f.d[mine];
-      b_fe = p.f.e[mine];
-    }
+    const int mine = row0 + i0 + lane;
+    if (i0 > 0) load_inputs(i0);
     for (int t = 0; t < cnt; t += 2) {
       const int i = i0 + t;
-      if (i + 1 < nrows) load(a1, gw + (i + 1) * W);
+      if (i + 1 < nrows) load(a1, row0 + i + 1);
       row(a0, t);
       if (t + 1 >= cnt) break;
-      if (i + 2 < nrows) load(a0, gw + (i + 2) * W);
+      if (i + 2 < nrows) load(a0, row0 + i + 2);
       row(a1, t + 1);
     }
     if (lane < cnt) {
@@ -718,6 +733,10 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
     for (int u = 0; u < NC; ++u)
 #pragma unroll
       for (int k = 0; k < 4; ++k) red[w][r][4 * lane + 256 * u + k] = acc[r][u][k];
+  if (lane == 0) {  // pri and yh2 are the same in every lane of the wave
+    bs[w] = pri;
+    bs[NW + w] = yh2;
+  }
   __syncthreads();
   for (int j = threadIdx.x; j < ncolp; j += kOnePassThreads) {
 #pragma unroll
@@ -728,9 +747,13 @@ __device__ __forceinline__ void tall_one_pass_body(const Blk &b, const IterArgs<
       p.part[(size_t)(b.x * 2 + r) * ncolp + j] = v;
     }
   }
-  const double sp = block_sum(lane == 0 ? pri : 0.0, bs);
-  const double sy = block_sum(lane == 0 ? yh2 : 0.0, bs);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) {  // the waves in index order (the bits of block_sum)
+    double sp = 0.0, sy = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      sp += bs[k];
+      sy += bs[NW + k];
+    }
     p.s_pri[b.x] = sp;
     p.s_yh[(size_t)(1 - p.par) * p.n_syh + b.x] = sy;
   }

@@ -68,7 +68,9 @@ int pogs_params_default(pogs_params *p) {
 
 int pogs_free(pogs_ctx *ctx) {
   if (!ctx) return POGS_OK;
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  // drained, the context's blocks can be kept for the next context
+  const bool idle = !ctx->stream || hipStreamSynchronize(ctx->stream) == hipSuccess;
+  ctx->arena.free_all(idle);
   delete ctx;
   return POGS_OK;
 }
@@ -116,11 +118,8 @@ template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, 
   }
   // -- Gram and factorisation (direct projection) -------------------------
   if (c->proj == POGS_PROJ_CGLS) {
-    unsigned bad = 0;
-    POGS_HIP_TRY(hipMemcpyAsync(&bad, flags, sizeof(bad), hipMemcpyDeviceToHost, s));
-    POGS_HIP_TRY(hipStreamSynchronize(s));
-    POGS_HIP_TRY(hipGetLastError());
-    return bad ? POGS_EINVAL : POGS_OK;
+    POGS_HIP_TRY(hipMemcpyAsync(c->flags_host, flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    return POGS_OK;
   }
   const int Q = c->Q;
   double *K;
@@ -136,12 +135,9 @@ template <typename T> int init_impl(pogs_ctx *c, const void *A, pogs_dtype sdt, 
     if ((rc = run_gram<T>((const T *)c->A, m, n, c->ld, K, Q, (float *)ws, (double *)ws, gb, s))) return rc;
     if ((rc = run_factor_inverse<T>(K, c->q, Q, (T *)c->Kinv, c->ldk, (double *)ws, flags + 1, s))) return rc;
   }
-  unsigned hflags[2] = {0, 0};
-  POGS_HIP_TRY(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
-  POGS_HIP_TRY(hipStreamSynchronize(s));
-  POGS_HIP_TRY(hipGetLastError());
-  if (hflags[0]) return POGS_EINVAL;  // non-finite entries in A
-  if (hflags[1]) return POGS_EDEVICE;  // I + G not positive definite numerically
+  // read back once pogs_init has queued the rest of its work (the frees of
+  // the temporaries above go in stream order meanwhile)
+  POGS_HIP_TRY(hipMemcpyAsync(c->flags_host, flags, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s));
   return POGS_OK;
 }
 
@@ -328,10 +324,19 @@ extern "C" int pogs_init(pogs_ctx **out, int64_t m, int64_t n, const void *A, po
     c->own_stream = true;
   }
   c->arena.stream = c->stream;
-  int rc = dt == POGS_F32 ? init_impl<float>(c, A, dt, ord, lda, mem) : init_impl<double>(c, A, dt, ord, lda, mem);
+  // [0] non-finite A, [1] factorisation failures: read after the one wait below
+  c->flags_host = (unsigned *)pinned_slab().get();
+  int rc = c->flags_host ? POGS_OK : POGS_ENOMEM;
+  if (!rc) {
+    c->flags_host[0] = c->flags_host[1] = 0;
+    rc = dt == POGS_F32 ? init_impl<float>(c, A, dt, ord, lda, mem) : init_impl<double>(c, A, dt, ord, lda, mem);
+  }
   if (!rc) rc = dt == POGS_F32 ? alloc_iteration<float>(c) : alloc_iteration<double>(c);
   if (!rc) rc = dt == POGS_F32 ? tune_loads<float>(c) : tune_loads<double>(c);
-  if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = POGS_EDEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess && !rc) rc = POGS_EDEVICE;
+  if (!rc && hipGetLastError() != hipSuccess) rc = POGS_EDEVICE;
+  if (!rc && c->flags_host[0]) rc = POGS_EINVAL;   // non-finite entries in A
+  if (!rc && c->flags_host[1]) rc = POGS_EDEVICE;  // I + G not positive definite numerically
   if (rc) {
     delete c;
     return rc;
@@ -505,21 +510,18 @@ extern "C" int pogs_init_sparse(pogs_ctx **out, int64_t m, int64_t n, int64_t nn
 
 namespace {
 
-template <typename T> int upload_fns(pogs_ctx *c, const HostFn &f, const HostFn &g) {
+template <typename T> int upload_fns(pogs_ctx *c, const pogs_fn *f, const pogs_fn *g) {
   const int m = (int)c->m, n = (int)c->n;
   hipStream_t s = c->stream;
-  // one pinned staging copy of fh0 | gh0 | f0 | g0
+  // one pinned staging copy of fh0 | gh0 | f0 | g0, validated and expanded
+  // straight into the stage
   char *st = (char *)pinned_stage().acquire(c->fn_bytes);
   if (!st) return POGS_ENOMEM;
-  std::memcpy(st, f.h.data(), (size_t)m);
-  std::memcpy(st + c->off_gh0, g.h.data(), (size_t)n);
-  const HostFn *fs[2] = {&f, &g};
-  const size_t off[2] = {c->off_f0, c->off_g0};
-  const int len[2] = {m, n};
-  for (int k = 0; k < 2; ++k) {
-    const std::vector<double> *arr[5] = {&fs[k]->a, &fs[k]->b, &fs[k]->c, &fs[k]->d, &fs[k]->e};
-    for (int j = 0; j < 5; ++j)
-      std::memcpy(st + off[k] + (size_t)j * len[k] * 8, arr[j]->data(), (size_t)len[k] * 8);
+  int rc = stage_fn(f, m, (uint8_t *)st, (double *)(st + c->off_f0));
+  if (!rc) rc = stage_fn(g, n, (uint8_t *)st + c->off_gh0, (double *)(st + c->off_g0));
+  if (rc) {
+    pinned_stage().release(s);
+    return rc;
   }
   const hipError_t e = hipMemcpyAsync(c->fn_raw, st, c->fn_bytes, hipMemcpyHostToDevice, s);
   pinned_stage().release(s);
@@ -533,6 +535,21 @@ template <typename T> int upload_fns(pogs_ctx *c, const HostFn &f, const HostFn 
   return POGS_OK;
 }
 
+// An event of the calling thread on the current device, kept until the
+// process ends (no event is created or destroyed per solve).  It is recorded
+// and waited on within one call, so contexts on the same thread share it.
+hipEvent_t thread_event() {
+  static thread_local std::vector<std::pair<int, hipEvent_t>> evs;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  for (auto &e : evs)
+    if (e.first == dev) return e.second;
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+  evs.push_back({dev, ev});
+  return ev;
+}
+
 // Iterations per captured launch sequence: positive and even (the control
 // state alternates between two buffers by iteration parity).
 int even_chunk(int requested) {
@@ -544,10 +561,13 @@ int even_chunk(int requested) {
 // stop test of its last iteration so the state after the chunk is in st[0].
 // cg_cap > 0 selects the CGLS projection with that step cap; gap adds the
 // gap test after each prox step.
-template <typename T> void launch_chunk(pogs_ctx *c, int chunk, int cg_cap, int gap, hipStream_t s) {
+// Iterations i0 .. i1 - 1 of a chunk, and with preview the chunk's closing
+// stop test (i1 = chunk).
+template <typename T>
+void launch_iters(pogs_ctx *c, int i0, int i1, bool preview, int cg_cap, int gap, hipStream_t s) {
   const IterArgs<T> p0 = c->iter_args<T>(0), p1 = c->iter_args<T>(c->fused ? 1 : 0);
   IterArgs<T> p = p0;
-  for (int i = 0; i < chunk; ++i) {
+  for (int i = i0; i < i1; ++i) {
     p = (i & 1) ? p1 : p0;  // half-step set by iteration parity (one-pass iteration)
     p.par = i & 1;
     if (c->sparse) launch_iteration_cg_sparse<T>(p, cg_cap, s);
@@ -555,7 +575,14 @@ template <typename T> void launch_chunk(pogs_ctx *c, int chunk, int cg_cap, int 
     else if (gap) launch_iteration_gap<T>(p, c->splits, c->rps, c->ncolp, s);
     else launch_iteration<T>(p, c->splits, c->rps, c->ncolp, s);
   }
-  launch_control_preview<T>(p, 1, s);
+  if (preview) {
+    p = p1;
+    p.par = 1;
+    launch_control_preview<T>(p, 1, s);
+  }
+}
+template <typename T> void launch_chunk(pogs_ctx *c, int chunk, int cg_cap, int gap, hipStream_t s) {
+  launch_iters<T>(c, 0, chunk, true, cg_cap, gap, s);
 }
 
 template <typename T> int ensure_graph(pogs_ctx *c, int chunk, int cg_cap, int gap) {
@@ -581,17 +608,17 @@ template <typename T> int ensure_graph(pogs_ctx *c, int chunk, int cg_cap, int g
   return POGS_OK;
 }
 
-template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn &g, const pogs_params &p,
+template <typename T> int solve_impl(pogs_ctx *c, const pogs_fn *f, const pogs_fn *g, const pogs_params &p,
                                      const void *x0, const void *nu0, pogs_result *out) {
   const double t0 = now_ms();
   const int m = (int)c->m, n = (int)c->n;
   hipStream_t s = c->stream;
   const int cg_cap = p.projection == POGS_PROJ_CGLS ? p.cg_max_iter : 0;
   const int gap = p.stop_rule == POGS_STOP_GAP ? 1 : 0;
+  int rc;
+  if ((rc = upload_fns<T>(c, f, g))) return rc;  // validates f and g first
   // tall float32 direct solves with the residual rule read A once per iteration
   c->fused = c->fp_blocks > 0 && cg_cap == 0 && !gap;
-  int rc;
-  if ((rc = upload_fns<T>(c, f, g))) return rc;
   // zero state (Algorithm 1 starts from x = y = x~ = y~ = 0), or the warm start
   POGS_HIP_TRY(hipMemsetAsync(c->vec, 0, c->vec_elems() * sizeof(T), s));
   if (x0 || nu0) {
@@ -638,20 +665,37 @@ template <typename T> int solve_impl(pogs_ctx *c, const HostFn &f, const HostFn 
   // while the GPU runs it.
   const bool direct = c->sparse ? c->nnz >= ((int64_t)1 << 22) : (double)c->m * (double)c->n >= 16.0 * (1 << 20);
   bool eager = direct || !(c->graph && c->graph_chunk == chunk && c->graph_cg_cap == cg_cap && c->graph_gap == gap);
+  // Directly launched chunks: while the host waits for a chunk's control
+  // read-back, the first kLookahead iterations of the next chunk are already
+  // queued, so the GPU does not idle while the host wakes and launches the
+  // rest.  After the chunk that stops, they return at once (every iteration
+  // kernel checks the stop flag first).
+  constexpr int kLookahead = 1;
+  hipEvent_t chunk_done = nullptr;
+  if (direct && !(chunk_done = thread_event())) return POGS_EDEVICE;
+  if (direct) launch_chunk<T>(c, chunk, cg_cap, gap, s);
   for (;;) {
-    if (eager) launch_chunk<T>(c, chunk, cg_cap, gap, s);
-    else POGS_HIP_TRY(hipGraphLaunch(c->graph, s));
-    POGS_HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-    if (eager && !direct) {
-      if ((rc = ensure_graph<T>(c, chunk, cg_cap, gap))) return rc;
-      eager = false;
+    if (direct) {
+      POGS_HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+      POGS_HIP_TRY(hipEventRecord(chunk_done, s));
+      launch_iters<T>(c, 0, kLookahead, false, cg_cap, gap, s);
+      POGS_HIP_TRY(hipEventSynchronize(chunk_done));
+    } else {
+      if (eager) launch_chunk<T>(c, chunk, cg_cap, gap, s);
+      else POGS_HIP_TRY(hipGraphLaunch(c->graph, s));
+      POGS_HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+      if (eager) {
+        if ((rc = ensure_graph<T>(c, chunk, cg_cap, gap))) return rc;
+        eager = false;
+      }
+      POGS_HIP_TRY(hipStreamSynchronize(s));
     }
-    POGS_HIP_TRY(hipStreamSynchronize(s));
     const CtrlState &cs = c->ctrl_host->st[0];
     if (p.verbose)
       fprintf(stderr, "pogs: k=%d r_pri=%.3e eps_pri=%.3e r_dual=%.3e eps_dual=%.3e rho=%.4g\n", cs.k, cs.r_pri,
               cs.eps_pri, cs.r_dual, cs.eps_dual, cs.rho);
     if (cs.done) break;
+    if (direct) launch_iters<T>(c, kLookahead, chunk, true, cg_cap, gap, s);
   }
   // unscale into the caller's buffers (device) or staging (host); the
   // one-pass iteration left the last iteration's half step in set (k - 1) % 2
@@ -773,12 +817,8 @@ extern "C" int pogs_solve(pogs_ctx *ctx, const pogs_fn *f, const pogs_fn *g, con
   // CGLS state does not keep x~ and y~ for the gap test
   if (p.projection == POGS_PROJ_DIRECT && ctx->proj != POGS_PROJ_DIRECT) return POGS_EUNSUPPORTED;
   if (p.projection == POGS_PROJ_CGLS && p.stop_rule == POGS_STOP_GAP) return POGS_EUNSUPPORTED;
-  HostFn hf, hg;
-  int rc;
-  if ((rc = expand_fn(f, ctx->m, &hf))) return rc;
-  if ((rc = expand_fn(g, ctx->n, &hg))) return rc;
-  return ctx->dt == POGS_F32 ? solve_impl<float>(ctx, hf, hg, p, x0, nu0, out)
-                             : solve_impl<double>(ctx, hf, hg, p, x0, nu0, out);
+  return ctx->dt == POGS_F32 ? solve_impl<float>(ctx, f, g, p, x0, nu0, out)
+                             : solve_impl<double>(ctx, f, g, p, x0, nu0, out);
 }
 
 extern "C" int pogs_profile_iteration(pogs_ctx *ctx, int32_t reps, double *ms) {

@@ -181,10 +181,21 @@ class _FnHolder:
             self.h = np.full(length, H_CODES[fn.h], dtype=np.uint8)
         else:
             self.h = np.array([H_CODES[n] for n in fn.h], dtype=np.uint8)
-        self.arrs = [np.ascontiguousarray(fn.field(k), dtype=np.float64) for k in "abcde"]
+        # a parameter that is its default everywhere goes as NULL (the library
+        # fills the default), so no array is built for it
+        self.arrs = [None if _is_default(fn, k) else np.ascontiguousarray(fn.field(k), dtype=np.float64)
+                     for k in "abcde"]
         dp = C.POINTER(C.c_double)
         self.s = pogs_fn(length, 1, self.h.ctypes.data_as(C.POINTER(C.c_uint8)),
-                         *(a.ctypes.data_as(dp) for a in self.arrs))
+                         *(dp() if a is None else a.ctypes.data_as(dp) for a in self.arrs))
+
+
+_DEFAULTS = {"a": 1.0, "b": 0.0, "c": 1.0, "d": 0.0, "e": 0.0}
+
+
+def _is_default(fn, k: str) -> bool:
+    v = getattr(fn, k, None)
+    return v is not None and np.ndim(v) == 0 and float(v) == _DEFAULTS[k]
 
 
 def _is_torch(x) -> bool:
