@@ -7,6 +7,7 @@
 // solver calls the same functions in loops inside one workgroup per problem.
 #pragma once
 
+#include <type_traits>
 #include <utility>
 
 #include "common.hpp"
@@ -146,6 +147,165 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         out(wi * 64 + i * 16 + 4 * (lane >> 4) + r, wj * 64 + j * 16 + (lane & 15), acc[i][j][r]);
+}
+
+// Gram tile of a tall matrix from bf16 MFMAs at float32 accuracy.  Every
+// float32 entry x is split into three bf16 pieces, x = h + m + l (h = bf16(x),
+// m = bf16(x - h), l = bf16(x - h - m), each rounded to nearest; the
+// remainders are exact in float32, so the three pieces hold all 24 bits of x
+// outside the subnormal range), and a product x y is formed from the six
+// products of pieces whose weight is at least 2^-16 of h h:
+// l h + h l + m m + m h + h m + h h (the three dropped ones are below 2^-24 of
+// x y, the size of a float32 product's rounding).  Each bf16 product is exact
+// in the float32 accumulator of the MFMA, so the tile carries the errors of
+// float32 accumulation only, as gram_tile_f32 does, at six bf16 MFMAs per
+// product of float32 values (MI355X: 2.5 PFLOP/s bf16 against 157 TFLOP/s
+// float32).  sum_k A[k][i] A[k][j] over k in [k0, k1), tile (ti, tj);
+// k0 is a multiple of kG6KC; columns >= n and rows >= k1 read as zero.
+// Stages of kG6KC rows: the loads of the stage after next go out before a
+// stage's MFMAs, and the next stage's pieces are stored into the other LDS
+// buffer after them (one barrier per stage).  Each wave owns a 64 x 64
+// quarter as 2 x 2 MFMA 32x32x16 blocks.  Ends with a barrier.
+constexpr int kG6KC = 16;  // k depth of one stage (one MFMA depth)
+// [operand][piece][column][k]: 24 KB.  A column's 16 k are two 16-byte
+// halves, swapped in columns c with bit 3 of c set, so the 16 lanes of a
+// 16-byte access (16 consecutive columns, one half) hit 16 disjoint bank
+// groups.
+struct Gram6Stage {
+  __bf16 v[2][3][kGramTB][kG6KC];
+};
+__device__ inline int g6_half(int c, int h) { return (h ^ ((c >> 3) & 1)) * 8; }
+typedef float Gram6Acc __attribute__((ext_vector_type(16)));
+
+template <class Out>
+__device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int ti, int tj, int k0, int k1,
+                                 Gram6Stage (&st)[2], Out out) {
+  typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+  constexpr int TB = kGramTB;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  const bool diag = ti == tj;
+  // staging: thread t takes column t % 128 and rows 8 (t / 128) .. + 7 of a
+  // stage; a row is wave-uniform, so each load is a uniform row base plus
+  // the lane's column (columns and rows past the ends are clamped, then
+  // zeroed)
+  const int sc = t & (TB - 1), sh = __builtin_amdgcn_readfirstlane((t >> 7) * 8);
+  const int ca = ti * TB + sc, cb = tj * TB + sc;
+  const bool oka = ca < n, okb = !diag && cb < n;
+  const int cla = min(ca, n - 1), clb = diag ? cla : min(cb, n - 1);
+  const int sk = g6_half(sc, sh >> 3);  // where this thread's 8 k go in its column
+  // two register sets: the loads of stage s + 2 go out while stage s is
+  // multiplied and stage s + 1 waits in the other set for its store
+  float ra[2][8], rb[2][8];
+  // loads only (no wait): rows and columns past the ends are zeroed when the
+  // stage is stored
+  auto load = [&](auto set, int kk0) {
+    constexpr int S = decltype(set)::value;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float *rp = A + (size_t)min(kk0 + sh + e, k1 - 1) * ld;
+      ra[S][e] = rp[cla];
+      rb[S][e] = rp[clb];  // unused on a diagonal tile (clb = cla there)
+    }
+  };
+  // x = h + m + l by pairs: v_cvt_pk_bf16_f32 rounds two values to nearest
+  // and packs them; a packed pair widens back by a shift and a mask
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  auto widen = [](unsigned pk) { return f2{__uint_as_float(pk << 16), __uint_as_float(pk & 0xffff0000u)}; };
+  auto pack = [](f2 v) { return __builtin_bit_cast(unsigned, __builtin_convertvector(v, b2)); };
+  auto split_store = [&](const float (&r)[8], bool ok, int kk0, __bf16 (*dst)[kGramTB][kG6KC]) {
+    u4 ph, pm, pl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = kk0 + sh + 2 * q;
+      const f2 x = {ok && row < k1 ? r[2 * q] : 0.f, ok && row + 1 < k1 ? r[2 * q + 1] : 0.f};
+      const unsigned h = pack(x);
+      const f2 r1 = x - widen(h);
+      const unsigned mm = pack(r1);
+      const f2 r2 = r1 - widen(mm);
+      ph[q] = h;
+      pm[q] = mm;
+      pl[q] = pack(r2);
+    }
+    *reinterpret_cast<u4 *>(&dst[0][sc][sk]) = ph;
+    *reinterpret_cast<u4 *>(&dst[1][sc][sk]) = pm;
+    *reinterpret_cast<u4 *>(&dst[2][sc][sk]) = pl;
+  };
+  auto store = [&](Gram6Stage &sd, auto set, int kk0) {
+    constexpr int S = decltype(set)::value;
+    split_store(ra[S], oka, kk0, sd.v[0]);
+    if (!diag) split_store(rb[S], okb, kk0, sd.v[1]);
+  };
+  Gram6Acc acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  // loads are issued whether or not their stage exists (rows clamp to
+  // k1 - 1): a conditional load makes the compiler wait for every load in
+  // flight where the paths join
+  load(S0{}, k0);
+  load(S1{}, k0 + kG6KC);
+  store(st[0], S0{}, k0);
+  __syncthreads();
+  int cur = 0;
+  // MFMA 32x32x16 operands: lane l holds 8 consecutive k (8 (l / 32) ..) of
+  // row (A) or column (B) l % 32
+  const int fr = lane & 31;
+  // (bit 3 of a column index is that of fr: 64 and 32 leave it alone)
+  const int fka = g6_half(wi * 64 + fr, lane >> 5), fkb = g6_half(wj * 64 + fr, lane >> 5);
+  const int ob = diag ? 0 : 1;
+  // stage kk0 is in LDS buffer cur, stage kk0 + kG6KC in register set S
+  auto step = [&](int kk0, auto set) {
+    constexpr int S = decltype(set)::value;
+    load(std::integral_constant<int, 1 - S>{}, kk0 + 2 * kG6KC);
+    const Gram6Stage &sc_ = st[cur];
+    bf8 a[2][3], b[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int pc = 0; pc < 3; ++pc) {
+        a[i][pc] = *reinterpret_cast<const bf8 *>(&sc_.v[0][pc][wi * 64 + i * 32 + fr][fka]);
+        b[i][pc] = *reinterpret_cast<const bf8 *>(&sc_.v[ob][pc][wj * 64 + i * 32 + fr][fkb]);
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        Gram6Acc c = acc[i][j];
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], c, 0, 0, 0);  // l h
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], c, 0, 0, 0);  // h l
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], c, 0, 0, 0);  // m m
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], c, 0, 0, 0);  // m h
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], c, 0, 0, 0);  // h m
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], c, 0, 0, 0);  // h h
+        acc[i][j] = c;
+      }
+    // the other buffer was last read before the previous barrier
+    store(st[cur ^ 1], set, kk0 + kG6KC);
+    __syncthreads();
+    cur ^= 1;
+  };
+  // stages in pairs, with no condition in the loop (a stage past k1 is all
+  // zeros and adds nothing)
+  for (int kk0 = k0; kk0 < k1; kk0 += 2 * kG6KC) {
+    step(kk0, S1{});
+    step(kk0 + kG6KC, S0{});
+  }
+  // 32x32 result layout: lane l, element r -> row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        out(wi * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), wj * 64 + j * 32 + (lane & 31), acc[i][j][r]);
 }
 
 // General f32 MFMA tile product: tile (i0.., j0..) of sum_{k in [k0, k1)} opA(i, k) B(k, j)

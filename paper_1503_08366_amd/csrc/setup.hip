@@ -205,6 +205,18 @@ __global__ __launch_bounds__(256, 4) void gram_f32_kernel(const float *__restric
                       [&](int r, int c, float v) { out[r * kGramTB + c] = v; });
 }
 
+// Tall float32 matrices: the same tiles and splits from bf16 MFMAs at float32
+// accuracy (gram_tile_bf16x6).
+__global__ __launch_bounds__(256, 3) void gram_bf16x6_kernel(const float *__restrict__ A, int n, int ld, int m,
+                                                          int kchunk, int ntp, float *__restrict__ part) {
+  __shared__ Gram6Stage st[2];
+  int ti, tj;
+  tri_index(blockIdx.x, &ti, &tj);
+  const int k0 = blockIdx.y * kchunk;
+  const int k1 = min(m, k0 + kchunk);
+  float *out = part + ((size_t)blockIdx.y * ntp + blockIdx.x) * kGramTB * kGramTB;
+  gram_tile_bf16x6(A, n, ld, ti, tj, k0, k1, st, [&](int r, int c, float v) { out[r * kGramTB + c] = v; });
+}
 
 // float64 matrices: the same scheme with 64 x 64 tiles on f64 MFMA.
 template <bool TALL>
@@ -299,7 +311,7 @@ static void gram_geometry(int m, int n, int elem_size, int *TB, int *ntp, int *s
   *ntp = nt * (nt + 1) / 2;
   // as many (tile, split) workgroups as are resident at once, one round,
   // each split at least 256 deep
-  const void *kern = elem_size == 4 ? (tall ? (const void *)gram_f32_kernel<true> : (const void *)gram_f32_kernel<false>)
+  const void *kern = elem_size == 4 ? (tall ? (const void *)gram_bf16x6_kernel : (const void *)gram_f32_kernel<false>)
                                     : (tall ? (const void *)gram_f64_kernel<true> : (const void *)gram_f64_kernel<false>);
   static std::atomic<int> resident[2][2];  // per (element size, orientation); 0 = not yet queried
   int res = resident[elem_size == 4][tall].load(std::memory_order_relaxed);
@@ -329,7 +341,7 @@ int run_gram(const T *A, int m, int n, int ld, double *K, int Q, float *ws32, do
   dim3 grid(ntp, splits);
   if constexpr (sizeof(T) == 4) {
     if (tall)
-      hipLaunchKernelGGL(gram_f32_kernel<true>, grid, dim3(256), 0, s, (const float *)A, m, n, ld, kchunk, ntp, ws32);
+      hipLaunchKernelGGL(gram_bf16x6_kernel, grid, dim3(256), 0, s, (const float *)A, n, ld, m, kchunk, ntp, ws32);
     else
       hipLaunchKernelGGL(gram_f32_kernel<false>, grid, dim3(256), 0, s, (const float *)A, m, n, ld, kchunk, ntp, ws32);
     hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3(ntp * (TB / 64) * (TB / 64)), dim3(256), 0, s, ws32, splits, ntp, TB, q,
