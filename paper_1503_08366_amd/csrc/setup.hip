@@ -26,9 +26,30 @@ __global__ __launch_bounds__(256) void layout_kernel(const S *src, int colmajor,
   layout_body<T, S>(hw_block(), src, colmajor, lda, m, n, dst, ld, bad);
 }
 
+__global__ __launch_bounds__(256) void layout_rows_f32_kernel(const float *src, int64_t lda, int m, int n,
+                                                              float *dst, int ld, unsigned *bad) {
+  layout_rows_f32_body(hw_block(), src, lda, m, n, dst, ld, bad);
+}
+
+__global__ __launch_bounds__(256) void scale_rows_f32_kernel(float *A, int m, int n, int ld, const double *D,
+                                                             const double *E) {
+  scale_rows_f32_body(hw_block(), A, m, n, ld, D, E);
+}
+
+// Rows per launch column of the 16-byte row kernels: enough workgroups to
+// fill the GPU several times over, each thread with a few rows of work.
+static int row_blocks(int m) { return std::max(1, std::min(m, 2048)); }
+
 template <typename T>
 void launch_layout(const void *src, pogs_dtype sdt, pogs_order ord, int64_t lda, int m, int n, T *dst,
                    int ld, unsigned *bad, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (sdt == POGS_F32 && ord == POGS_ROW_MAJOR && lda % 4 == 0 && ((uintptr_t)src & 15) == 0) {
+      hipLaunchKernelGGL(layout_rows_f32_kernel, dim3(cdiv(ld, 1024), row_blocks(m)), dim3(256), 0, s,
+                         (const float *)src, lda, m, n, (float *)dst, ld, bad);
+      return;
+    }
+  }
   dim3 grid(cdiv(ld, 32), cdiv(m, 32));
   const int cm = ord == POGS_COL_MAJOR;
   if (sdt == POGS_F32)
@@ -182,8 +203,12 @@ int run_equilibrate(T *A, int m, int n, int ld, int iters, double eps_cmp, doubl
   const int q = std::min(m, n);
   hipLaunchKernelGGL(equil_finish_kernel, dim3(cdiv(m + n, 256)), dim3(256), 0, s, a.d, a.e, a.slots,
                      (int)cdiv(n, kFinishCols), m, n, q, D, E);
-  hipLaunchKernelGGL((scale_matrix_kernel<T>), dim3(cdiv(n, 256), std::min(m, 32768)), dim3(256), 0, s, A, m, n,
-                     ld, D, E);
+  if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL(scale_rows_f32_kernel, dim3(cdiv(n, 1024), row_blocks(m)), dim3(256), 0, s, (float *)A, m, n,
+                       ld, D, E);
+  else
+    hipLaunchKernelGGL((scale_matrix_kernel<T>), dim3(cdiv(n, 256), std::min(m, 32768)), dim3(256), 0, s, A, m, n,
+                       ld, D, E);
   return POGS_OK;
 }
 

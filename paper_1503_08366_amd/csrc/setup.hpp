@@ -173,6 +173,80 @@ __device__ __forceinline__ void equil_finish_body(const Blk &b, const double *d,
 }
 
 // A <- D A E in place (padding columns stay zero).
+// float32 A = D A E in 16-byte pieces: thread (x, t) takes columns 4 (256 x
+// + t) .. + 3 and rows y, y + ny, ..., four rows in flight.  The same
+// arithmetic per entry as scale_matrix_body (D_r A_rc, then times E_c, in
+// float64); padding columns (n .. ld) stay zero.
+__device__ __forceinline__ void scale_rows_f32_body(const Blk &b, float *A, int m, int n, int ld, const double *D,
+                                                    const double *E) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const int c4 = (b.x * 256 + (int)threadIdx.x) * 4;
+  if (c4 >= n) return;  // c4 + 3 < ld: ld is a multiple of 64
+  double e[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) e[k] = c4 + k < n ? E[c4 + k] : 0.0;
+  for (int r0 = b.y; r0 < m; r0 += 4 * b.ny) {
+    f4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * b.ny;
+      if (r < m) v[u] = *reinterpret_cast<const f4 *>(A + (size_t)r * ld + c4);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * b.ny;
+      if (r < m) {
+        const double d = D[r];
+        f4 o;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = (float)(d * (double)v[u][k] * e[k]);
+        *reinterpret_cast<f4 *>(A + (size_t)r * ld + c4) = o;
+      }
+    }
+  }
+}
+
+// Row-major float32 source copied into the row-major layout in 16-byte
+// pieces (src 16-byte aligned, lda % 4 == 0): thread (x, t) takes columns
+// 4 (256 x + t) .. + 3 of rows y, y + ny, ...; columns n .. ld are zero;
+// non-finite entries are counted in *bad.
+__device__ __forceinline__ void layout_rows_f32_body(const Blk &b, const float *src, int64_t lda, int m, int n,
+                                                     float *dst, int ld, unsigned *bad) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const int c4 = (b.x * 256 + (int)threadIdx.x) * 4;
+  if (c4 >= ld) return;
+  unsigned nbad = 0;
+  for (int r0 = b.y; r0 < m; r0 += 4 * b.ny) {
+    f4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * b.ny;
+      v[u] = f4{0.f, 0.f, 0.f, 0.f};
+      if (r < m) {
+        const float *sp = src + (size_t)r * lda + c4;
+        if (c4 + 3 < n) {
+          v[u] = *reinterpret_cast<const f4 *>(sp);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (c4 + k < n) v[u][k] = sp[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * b.ny;
+      if (r < m) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (!isfinite(v[u][k])) ++nbad;
+        *reinterpret_cast<f4 *>(dst + (size_t)r * ld + c4) = v[u];
+      }
+    }
+  }
+  if (nbad) atomicAdd(bad, nbad);
+}
+
 template <typename T>
 __device__ __forceinline__ void scale_matrix_body(const Blk &b, T *A, int m, int n, int ld, const double *D,
                                                   const double *E) {
