@@ -158,9 +158,13 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
 // l h + h l + m m + m h + h m + h h (the three dropped ones are below 2^-24 of
 // x y, the size of a float32 product's rounding).  Each bf16 product is exact
 // in the float32 accumulator of the MFMA, so the tile carries the errors of
-// float32 accumulation only, as gram_tile_f32 does, at six bf16 MFMAs per
-// product of float32 values (MI355X: 2.5 PFLOP/s bf16 against 157 TFLOP/s
-// float32).  sum_k A[k][i] A[k][j] over k in [k0, k1), tile (ti, tj);
+// float32 accumulation only, at six bf16 MFMAs per product of float32 values
+// (MI355X: 2.5 PFLOP/s bf16 against 157 TFLOP/s float32).  The h h products
+// and the five smaller ones go to separate accumulators, added at the end:
+// with all six in one, every 16 rows put six roundings of the large partial
+// sum into it, and over a 4000-row split that cost the 20000 x 2000
+// projection a factor of six in accuracy (1.1e-6 against the FP64 projection,
+// 1.7e-7 with two accumulators, 2.3e-7 with the float32-MFMA Gram).  sum_k A[k][i] A[k][j] over k in [k0, k1), tile (ti, tj);
 // k0 is a multiple of kG6KC; columns >= n and rows >= k1 read as zero.
 // Stages of kG6KC rows: the loads of the stage after next go out before a
 // stage's MFMAs, and the next stage's pieces are stored into the other LDS
@@ -238,13 +242,15 @@ __device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int
     split_store(ra[S], oka, kk0, sd.v[0]);
     if (!diag) split_store(rb[S], okb, kk0, sd.v[1]);
   };
-  Gram6Acc acc[2][2];
+  // the h h products accumulate in acc, the five smaller ones in acs: the
+  // large accumulator then takes one rounding per 16 rows instead of six
+  Gram6Acc acc[2][2], acs[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = acs[i][j][r] = 0.f;
   using S0 = std::integral_constant<int, 0>;
   using S1 = std::integral_constant<int, 1>;
   // loads are issued whether or not their stage exists (rows clamp to
@@ -278,14 +284,14 @@ __device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        Gram6Acc c = acc[i][j];
+        Gram6Acc c = acs[i][j];
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], c, 0, 0, 0);  // l h
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], c, 0, 0, 0);  // h l
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], c, 0, 0, 0);  // m m
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], c, 0, 0, 0);  // m h
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], c, 0, 0, 0);  // h m
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], c, 0, 0, 0);  // h h
-        acc[i][j] = c;
+        acs[i][j] = c;
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);  // h h
       }
     // the other buffer was last read before the previous barrier
     store(st[cur ^ 1], set, kk0 + kG6KC);
@@ -305,7 +311,8 @@ __device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        out(wi * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), wj * 64 + j * 32 + (lane & 31), acc[i][j][r]);
+        out(wi * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), wj * 64 + j * 32 + (lane & 31),
+            acc[i][j][r] + acs[i][j][r]);
 }
 
 // General f32 MFMA tile product: tile (i0.., j0..) of sum_{k in [k0, k1)} opA(i, k) B(k, j)

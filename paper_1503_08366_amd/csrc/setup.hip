@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256, 4) void gram_f32_kernel(const float *__restric
 
 // Tall float32 matrices: the same tiles and splits from bf16 MFMAs at float32
 // accuracy (gram_tile_bf16x6).
-__global__ __launch_bounds__(256, 3) void gram_bf16x6_kernel(const float *__restrict__ A, int n, int ld, int m,
+__global__ __launch_bounds__(256, 2) void gram_bf16x6_kernel(const float *__restrict__ A, int n, int ld, int m,
                                                           int kchunk, int ntp, float *__restrict__ part) {
   __shared__ Gram6Stage st[2];
   int ti, tj;
