@@ -168,8 +168,8 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
 // k0 is a multiple of kG6KC; columns >= n and rows >= k1 read as zero.
 // Stages of kG6KC rows: the loads of the stage after next go out before a
 // stage's MFMAs, and the next stage's pieces are stored into the other LDS
-// buffer after them (one barrier per stage).  Each wave owns a 64 x 64
-// quarter as 2 x 2 MFMA 32x32x16 blocks.  Ends with a barrier.
+// buffer after them (one barrier per stage).  512 threads (8 waves), each
+// wave a 32 x 64 part of the tile.  Ends with a barrier.
 constexpr int kG6KC = 16;  // k depth of one stage (one MFMA depth)
 // [operand][piece][column][k]: 24 KB.  A column's 16 k are two 16-byte
 // halves, swapped in columns c with bit 3 of c set, so the 16 lanes of a
@@ -186,27 +186,30 @@ __device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int
                                  Gram6Stage (&st)[2], Out out) {
   typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
   constexpr int TB = kGramTB;
+  // 8 waves: wave w owns rows 32 (w / 2) .. + 31 and columns 64 (w % 2) .. + 63
+  // of the tile, as 1 x 2 MFMA 32x32x16 blocks
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = w >> 1, wj = w & 1;
   const bool diag = ti == tj;
-  // staging: thread t takes column t % 128 and rows 8 (t / 128) .. + 7 of a
+  // staging: thread t takes column t % 128 and rows 4 (t / 128) .. + 3 of a
   // stage; a row is wave-uniform, so each load is a uniform row base plus
   // the lane's column (columns and rows past the ends are clamped, then
   // zeroed)
-  const int sc = t & (TB - 1), sh = __builtin_amdgcn_readfirstlane((t >> 7) * 8);
+  constexpr int E = 4;
+  const int sc = t & (TB - 1), sh = __builtin_amdgcn_readfirstlane((t >> 7) * E);
   const int ca = ti * TB + sc, cb = tj * TB + sc;
   const bool oka = ca < n, okb = !diag && cb < n;
   const int cla = min(ca, n - 1), clb = diag ? cla : min(cb, n - 1);
-  const int sk = g6_half(sc, sh >> 3);  // where this thread's 8 k go in its column
+  const int sk = g6_half(sc, sh >> 3) + (sh & 7);  // where this thread's E k go in its column
   // two register sets: the loads of stage s + 2 go out while stage s is
   // multiplied and stage s + 1 waits in the other set for its store
-  float ra[2][8], rb[2][8];
+  float ra[2][E], rb[2][E];
   // loads only (no wait): rows and columns past the ends are zeroed when the
   // stage is stored
   auto load = [&](auto set, int kk0) {
     constexpr int S = decltype(set)::value;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
       const float *rp = A + (size_t)min(kk0 + sh + e, k1 - 1) * ld;
       ra[S][e] = rp[cla];
       rb[S][e] = rp[clb];  // unused on a diagonal tile (clb = cla there)
@@ -216,13 +219,13 @@ __device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int
   // and packs them; a packed pair widens back by a shift and a mask
   typedef float f2 __attribute__((ext_vector_type(2)));
   typedef __bf16 b2 __attribute__((ext_vector_type(2)));
-  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
   auto widen = [](unsigned pk) { return f2{__uint_as_float(pk << 16), __uint_as_float(pk & 0xffff0000u)}; };
   auto pack = [](f2 v) { return __builtin_bit_cast(unsigned, __builtin_convertvector(v, b2)); };
-  auto split_store = [&](const float (&r)[8], bool ok, int kk0, __bf16 (*dst)[kGramTB][kG6KC]) {
-    u4 ph, pm, pl;
+  auto split_store = [&](const float (&r)[E], bool ok, int kk0, __bf16 (*dst)[kGramTB][kG6KC]) {
+    u2 ph, pm, pl;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < E / 2; ++q) {
       const int row = kk0 + sh + 2 * q;
       const f2 x = {ok && row < k1 ? r[2 * q] : 0.f, ok && row + 1 < k1 ? r[2 * q + 1] : 0.f};
       const unsigned h = pack(x);
@@ -233,9 +236,9 @@ __device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int
       pm[q] = mm;
       pl[q] = pack(r2);
     }
-    *reinterpret_cast<u4 *>(&dst[0][sc][sk]) = ph;
-    *reinterpret_cast<u4 *>(&dst[1][sc][sk]) = pm;
-    *reinterpret_cast<u4 *>(&dst[2][sc][sk]) = pl;
+    *reinterpret_cast<u2 *>(&dst[0][sc][sk]) = ph;
+    *reinterpret_cast<u2 *>(&dst[1][sc][sk]) = pm;
+    *reinterpret_cast<u2 *>(&dst[2][sc][sk]) = pl;
   };
   auto store = [&](Gram6Stage &sd, auto set, int kk0) {
     constexpr int S = decltype(set)::value;
@@ -244,13 +247,11 @@ __device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int
   };
   // the h h products accumulate in acc, the five smaller ones in acs: the
   // large accumulator then takes one rounding per 16 rows instead of six
-  Gram6Acc acc[2][2], acs[2][2];
+  Gram6Acc acc[2], acs[2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = acs[i][j][r] = 0.f;
+    for (int r = 0; r < 16; ++r) acc[j][r] = acs[j][r] = 0.f;
   using S0 = std::integral_constant<int, 0>;
   using S1 = std::integral_constant<int, 1>;
   // loads are issued whether or not their stage exists (rows clamp to
@@ -264,35 +265,32 @@ __device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int
   // MFMA 32x32x16 operands: lane l holds 8 consecutive k (8 (l / 32) ..) of
   // row (A) or column (B) l % 32
   const int fr = lane & 31;
-  // (bit 3 of a column index is that of fr: 64 and 32 leave it alone)
-  const int fka = g6_half(wi * 64 + fr, lane >> 5), fkb = g6_half(wj * 64 + fr, lane >> 5);
+  // (bit 3 of a column index is that of fr: multiples of 32 leave it alone)
+  const int fka = g6_half(wi * 32 + fr, lane >> 5), fkb = g6_half(wj * 64 + fr, lane >> 5);
   const int ob = diag ? 0 : 1;
   // stage kk0 is in LDS buffer cur, stage kk0 + kG6KC in register set S
   auto step = [&](int kk0, auto set) {
     constexpr int S = decltype(set)::value;
     load(std::integral_constant<int, 1 - S>{}, kk0 + 2 * kG6KC);
     const Gram6Stage &sc_ = st[cur];
-    bf8 a[2][3], b[2][3];
+    bf8 a[3], b[2][3];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int pc = 0; pc < 3; ++pc) {
+      a[pc] = *reinterpret_cast<const bf8 *>(&sc_.v[0][pc][wi * 32 + fr][fka]);
 #pragma unroll
-      for (int pc = 0; pc < 3; ++pc) {
-        a[i][pc] = *reinterpret_cast<const bf8 *>(&sc_.v[0][pc][wi * 64 + i * 32 + fr][fka]);
-        b[i][pc] = *reinterpret_cast<const bf8 *>(&sc_.v[ob][pc][wj * 64 + i * 32 + fr][fkb]);
-      }
+      for (int j = 0; j < 2; ++j) b[j][pc] = *reinterpret_cast<const bf8 *>(&sc_.v[ob][pc][wj * 64 + j * 32 + fr][fkb]);
+    }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        Gram6Acc c = acs[i][j];
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], c, 0, 0, 0);  // l h
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], c, 0, 0, 0);  // h l
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], c, 0, 0, 0);  // m m
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], c, 0, 0, 0);  // m h
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], c, 0, 0, 0);  // h m
-        acs[i][j] = c;
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);  // h h
-      }
+    for (int j = 0; j < 2; ++j) {
+      Gram6Acc c = acs[j];
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[j][0], c, 0, 0, 0);  // l h
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][2], c, 0, 0, 0);  // h l
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[j][1], c, 0, 0, 0);  // m m
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[j][0], c, 0, 0, 0);  // m h
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][1], c, 0, 0, 0);  // h m
+      acs[j] = c;
+      acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][0], acc[j], 0, 0, 0);  // h h
+    }
     // the other buffer was last read before the previous barrier
     store(st[cur ^ 1], set, kk0 + kG6KC);
     __syncthreads();
@@ -306,13 +304,10 @@ __device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int
   }
   // 32x32 result layout: lane l, element r -> row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        out(wi * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), wj * 64 + j * 32 + (lane & 31),
-            acc[i][j][r] + acs[i][j][r]);
+    for (int r = 0; r < 16; ++r)
+      out(wi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), wj * 64 + j * 32 + (lane & 31), acc[j][r] + acs[j][r]);
 }
 
 // General f32 MFMA tile product: tile (i0.., j0..) of sum_{k in [k0, k1)} opA(i, k) B(k, j)

@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256, 4) void gram_f32_kernel(const float *__restric
 
 // Tall float32 matrices: the same tiles and splits from bf16 MFMAs at float32
 // accuracy (gram_tile_bf16x6).
-__global__ __launch_bounds__(256, 2) void gram_bf16x6_kernel(const float *__restrict__ A, int n, int ld, int m,
+__global__ __launch_bounds__(512, 2) void gram_bf16x6_kernel(const float *__restrict__ A, int n, int ld, int m,
                                                           int kchunk, int ntp, float *__restrict__ part) {
   __shared__ Gram6Stage st[2];
   int ti, tj;
@@ -341,7 +341,7 @@ static void gram_geometry(int m, int n, int elem_size, int *TB, int *ntp, int *s
   static std::atomic<int> resident[2][2];  // per (element size, orientation); 0 = not yet queried
   int res = resident[elem_size == 4][tall].load(std::memory_order_relaxed);
   if (!res) {
-    res = resident_workgroups(kern, 256);
+    res = resident_workgroups(kern, elem_size == 4 && tall ? 512 : 256);
     resident[elem_size == 4][tall].store(res, std::memory_order_relaxed);
   }
   int s = (int)std::max<int64_t>(1, std::min<int64_t>(res / *ntp, cdiv(kdim, 256)));
@@ -366,7 +366,7 @@ int run_gram(const T *A, int m, int n, int ld, double *K, int Q, float *ws32, do
   dim3 grid(ntp, splits);
   if constexpr (sizeof(T) == 4) {
     if (tall)
-      hipLaunchKernelGGL(gram_bf16x6_kernel, grid, dim3(256), 0, s, (const float *)A, n, ld, m, kchunk, ntp, ws32);
+      hipLaunchKernelGGL(gram_bf16x6_kernel, grid, dim3(512), 0, s, (const float *)A, n, ld, m, kchunk, ntp, ws32);
     else
       hipLaunchKernelGGL(gram_f32_kernel<false>, grid, dim3(256), 0, s, (const float *)A, m, n, ld, kchunk, ntp, ws32);
     hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3(ntp * (TB / 64) * (TB / 64)), dim3(256), 0, s, ws32, splits, ntp, TB, q,
