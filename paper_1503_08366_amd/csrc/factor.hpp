@@ -164,7 +164,8 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
 // with all six in one, every 16 rows put six roundings of the large partial
 // sum into it, and over a 4000-row split that cost the 20000 x 2000
 // projection a factor of six in accuracy (1.1e-6 against the FP64 projection,
-// 1.7e-7 with two accumulators, 2.3e-7 with the float32-MFMA Gram).  sum_k A[k][i] A[k][j] over k in [k0, k1), tile (ti, tj);
+// 1.7e-7 with two accumulators, 2.3e-7 with the float32-MFMA Gram; 9.7e-8 with
+// two accumulators and the 2900-row splits of two dispatch rounds).  sum_k A[k][i] A[k][j] over k in [k0, k1), tile (ti, tj);
 // k0 is a multiple of kG6KC; columns >= n and rows >= k1 read as zero.
 // Stages of kG6KC rows: the loads of the stage after next go out before a
 // stage's MFMAs, and the next stage's pieces are stored into the other LDS

@@ -312,13 +312,40 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const P *part, int spl
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const P *src = part + (size_t)tp * TB * TB + (size_t)si * 64 * TB + sj * 64;
   const size_t sstride = (size_t)ntp * TB * TB;
-  for (int r = ty; r < 64; r += 4) {
-    const int i = i0 + r, j = j0 + tx;
-    double v = (i == j) ? 1.0 : 0.0;
-    if (i < q && j < q)
-      for (int s = 0; s < splits; ++s) v += (double)src[s * sstride + (size_t)r * TB + tx];
-    tile[r][tx] = v;
+  // the thread's 16 rows are summed together, four splits at a time (64
+  // loads in flight), each element in split order
+  double v[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int i = i0 + ty + 4 * u, j = j0 + tx;
+    v[u] = (i == j) ? 1.0 : 0.0;
   }
+  const bool jok = j0 + tx < q;
+  int s = 0;
+  for (; s + 4 <= splits; s += 4) {
+    P x[4][16];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const P *ps = src + (s + g) * sstride + tx;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[g][u] = ps[(size_t)(ty + 4 * u) * TB];
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (i0 + ty + 4 * u < q && jok) v[u] += (double)x[g][u];
+  }
+  for (; s < splits; ++s) {
+    const P *ps = src + s * sstride + tx;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = ty + 4 * u;
+      if (i0 + r < q && jok) v[u] += (double)ps[(size_t)r * TB];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) tile[ty + 4 * u][tx] = v[u];
   __syncthreads();
   for (int r = ty; r < 64; r += 4) {
     const int i = i0 + r, j = j0 + tx;
@@ -334,8 +361,8 @@ static void gram_geometry(int m, int n, int elem_size, int *TB, int *ntp, int *s
   *TB = elem_size == 4 ? 128 : 64;
   const int nt = (int)cdiv(qdim, *TB);
   *ntp = nt * (nt + 1) / 2;
-  // as many (tile, split) workgroups as are resident at once, one round,
-  // each split at least 256 deep
+  // as many (tile, split) workgroups as are resident at once, one round
+  // (two for the tall float32 Gram, below), each split at least 256 deep
   const void *kern = elem_size == 4 ? (tall ? (const void *)gram_bf16x6_kernel : (const void *)gram_f32_kernel<false>)
                                     : (tall ? (const void *)gram_f64_kernel<true> : (const void *)gram_f64_kernel<false>);
   static std::atomic<int> resident[2][2];  // per (element size, orientation); 0 = not yet queried
@@ -345,6 +372,11 @@ static void gram_geometry(int m, int n, int elem_size, int *TB, int *ntp, int *s
     resident[elem_size == 4][tall].store(res, std::memory_order_relaxed);
   }
   int s = (int)std::max<int64_t>(1, std::min<int64_t>(res / *ntp, cdiv(kdim, 256)));
+  // the tall float32 Gram takes two rounds of resident workgroups: with one,
+  // the tile count leaves up to a fifth of them idle (136 tiles at
+  // 20000 x 2000: 3 splits fill 408 of 512), with two the dispatcher refills
+  // them, and the shorter splits also accumulate more accurately
+  if (elem_size == 4 && tall) s = (int)std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)res / *ntp, cdiv(kdim, 256)));
   *kchunk = (int)round_up(cdiv(kdim, s), kGramKC);
   *splits = (int)cdiv(kdim, *kchunk);
 }

@@ -132,7 +132,7 @@ def test_dose_setup_and_projection_full_size(dose):
     graph = np.linalg.norm(y64 - Ah @ x64) / np.linalg.norm(y64)
     print(f"dose projection: rel err x {ex:.3e} y {ey:.3e}; ||x - c + A^T(y - d)||/||c|| {kkt:.3e}; "
           f"||y - A x||/||y|| {graph:.3e}")
-    # float32 accuracy of the Gram over long row splits (2.5e-7 measured)
+    # float32 accuracy of the Gram over long row splits (1.3e-7 measured)
     assert ex <= 5e-7 and ey <= 5e-7, (ex, ey)
 
 

@@ -287,8 +287,9 @@ def test_big_setup_and_projection(big):
     kkt = np.linalg.norm(x64 - c + Ah.T @ (y64 - d)) / np.linalg.norm(c)
     print(f"20000x2000 projection: rel err x {np.linalg.norm(x - xr) / np.linalg.norm(xr):.3e} "
           f"y {np.linalg.norm(y - yr) / np.linalg.norm(yr):.3e}; ||x - c + A^T(y - d)||/||c|| {kkt:.3e}")
-    # float32 accuracy of the Gram over 4000-row splits (1.7e-7 measured; one
-    # accumulator for all six bf16 piece products gave 1.1e-6)
+    # float32 accuracy of the Gram over its row splits (9.7e-8 measured with
+    # 2900-row splits; one accumulator for all six bf16 piece products over
+    # 4000-row splits gave 1.1e-6)
     assert np.linalg.norm(x - xr) <= 5e-7 * np.linalg.norm(xr)
     assert np.linalg.norm(y - yr) <= 5e-7 * np.linalg.norm(yr)
 
