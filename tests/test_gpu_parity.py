@@ -256,6 +256,32 @@ def test_tall_gram_float32_accuracy(m, n):
     assert ex <= 1e-6 and ey <= 1e-6, (ex, ey)
 
 
+def test_direct_chunks_do_not_change_the_solve():
+    """A problem large enough (m n >= 16 Mi) that chunks are launched directly,
+    with one iteration of the next chunk queued behind each control read-back:
+    the stop test runs on the device, so the chunk length changes neither the
+    stopping iteration nor a bit of the result -- whether the solve stops in
+    the middle of a chunk or at its end (after which the queued iteration must
+    change nothing)."""
+    import torch
+    prob = W.lasso(8192, 2048, 33)
+    A = torch.from_numpy(prob.A).cuda()
+    res = {}
+    with P.Context(A) as ctx:
+        for chunk in (20, 6, 2):
+            prm = P.default_params(eps_abs=prob.eps_abs, eps_rel=prob.eps_rel, max_iter=prob.max_iter,
+                                   chunk_iters=chunk)
+            res[chunk] = ctx.solve(prob.f, prob.g, prm)
+    r20 = res[20]
+    assert r20.converged
+    for chunk in (6, 2):
+        r = res[chunk]
+        assert r.iters == r20.iters, (chunk, r.iters, r20.iters)
+        np.testing.assert_array_equal(r.x, r20.x)
+        np.testing.assert_array_equal(r.nu, r20.nu)
+        assert r.optval == r20.optval
+
+
 # ---------------------------------------------------------------------------
 # full-size workload (Lasso and NNLS on 20000 x 2000, float32)
 # ---------------------------------------------------------------------------
