@@ -165,14 +165,15 @@ __device__ void gram_tile_f32(const float *__restrict__ A, int m, int n, int ld,
 // sum into it, and over a 4000-row split that cost the 20000 x 2000
 // projection a factor of six in accuracy (1.1e-6 against the FP64 projection,
 // 1.7e-7 with two accumulators, 2.3e-7 with the float32-MFMA Gram; 9.7e-8 with
-// two accumulators and the 2900-row splits of two dispatch rounds).  sum_k A[k][i] A[k][j] over k in [k0, k1), tile (ti, tj);
-// k0 is a multiple of kG6KC; columns >= n and rows >= k1 read as zero.
+// two accumulators and the 2900-row splits of two dispatch rounds).
+// The tile is sum_k A[k][i] A[k][j] over k in [k0, k1), tile (ti, tj); k0 is
+// a multiple of kG6KC; columns >= n and rows >= k1 read as zero.
 // Stages of kG6KC rows: the loads of the stage after next go out before a
 // stage's MFMAs, and the next stage's pieces are stored into the other LDS
 // buffer after them (one barrier per stage).  512 threads (8 waves), each
 // wave a 32 x 64 part of the tile.  Ends with a barrier.
 constexpr int kG6KC = 16;  // k depth of one stage (one MFMA depth)
-// [operand][piece][column][k]: 24 KB.  A column's 16 k are two 16-byte
+// [operand][piece][column][k]: 24 KB per stage.  A column's 16 k are two 16-byte
 // halves, swapped in columns c with bit 3 of c set, so the 16 lanes of a
 // 16-byte access (16 consecutive columns, one half) hit 16 disjoint bank
 // groups.
