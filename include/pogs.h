@@ -48,7 +48,7 @@ extern "C" {
 #define POGS_EAGAIN       -4   /* batch: request can never fit the memory budget,
                                   or the queue is full */
 #define POGS_ENOTFOUND    -5   /* batch: unknown ticket */
-#define POGS_EUNSUPPORTED -6   /* valid request this build does not implement */
+#define POGS_EUNSUPPORTED -6   /* valid request the library does not implement */
 #define POGS_ETOOBIG      -7   /* input larger than the fixed device buffer of an
                                   allocation-free entry point */
 
@@ -330,7 +330,7 @@ int pogs_profile_iteration(pogs_ctx *ctx, int32_t reps, double *ms);
 typedef struct {
   int64_t m, n;
   const void *A;
-  pogs_dtype dt;        /* POGS_F32 only in this build */
+  pogs_dtype dt;        /* POGS_F32 only */
   pogs_order ord;
   int64_t lda;
   pogs_fn f, g;

@@ -37,7 +37,7 @@ const char *pogs_strerror(int code) {
     case POGS_EDEVICE: return "HIP runtime error";
     case POGS_EAGAIN: return "request does not fit the memory budget or the queue is full";
     case POGS_ENOTFOUND: return "unknown ticket";
-    case POGS_EUNSUPPORTED: return "not supported by this build";
+    case POGS_EUNSUPPORTED: return "not supported by the library";
     case POGS_ETOOBIG: return "input exceeds the fixed device buffer of an allocation-free entry point";
     default: return "unknown error";
   }
