@@ -24,7 +24,10 @@
  *     be freed by the caller as soon as the call returns (the library copies
  *     what it keeps).  Output buffers are caller-allocated.
  *   - "stream" arguments are a hipStream_t passed as void*; NULL means the
- *     library's own stream.  Calls are synchronous with respect to the host:
+ *     library's own stream (one per calling thread and device, created on
+ *     first use and kept until the process ends; non-blocking, so it is not
+ *     ordered after work on the legacy null stream).  Calls are synchronous
+ *     with respect to the host:
  *     they return after their device work has finished.
  *   - A context (pogs_ctx) is not thread-safe; use one per thread.  The batch
  *     engine (pogs_batch) is thread-safe.
