@@ -198,12 +198,18 @@ def path_block(P, probs):
     lambda on the same context; shared setup excluded from both legs."""
     recs = stored_oracle("lambda_path_8000x1000.json", probs)
     with P.Context(probs[0].A) as ctx:
-        # warm both legs at full size (device memory pool, captured graphs)
-        ctx.solve_path([p.f for p in probs], [p.g for p in probs])
+        # warm both legs at full size (device memory pool, captured graphs,
+        # the host pool that packs the functions: its second call is still
+        # slower), then the median of three path calls
+        for _ in range(2):
+            ctx.solve_path([p.f for p in probs], [p.g for p in probs])
         ctx.solve(probs[0].f, probs[0].g)
-        t = time.perf_counter()
-        res = ctx.solve_path([p.f for p in probs], [p.g for p in probs])
-        tpath = time.perf_counter() - t
+        tp = []
+        for _ in range(3):
+            t = time.perf_counter()
+            res = ctx.solve_path([p.f for p in probs], [p.g for p in probs])
+            tp.append(time.perf_counter() - t)
+        tpath = sorted(tp)[1]
         t = time.perf_counter()
         alone = [ctx.solve(p.f, p.g) for p in probs]
         tplain = time.perf_counter() - t
@@ -211,7 +217,7 @@ def path_block(P, probs):
     conv = sum(r.converged for r in res)
     return {"workload": f"{len(probs)} Lasso lambdas log-spaced over [1e-3, 1] lam_max, A 8000x1000 float32, "
                         "shared setup excluded from both legs", "setup_ms": setup_ms,
-            "solves_per_s": conv / tpath, "seconds": tpath, "converged": f"{conv}/{len(res)}",
+            "solves_per_s": conv / tpath, "seconds": tpath, "seconds_samples": tp, "converged": f"{conv}/{len(res)}",
             "iters_max": max(r.iters for r in res),
             "plain": {"seconds": tplain, "solves_per_s": sum(r.converged for r in alone) / tplain,
                       "iters_sum": sum(r.iters for r in alone)},

@@ -34,6 +34,12 @@ struct GramStage {            // 18.4 KB (row stride 144: the 16-lane row groups
   float b[kGramKC][kGramTB + 16];
 };
 
+constexpr int kGemmKC = 16;   // k depth of one stage of the general f32 tile product (32 measured the same)
+struct GemmStage {            // 18.4 KB (row stride 144, as GramStage)
+  float a[kGemmKC][kGramTB + 16];
+  float b[kGemmKC][kGramTB + 16];
+};
+
 // Tile pair t of a lower triangle (ti >= tj), row by row.
 __device__ inline void tri_index(int t, int *ti, int *tj) {
   int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -318,28 +324,30 @@ __device__ void gram_tile_bf16x6(const float *__restrict__ A, int n, int ld, int
 // columns >= N and k >= k1 read as zero; lda and ldb are multiples of 4 and
 // the rows of A and B are readable up to the next multiple of 16 elements
 // past M (A_T), k1 (not A_T) and N.  out(row, col, value) gets tile-local
-// indices.  128 x 128 tile, 4 waves in 2 x 2, f32 MFMA 16x16x4.
+// indices.  128 x 128 tile, kGemmKC-deep stages, 512 threads: 8 waves in 2 (rows) x 4 (columns),
+// each 64 x 32 as 4 x 2 f32 MFMA 16x16x4 blocks, so that every SIMD holds two
+// waves and one wave's LDS reads and stage wait run under the other's MFMAs.
 template <bool A_T, class Out>
 __device__ void gemm_tile_f32(const float *__restrict__ A, int lda, int M, const float *__restrict__ B, int ldb,
-                              int N, int i0, int j0, int k0, int k1, GramStage (&st)[2], Out out) {
-  constexpr int KC = 16;
+                              int N, int i0, int j0, int k0, int k1, GemmStage (&st)[2], Out out) {
+  constexpr int KC = kGemmKC, NH = KC / 16;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wi = w >> 1, wj = w & 1;
+  const int wi = w >> 2, wj = w & 3;
   typedef float f4 __attribute__((ext_vector_type(4)));
-  GramAcc acc[4][4];
+  GramAcc acc[4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = GramAcc{0.f, 0.f, 0.f, 0.f};
-  // stage k range [kk0, kk0 + 16) into registers (two float4 of A and of B
-  // per thread), then into an LDS buffer; as in gram_tile_f32, the next
-  // stage's loads are in flight while the MFMAs of the current one run
-  f4 ra[2], rb[2];
+    for (int j = 0; j < 2; ++j) acc[i][j] = GramAcc{0.f, 0.f, 0.f, 0.f};
+  // stage k range [kk0, kk0 + KC) into registers (KC / 16 float4 of A and
+  // of B per thread), then into an LDS buffer; the next stage's loads are in
+  // flight while the MFMAs of the current one run
+  f4 ra[NH], rb[NH];
   auto load = [&](int kk0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int f = t + h * 256;  // float4 index in a 16 x 128 stage
-      {  // B: rows kk0 + k, columns j0 + c .. c + 3
+    for (int h = 0; h < NH; ++h) {
+      const int f = t + h * 512;  // float4 index in a KC x 128 stage
+      {                           // B: rows kk0 + k, columns j0 + c .. c + 3
         const int k = f >> 5, c = (f & 31) * 4;
         const int row = kk0 + k, col = j0 + c;
         rb[h] = f4{0.f, 0.f, 0.f, 0.f};
@@ -357,10 +365,10 @@ __device__ void gemm_tile_f32(const float *__restrict__ A, int lda, int M, const
       }
     }
   };
-  auto store = [&](GramStage &sd, int kk0) {
+  auto store = [&](GemmStage &sd, int kk0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int f = t + h * 256;
+    for (int h = 0; h < NH; ++h) {
+      const int f = t + h * 512;
       {
         const int k = f >> 5, c = (f & 31) * 4;
         *reinterpret_cast<f4 *>(&sd.b[k][c]) = rb[h];
@@ -383,33 +391,33 @@ __device__ void gemm_tile_f32(const float *__restrict__ A, int lda, int M, const
   for (int kk0 = k0; kk0 < k1; kk0 += KC) {
     const bool more = kk0 + KC < k1;
     if (more) load(kk0 + KC);
-    const GramStage &sc = st[cur];
+    const GemmStage &sc = st[cur];
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
-      float av[4], bv[4];
+      float av[4], bv[2];
       const int kr = k4 + (lane >> 4), cl = lane & 15;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        av[b] = sc.a[kr][wi * 64 + b * 16 + cl];
-        bv[b] = sc.b[kr][wj * 64 + b * 16 + cl];
-      }
+      for (int b = 0; b < 4; ++b) av[b] = sc.a[kr][wi * 64 + b * 16 + cl];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = sc.b[kr][wj * 32 + b * 16 + cl];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     // the other buffer was last read before the previous barrier
     if (more) store(st[cur ^ 1], kk0 + KC);
     __syncthreads();
     cur ^= 1;
   }
+  // 16x16 result layout: lane l, element r -> row 4 (l / 16) + r, column l % 16
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        out(wi * 64 + i * 16 + 4 * (lane >> 4) + r, wj * 64 + j * 16 + (lane & 15), acc[i][j][r]);
+        out(wi * 64 + i * 16 + 4 * (lane >> 4) + r, wj * 32 + j * 16 + (lane & 15), acc[i][j][r]);
 }
 
 // One 64 (k) x 64 (index) chunk of op(k, x) = p[k * sk + x * sx], with

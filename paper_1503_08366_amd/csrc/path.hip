@@ -80,9 +80,9 @@ __global__ __launch_bounds__(256) void path_prox_kernel(PathArgs p) {
 // Split-K partial product of one 128 x 128 output tile:
 // part[split][i][j] = sum_{k in split} opA(i, k) B(k, j).
 template <bool A_T>
-__global__ __launch_bounds__(256) void path_gemm_kernel(const float *A, int lda, int M, const float *B, int ldb, int N,
+__global__ __launch_bounds__(512) void path_gemm_kernel(const float *A, int lda, int M, const float *B, int ldb, int N,
                                                         int K, int kchunk, float *part, const int *all_done) {
-  __shared__ GramStage st[2];
+  __shared__ GemmStage st[2];
   if (*all_done) return;
   const int i0 = blockIdx.x * kGramTB, j0 = blockIdx.y * kGramTB;
   const int k0 = blockIdx.z * kchunk, k1 = min(K, k0 + kchunk);
@@ -307,14 +307,14 @@ int gemm_splits(int M, int N, int K) {
 template <bool A_T>
 void gemm(const float *A, int lda, int M, const float *B, int ldb, int N, int K, float *part, int splits,
           const int *all_done, hipStream_t s) {
-  const int kchunk = (int)round_up(cdiv(K, splits), 16);
+  const int kchunk = (int)round_up(cdiv(K, splits), kGemmKC);
   const int sp = (int)cdiv(K, kchunk);
   dim3 grid(cdiv(M, kGramTB), cdiv(N, kGramTB), sp);
-  hipLaunchKernelGGL(path_gemm_kernel<A_T>, grid, dim3(256), 0, s, A, lda, M, B, ldb, N, K, kchunk, part, all_done);
+  hipLaunchKernelGGL(path_gemm_kernel<A_T>, grid, dim3(512), 0, s, A, lda, M, B, ldb, N, K, kchunk, part, all_done);
 }
 
 int actual_splits(int K, int splits) {
-  const int kchunk = (int)round_up(cdiv(K, splits), 16);
+  const int kchunk = (int)round_up(cdiv(K, splits), kGemmKC);
   return (int)cdiv(K, kchunk);
 }
 
