@@ -325,7 +325,9 @@ def serve_block(P, W, count, window, loads, qps=0.0):
     unit = [t for t, _ in stream]
     probs = [p for _, p in stream]
     say = lambda msg: print(msg, file=sys.stderr, flush=True)
-    _serve_leg(P, probs[:16], window=16)  # warm
+    # warm with one full leg: the device pool grows for every request size
+    # once (the batch leg is warmed the same way)
+    _serve_leg(P, probs, window=window)
     closed = _serve_leg(P, probs, window=window)
     say(f"serve closed loop: {closed}")
     t = time.perf_counter()

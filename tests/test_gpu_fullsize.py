@@ -13,10 +13,20 @@ variants that only large shapes select.
   stored FP64-oracle objective (tests/golden/, written by make_golden.py from
   the oracle only).
 * The 512-problem batch and the 64-point lambda path at full size against the
-  stored oracle objectives.
+  stored oracle objectives; on the path, the solutions x of three lambdas
+  against the oracle's and against the same problems solved alone, and the
+  critical lambda's x = 0 (Appendix A.4).
 
 Tolerances: objectives |p - p_oracle| <= 1e-3 max(|p_oracle|, 1); projection
 ||v - v*|| <= 1e-5 ||v*||; equilibration relative 1e-10; alone vs mix bitwise.
+Path solutions: ||x - x_ref|| <= 1e-4 ||x_ref|| when both runs take the same
+number of iterations: the ADMM map is nonexpansive, so the per-step
+difference of the float32 projection (within 5e-7 relative, pinned by the
+projection tests) adds up at most linearly over the <= 100 steps.  Runs that
+stop at different iterations: 1e-2, since each stops once its residuals are
+within eps_rel = 1e-3 (relative), which fixes x to about that accuracy, and
+ten times eps_rel leaves room for one iteration's difference.  Entries of
+x_ref above 1e-2 max|x_ref| keep their sign (the Lasso solution's support).
 """
 import json
 import os
@@ -176,3 +186,28 @@ def test_lambda_path_full_size_against_stored_oracle():
     print(f"lambda path 64: max rel objective error {errs.max():.2e}; converged {sum(r.converged for r in res)}/64")
     assert all(r.converged for r in res)
     assert errs.max() <= 1e-3, (int(errs.argmax()), errs.max())
+
+
+def test_lambda_path_full_size_solutions():
+    probs = W.lambda_path()
+    A = probs[0].A
+    pick = (0, 21, 42)
+    with P.Context(A) as ctx:
+        res = ctx.solve_path([p.f for p in probs], [p.g for p in probs])
+        alone = {r: ctx.solve(probs[r].f, probs[r].g) for r in pick}
+    A64 = A.astype(np.float64)
+    for r in pick:
+        ref = O.solve(A64, probs[r].f, probs[r].g, O.Params(eps_cmp=FLT_EPS))
+        x, xr, xa = res[r].x.astype(np.float64), ref.x, alone[r].x.astype(np.float64)
+        e_or = float(np.linalg.norm(x - xr) / np.linalg.norm(xr))
+        e_al = float(np.linalg.norm(x - xa) / np.linalg.norm(xa))
+        big = np.abs(xr) > 1e-2 * np.abs(xr).max()
+        print(f"lambda {r}: ||x - x_oracle||/||x_oracle|| {e_or:.2e}, vs alone {e_al:.2e}, "
+              f"support {int(big.sum())}, iters {res[r].iters}/{ref.iters}")
+        assert res[r].converged and res[r].iters <= 100
+        assert e_or <= (1e-4 if res[r].iters == ref.iters else 1e-2), (r, e_or)
+        assert e_al <= (1e-4 if res[r].iters == alone[r].iters else 1e-2), (r, e_al)
+        assert np.all(np.sign(x[big]) == np.sign(xr[big])), r
+    # the largest lambda is lambda_max: x* = 0 (Appendix A.4); at the stopping
+    # tolerance the iterate is small next to the smallest lambda's
+    assert float(np.abs(res[-1].x).max()) <= 1e-2 * float(np.abs(res[0].x).max())
