@@ -17,6 +17,14 @@ struct HostFn {
   std::vector<double> a, b, c, d, e;
 };
 
+// One entry of a separable function: a known h code, finite parameters,
+// c >= 0 and e >= 0 (convexity, Section 5), a != 0 where c > 0 (else the h
+// term would be constant).
+inline bool fn_entry_ok(uint8_t h, double a, double b, double c, double d, double e) {
+  return h < kNumH && finite(a) && finite(b) && finite(c) && finite(d) && finite(e) && c >= 0.0 && e >= 0.0 &&
+         !(c > 0.0 && a == 0.0);
+}
+
 // Validate a pogs_fn of length len in place (no copies): known h codes,
 // finite parameters, c >= 0 and e >= 0 (convexity), a != 0 where c > 0.
 inline int check_fn(const pogs_fn *fn, int64_t len) {
@@ -28,10 +36,7 @@ inline int check_fn(const pogs_fn *fn, int64_t len) {
     const double c = fn->c ? fn->c[k] : 1.0;
     const double d = fn->d ? fn->d[k] : 0.0;
     const double e = fn->e ? fn->e[k] : 0.0;
-    if (fn->h[k] >= kNumH) return POGS_EINVAL;
-    if (!finite(a) || !finite(b) || !finite(c) || !finite(d) || !finite(e)) return POGS_EINVAL;
-    if (c < 0.0 || e < 0.0) return POGS_EINVAL;   // convexity (Section 5: c, e >= 0)
-    if (c > 0.0 && a == 0.0) return POGS_EINVAL;  // h term would be constant
+    if (!fn_entry_ok(fn->h[k], a, b, c, d, e)) return POGS_EINVAL;
   }
   return POGS_OK;
 }
@@ -52,10 +57,7 @@ inline int expand_fn(const pogs_fn *fn, int64_t len, HostFn *out) {
     const double c = fn->c ? fn->c[k] : 1.0;
     const double d = fn->d ? fn->d[k] : 0.0;
     const double e = fn->e ? fn->e[k] : 0.0;
-    if (h >= kNumH) return POGS_EINVAL;
-    if (!finite(a) || !finite(b) || !finite(c) || !finite(d) || !finite(e)) return POGS_EINVAL;
-    if (c < 0.0 || e < 0.0) return POGS_EINVAL;   // convexity (Section 5: c, e >= 0)
-    if (c > 0.0 && a == 0.0) return POGS_EINVAL;  // h term would be constant
+    if (!fn_entry_ok(h, a, b, c, d, e)) return POGS_EINVAL;
     out->h[i] = h;
     out->a[i] = a;
     out->b[i] = b;
@@ -80,10 +82,7 @@ inline int stage_fn(const pogs_fn *fn, int64_t len, uint8_t *h, double *v) {
     const double c = fn->c ? fn->c[k] : 1.0;
     const double d = fn->d ? fn->d[k] : 0.0;
     const double e = fn->e ? fn->e[k] : 0.0;
-    if (hk >= kNumH) return POGS_EINVAL;
-    if (!finite(a) || !finite(b) || !finite(c) || !finite(d) || !finite(e)) return POGS_EINVAL;
-    if (c < 0.0 || e < 0.0) return POGS_EINVAL;   // convexity (Section 5: c, e >= 0)
-    if (c > 0.0 && a == 0.0) return POGS_EINVAL;  // h term would be constant
+    if (!fn_entry_ok(hk, a, b, c, d, e)) return POGS_EINVAL;
     h[i] = hk;
     va[i] = a;
     vb[i] = b;

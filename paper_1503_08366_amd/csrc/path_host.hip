@@ -4,8 +4,10 @@
 // state allocation, graph-captured iteration chunks, results.
 #include <chrono>
 #include <cstdio>
-#include <cstring>
+#include <atomic>
 #include <cmath>
+#include <cstring>
+#include <memory>
 #include <vector>
 
 #include "ctx.hpp"
@@ -22,30 +24,51 @@ double now_ms() {
 }
 
 // Per-problem functions packed as [len][Rp] (problem index fastest), float64
-// a, b, c, d, e planes followed by the h codes; element ranges on the host
-// pool's threads, writes contiguous over the problems.
-void pack_fns(const std::vector<HostFn> &fs, int len, int Rp, std::vector<double> *prm, std::vector<uint8_t> *h) {
+// a, b, c, d, e planes (prm) and the h codes (h), read straight from the
+// callers' descriptors (stride 0 or 1) and validated on the way with the
+// checks of expand_fn; columns r >= R are zero.  Element ranges run on the
+// host pool's threads, writes contiguous over the problems.
+int pack_fns(const pogs_fn *fs, int R, int len, int Rp, std::unique_ptr<double[]> *prm,
+             std::unique_ptr<uint8_t[]> *h) {
+  for (int r = 0; r < R; ++r)
+    if (fs[r].len != len || !fs[r].h || (fs[r].stride != 0 && fs[r].stride != 1)) return POGS_EINVAL;
   const size_t tot = (size_t)len * Rp;
-  prm->assign(5 * tot, 0.0);
-  h->assign(tot, 0);
-  const int R = (int)fs.size(), parts = len >= 4096 ? 16 : 1;
+  prm->reset(new (std::nothrow) double[5 * tot]);
+  h->reset(new (std::nothrow) uint8_t[tot]);
+  if (!*prm || !*h) return POGS_ENOMEM;
+  double *P = prm->get();
+  uint8_t *H = h->get();
+  std::atomic<int> bad{0};
+  const int parts = len >= 4096 ? 16 : 1;
   auto body = [&](int part) {
     const int i0 = (int)((int64_t)len * part / parts), i1 = (int)((int64_t)len * (part + 1) / parts);
+    bool ok = true;
     for (int i = i0; i < i1; ++i) {
       const size_t e0 = (size_t)i * Rp;
       for (int r = 0; r < R; ++r) {
-        const HostFn &F = fs[r];
-        (*prm)[e0 + r] = F.a[i];
-        (*prm)[tot + e0 + r] = F.b[i];
-        (*prm)[2 * tot + e0 + r] = F.c[i];
-        (*prm)[3 * tot + e0 + r] = F.d[i];
-        (*prm)[4 * tot + e0 + r] = F.e[i];
-        (*h)[e0 + r] = F.h[i];
+        const pogs_fn &F = fs[r];
+        const int64_t k = F.stride ? i : 0;
+        const uint8_t hc = F.h[k];
+        const double a = F.a ? F.a[k] : 1.0, b = F.b ? F.b[k] : 0.0, c = F.c ? F.c[k] : 1.0;
+        const double d = F.d ? F.d[k] : 0.0, e = F.e ? F.e[k] : 0.0;
+        ok = ok && fn_entry_ok(hc, a, b, c, d, e);
+        P[e0 + r] = a;
+        P[tot + e0 + r] = b;
+        P[2 * tot + e0 + r] = c;
+        P[3 * tot + e0 + r] = d;
+        P[4 * tot + e0 + r] = e;
+        H[e0 + r] = hc;
+      }
+      for (int r = R; r < Rp; ++r) {
+        for (int q = 0; q < 5; ++q) P[q * tot + e0 + r] = 0.0;
+        H[e0 + r] = 0;
       }
     }
+    if (!ok) bad.store(1, std::memory_order_relaxed);
   };
   if (parts > 1) host_pool().run(parts, body);
   else body(0);
+  return bad.load(std::memory_order_relaxed) ? POGS_EINVAL : POGS_OK;
 }
 
 }  // namespace
@@ -60,20 +83,15 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
     return POGS_EUNSUPPORTED;
   const double t0 = now_ms();
   const int m = (int)ctx->m, n = (int)ctx->n;
-  std::vector<HostFn> hf(R), hg(R);
   int rc;
-  for (int r = 0; r < R; ++r) {
-    if ((rc = expand_fn(&f[r], m, &hf[r]))) return rc;
-    if ((rc = expand_fn(&g[r], n, &hg[r]))) return rc;
+  for (int r = 0; r < R; ++r)
     if (out[r].mem != POGS_HOST && out[r].mem != POGS_DEVICE) return POGS_EINVAL;
-  }
   hipStream_t s = ctx->stream;
   const int Rp = (int)round_up(R, 64);
-  std::vector<double> fprm, gprm;
-  std::vector<uint8_t> fhh, ghh;
+  std::unique_ptr<double[]> fprm, gprm;
+  std::unique_ptr<uint8_t[]> fhh, ghh;
   const double t_expand = now_ms();
-  pack_fns(hf, m, Rp, &fprm, &fhh);
-  pack_fns(hg, n, Rp, &gprm, &ghh);
+  if ((rc = pack_fns(f, R, m, Rp, &fprm, &fhh)) || (rc = pack_fns(g, R, n, Rp, &gprm, &ghh))) return rc;
   const double t_pack = now_ms();
 
   PathArgs p{};
@@ -117,10 +135,10 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
       (rc = tmp.alloc((void **)&percol, (size_t)6 * Rp * 8)) || (rc = tmp.alloc((void **)&obj, (size_t)Rp * 8)) ||
       (rc = tmp.alloc((void **)&ints, (size_t)(5 * Rp + 64) * 4)))
     return rc;
-  POGS_HIP_TRY(hipMemcpyAsync(f0, fprm.data(), 5 * tf * 8, hipMemcpyHostToDevice, s));
-  POGS_HIP_TRY(hipMemcpyAsync(g0, gprm.data(), 5 * tg * 8, hipMemcpyHostToDevice, s));
-  POGS_HIP_TRY(hipMemcpyAsync(fh0, fhh.data(), tf, hipMemcpyHostToDevice, s));
-  POGS_HIP_TRY(hipMemcpyAsync(gh0, ghh.data(), tg, hipMemcpyHostToDevice, s));
+  POGS_HIP_TRY(hipMemcpyAsync(f0, fprm.get(), 5 * tf * 8, hipMemcpyHostToDevice, s));
+  POGS_HIP_TRY(hipMemcpyAsync(g0, gprm.get(), 5 * tg * 8, hipMemcpyHostToDevice, s));
+  POGS_HIP_TRY(hipMemcpyAsync(fh0, fhh.get(), tf, hipMemcpyHostToDevice, s));
+  POGS_HIP_TRY(hipMemcpyAsync(gh0, ghh.get(), tg, hipMemcpyHostToDevice, s));
   launch_path_scale_fn(f0, fh0, m, Rp, ctx->D, true, fh, fs, fs + tf, fs + 2 * tf, fs + 3 * tf, fs + 4 * tf, s);
   launch_path_scale_fn(g0, gh0, n, Rp, ctx->E, false, gh, gs, gs + tg, gs + 2 * tg, gs + 3 * tg, gs + 4 * tg, s);
   p.fh = fh;
@@ -248,7 +266,7 @@ extern "C" int pogs_solve_path(pogs_ctx *ctx, int32_t R, const pogs_fn *f, const
   const double ms = now_ms() - t0;
   if (prm.verbose)
     fprintf(stderr,
-            "pogs path: %d problems: expand %.1f ms, pack %.1f ms, upload and scale %.1f ms, capture %.1f ms, "
+            "pogs path: %d problems: checks %.1f ms, pack %.1f ms, upload and scale %.1f ms, capture %.1f ms, "
             "iterations %.1f ms, graph destroy %.1f ms, results %.1f ms\n",
             R, t_expand - t0, t_pack - t_expand, t_upload - t_pack, t_capture - t_upload, t_iter - t_capture,
             t_destroy - t_iter, now_ms() - t_destroy);
