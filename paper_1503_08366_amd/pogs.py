@@ -192,9 +192,50 @@ class _FnHolder:
 
 _DEFAULTS = {"a": 1.0, "b": 0.0, "c": 1.0, "d": 0.0, "e": 0.0}
 
+# pogs_fn as a numpy record, for calls that take many descriptors at once
+_FN_RECORD = np.dtype([("len", np.int64), ("stride", np.int64), ("h", np.uintp), ("a", np.uintp),
+                       ("b", np.uintp), ("c", np.uintp), ("d", np.uintp), ("e", np.uintp)])
+assert _FN_RECORD.itemsize == C.sizeof(pogs_fn)
+
+
+class _FnTable:
+    """Descriptors of functions of one length as one record array laid out as
+    an array of pogs_fn (stride 1; NULL for default parameters), with the
+    arrays behind them kept alive for the duration of a call.  Functions with
+    the same single base function share one array of codes."""
+
+    def __init__(self, fns, length: int):
+        R = len(fns)
+        cols = {k: [0] * R for k in "habcde"}
+        self.keep, codes = [], {}
+        for i, fn in enumerate(fns):
+            if fn.size != length:
+                raise ValueError(f"function has length {fn.size}, expected {length}")
+            if isinstance(fn.h, str):
+                h = codes.get(fn.h)
+                if h is None:
+                    h = codes[fn.h] = np.full(length, H_CODES[fn.h], dtype=np.uint8)
+            else:
+                h = np.array([H_CODES[n] for n in fn.h], dtype=np.uint8)
+            self.keep.append(h)
+            cols["h"][i] = h.ctypes.data
+            for k in "abcde":
+                if not _is_default(fn, k):
+                    arr = np.ascontiguousarray(fn.field(k), dtype=np.float64)
+                    self.keep.append(arr)
+                    cols[k][i] = arr.ctypes.data
+        self.t = np.zeros(R, dtype=_FN_RECORD)
+        self.t["len"] = length
+        self.t["stride"] = 1
+        for k, v in cols.items():
+            self.t[k] = v
+        self.ptr = self.t.ctypes.data_as(C.POINTER(pogs_fn))
+
 
 def _is_default(fn, k: str) -> bool:
     v = getattr(fn, k, None)
+    if isinstance(v, (float, int, np.generic)):  # the common case, without np.ndim
+        return float(v) == _DEFAULTS[k]
     return v is not None and np.ndim(v) == 0 and float(v) == _DEFAULTS[k]
 
 
@@ -403,21 +444,23 @@ class Context:
 
     def solve_path(self, fs: Sequence, gs: Sequence, params: Optional[pogs_params] = None) -> List[Result]:
         R = len(fs)
-        fh = [_FnHolder(f, self.m) for f in fs]
-        gh = [_FnHolder(g, self.n) for g in gs]
-        farr = (pogs_fn * R)(*(h.s for h in fh))
-        garr = (pogs_fn * R)(*(h.s for h in gh))
+        if len(gs) != R:
+            raise ValueError(f"{R} functions f but {len(gs)} functions g")
+        ft, gt = _FnTable(fs, self.m), _FnTable(gs, self.n)
         res = (pogs_result * R)()
-        npdt = _np_dtype(self.dtype)
-        outs = []
+        m, n = self.m, self.n
+        # x, y, mu, nu of every problem in one host block, a row per problem
+        blk = np.empty((R, 2 * (m + n)), dtype=_np_dtype(self.dtype))
+        base, row, size = blk.ctypes.data, blk.strides[0], blk.itemsize
+        offs = (0, n * size, (n + m) * size, (2 * n + m) * size)
         for r in range(R):
-            o = [np.empty(k, dtype=npdt) for k in (self.n, self.m, self.n, self.m)]
-            res[r].x, res[r].y, res[r].mu, res[r].nu = (a.ctypes.data for a in o)
+            a = base + r * row
+            res[r].x, res[r].y, res[r].mu, res[r].nu = (a + o for o in offs)
             res[r].mem = POGS_HOST
-            outs.append(o)
-        rc = _lib().pogs_solve_path(self._h(), R, farr, garr, C.byref(params) if params is not None else None, res)
+        rc = _lib().pogs_solve_path(self._h(), R, ft.ptr, gt.ptr, C.byref(params) if params is not None else None, res)
         _check(rc, "pogs_solve_path")
-        return [Result(res[r], *outs[r]) for r in range(R)]
+        return [Result(res[r], blk[r, :n], blk[r, n:n + m], blk[r, n + m:2 * n + m], blk[r, 2 * n + m:])
+                for r in range(R)]
 
     def solve_continuation(self, fs: Sequence, gs: Sequence, params: Optional[pogs_params] = None) -> List[Result]:
         """Solve a sequence of problems on this matrix (e.g. a lambda path),
