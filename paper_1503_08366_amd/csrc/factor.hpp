@@ -1,10 +1,14 @@
-// Workgroup-level building blocks of the setup (256 threads = 4 waves):
-//   * Gram tiles on f32 MFMA (128 x 128 output tile, 4 waves in 2 x 2),
-//   * float64 64 x 64 block products on f64 MFMA,
+// Workgroup-level building blocks of the setup and of the lambda path:
+//   * Gram tiles on f32 MFMA (128 x 128 output tile, 256 threads: 4 waves in
+//     2 x 2) and on bf16 MFMA at float32 accuracy (the six products of a
+//     three-way bf16 split, 512 threads: 8 waves in 4 x 2),
+//   * the general f32 MFMA tile product of the lambda path (128 x 128, 512
+//     threads: 8 waves in 2 x 4),
+//   * float64 64 x 64 block products on f64 MFMA (256 threads),
 //   * the diagonal-block Cholesky / triangular inverse, panel solve, trailing
 //     update, blocked inverse steps and the K^{-1} = L^{-T} L^{-1} product.
-// The multi-workgroup setup launches one workgroup per tile; the batched
-// solver calls the same functions in loops inside one workgroup per problem.
+// The single-problem setup launches one workgroup per tile; the grouped
+// (batched) launches run the same functions over the tiles of every problem.
 #pragma once
 
 #include <type_traits>
